@@ -1,0 +1,73 @@
+"""The oracle's pins must catch plausible mistakes. Each case plants one slip in
+a copy of the oracle's C source (on the CPU), builds it, swaps it in, and checks
+that at least one pin fails."""
+import ctypes as C
+import os
+import subprocess
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "cpapr_oracle.c")
+
+# (name, original text, planted mistake, pins expected to notice)
+MUTATIONS = [
+    ("no-eps-clamp", "vals[k] / (mk > eps ? mk : eps)", "vals[k] / mk",
+     ["test_phi_clamp_matches_dense", "test_phi_empty_rows_and_clamped_contribution"]),
+    ("pi-drops-last-mode", "if (m == mode) continue;\n            const double* row = A[m] + (int64_t)idx[(int64_t)m * nnz + k] * R;\n            for (int r = 0; r < R; ++r) pi[r] *= row[r];",
+     "if (m == mode || m == nmodes - 1) continue;\n            const double* row = A[m] + (int64_t)idx[(int64_t)m * nnz + k] * R;\n            for (int r = 0; r < R; ++r) pi[r] *= row[r];",
+     ["test_phi_matches_dense_bruteforce", "test_phi_mass_identity"]),
+    ("dot-wrong-row", "mk += B[i * R + r] * pi[r];", "mk += B[r] * pi[r];",
+     ["test_phi_matches_dense_bruteforce", "test_phi_golden_hand_example"]),
+    ("scatter-no-pi", "neumaier_add(&Phi[i * R + r], &comp[i * R + r], s * pi[r]);",
+     "neumaier_add(&Phi[i * R + r], &comp[i * R + r], s);",
+     ["test_phi_matches_dense_bruteforce", "test_phi_rank_one_closed_form"]),
+    ("kkt-sign", "q = 1.0 - Phi[i * R + r];", "q = Phi[i * R + r] - 1.0;",
+     ["test_mu_inner_kkt_break"]),
+    ("mu-update-divides", "B[i * R + r] *= Phi_last[i * R + r];", "B[i * R + r] /= Phi_last[i * R + r];",
+     ["test_mu_inner_n2_is_lee_seung_kl_nmf", "test_mu_inner_monotone_nonnegative_and_mass"]),
+    ("shift-any-phi", "phi_prev[n][e] > 1.0", "phi_prev[n][e] >= 0.0",
+     ["test_solve_inadmissible_zero_shift"]),
+    ("shift-ignores-A", "if (An[e] < kappa_tol && phi_prev[n][e] > 1.0)", "if (phi_prev[n][e] > 1.0)",
+     ["test_solve_inadmissible_zero_shift"]),
+    ("lambda-not-updated", "lam[r] = s + c;", "(void)s; (void)c;",
+     ["test_solve_rank_one_closed_form", "test_solve_mass_and_normalisation"]),
+    ("loglik-drops-mass", "*out = (s + c) - mass;", "*out = (s + c);",
+     ["test_loglik_matches_dense"]),
+    ("mttkrp-no-value", "neumaier_add(&M[i * R + r], &comp[i * R + r], vals[k] * t[r]);",
+     "neumaier_add(&M[i * R + r], &comp[i * R + r], t[r]);", ["test_mttkrp_matches_dense"]),
+]
+
+PARAMS = {
+    "test_phi_matches_dense_bruteforce": [((5, 4, 3), 3), ((3, 4, 2, 3), 2)],
+    "test_mttkrp_matches_dense": [((5, 4, 3),)],
+}
+
+
+def _run_pin(name):
+    fn = getattr(pins, name)
+    cases = PARAMS.get(name, [()])
+    for args in cases:
+        fn(oracle, *args)
+
+
+@pytest.mark.parametrize("name,orig,bad,catchers", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(tmp_path, monkeypatch, name, orig, bad, catchers):
+    src = open(SRC).read()
+    assert src.count(orig) >= 1, f"mutation anchor for {name} not found"
+    mutated = src.replace(orig, bad, 1)
+    cfile = tmp_path / "mut.c"
+    cfile.write_text(mutated)
+    so = tmp_path / "libmut.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+                           "-o", str(so), str(cfile), "-lm"])
+    monkeypatch.setattr(oracle, "_lib", C.CDLL(str(so)))
+    caught = []
+    for pin in catchers:
+        try:
+            _run_pin(pin)
+        except (AssertionError, RuntimeError, FloatingPointError, ValueError):
+            caught.append(pin)
+    assert caught, f"no pin noticed the planted mistake {name}"
