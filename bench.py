@@ -1,0 +1,171 @@
+"""Benchmark: CP-APR MU on one MI355X, Phi(n) nonzeros per second.
+
+One step = one whole CP-APR MU job on the 3-way 200,000 x 150,000 x 20,000
+tensor with 20M Zipf(1.1) nonzeros (duplicates kept), counts 1+Poisson(3),
+rank 16: plan creation (per-mode device sort), the fixed 5 outer x 10 inner
+schedule over all three modes (Phi, KKT, MU update, normalisation), and the
+log-likelihood of the result. Inputs are resident in HBM before timing.
+
+value = Phi nonzero visits per second over the whole step
+        (outer x modes x inner x nnz / step time).
+roofline: the Phi kernel, timed by HIP events on its own stream inside the
+        timed steps, against HBM peak, with its algorithmic bytes per launch
+        (per nonzero: coordinates, value, the other modes' factor rows; per
+        nonempty row: the B row read and the Phi row write).
+cpu_baseline: the FP64 CPU oracle on one core, Phi over every mode once.
+
+Prints one JSON line. Only one GPU is supported.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phi_traffic.json")
+
+
+def phi_kernel_bytes(N, R, nnz, segments, word=8):
+    """Algorithmic bytes of one Phi launch on the mode-sorted copy."""
+    per_nnz = 4 * N + 8 + (N - 1) * R * word
+    return nnz * per_nnz + segments * 2 * R * word
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("phi.hip", "internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2307_03276_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per Phi launch from committed rocprofv3 counter runs, or None
+    if they were taken on another kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(f"{workload}/{precision}")
+    if not e or e.get("kernel_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(X, M):
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    for n in range(X.nmodes):
+        oracle.phi(X, n, M.factors[n] * M.lam, M.factors)
+    dt = time.perf_counter() - t0
+    return {"value": X.nmodes * X.nnz / dt, "unit": "nonzeros/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle Phi(n) once per mode (3 x {X.nnz} nonzeros), single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--nnz", type=int, default=20_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2307_03276_amd import cpapr, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    X, M, sched = synth.config_zipf3(nnz=args.nnz)
+    N, R = X.nmodes, M.rank
+    prec = cpapr.CPAPR_MIXED if args.precision == "mixed" else cpapr.CPAPR_FP64
+    params = cpapr.cpapr_params_default(kmax=sched["kmax"], lmax=sched["lmax"], tol=sched["tau"],
+                                        eps=sched["eps"], precision=prec)
+    dev = torch.device("cuda")
+    idx = torch.from_numpy(X.idx).to(dev)
+    vals = torch.from_numpy(X.vals).to(dev)
+    lam0 = torch.from_numpy(M.lam).to(dev)
+    A0 = [torch.from_numpy(a).to(dev) for a in M.factors]
+    lam = lam0.clone()
+    A = [a.clone() for a in A0]
+    coo = cpapr.make_coo(X.dims, idx, vals)
+    ws = torch.empty(cpapr.cpapr_plan_workspace_size(coo, R, params), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        h = cpapr.cpapr_plan_create(coo, R, params, ws, stream)
+        lam.copy_(lam0)
+        for a, a0 in zip(A, A0):
+            a.copy_(a0)
+        st = cpapr.cpapr_solve(h, lam, A, stream)
+        segs = [cpapr.cpapr_plan_segments(h, n) for n in range(N)]
+        cpapr.cpapr_plan_destroy(h)
+        return st, segs
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    launches_per_step = sched["kmax"] * N * sched["lmax"]
+    cpapr.cpapr_prof_enable(launches_per_step * args.steps + 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, segs = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    recs = cpapr.cpapr_prof_read(launches_per_step * args.steps + 16)
+    cpapr.cpapr_prof_disable()
+
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    visits = launches_per_step * X.nnz
+    value = visits / (ms_per_step / 1000.0)
+    word = 4 if prec == cpapr.CPAPR_MIXED else 8
+    tot_bytes = sum(phi_kernel_bytes(N, R, X.nnz, segs[m], word) for m, _ in recs)
+    tot_ms = sum(ms for _, ms in recs)
+    achieved = tot_bytes / (tot_ms / 1000.0) / 1e9
+    avg_ms = tot_ms / max(1, len(recs))
+    traffic = measured_traffic("zipf3-20M-R16", args.precision)
+    out = {
+        "metric": "Phi^(n) nonzeros/s",
+        "value": value,
+        "unit": "nonzeros/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == cpapr.CPAPR_FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "cpapr-mu 3-way 200000x150000x20000, 20M Zipf(1.1) nnz, R=16, 5 outer x 10 inner, "
+                               "plan + solve + loglik per step",
+                   "nnz": X.nnz, "rank": R, "outer": sched["kmax"], "inner": sched["lmax"],
+                   "precision": args.precision},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "phi_kernel": {"launches": len(recs), "avg_ms": avg_ms, "nnz_per_s": X.nnz / (avg_ms / 1000.0),
+                       "bytes_per_launch_model": tot_bytes / max(1, len(recs)),
+                       "segments": segs, "share_of_step": tot_ms / (ms_per_step * args.steps)},
+        "solve": {"outer": st["outer_iters"], "inner_updates": st["inner_iters"],
+                  "kkt": st["kkt_violation"], "loglik": st["loglik"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(X, M)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/*
+ * cpapr.h - C ABI of the MI355X (gfx950) CP-APR MU library.
+ *
+ * CP-APR with multiplicative updates fits a nonnegative rank-R Kruskal model
+ * M = [lambda; A(1) .. A(N)] to a sparse count tensor X (Algorithm 1 of
+ * Anderson, Teranishi, Dunlavy, Choi, "Analyzing the Performance Portability
+ * of Tensor Decomposition", arXiv:2307.03276). Its hot path is
+ *
+ *     Phi(n) = (X_(n) ./ max(B Pi, eps)) Pi^T                  (Algorithm 2)
+ *
+ * computed one nonzero at a time (Section 3.1): pi_k[r] = prod_{m != n}
+ * A(m)[i_m(k), r]; m_k = B[i_n(k), :] . pi_k; s_k = x_k / max(m_k, eps);
+ * Phi[i_n(k), :] += s_k * pi_k. Phi feeds the MU step B <- B .* Phi, the
+ * inner loop and the KKT test on min(B, 1 - Phi).
+ *
+ * Conventions (every entry point):
+ *   - Layout: matrices are row-major I x R doubles (a row is R contiguous
+ *     words). Coordinates are 0-based int32; idx[m * nnz + k] is nonzero k's
+ *     mode-m coordinate.
+ *   - Memory: pointers documented "device" are HIP device memory on the
+ *     current device; "host" pointers are ordinary host memory. The caller
+ *     owns every buffer. The library never allocates device memory: a plan
+ *     lives in a caller-provided workspace sized by
+ *     cpapr_plan_workspace_size().
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream). cpapr_phi is stream-ordered and returns without waiting.
+ *     Functions that fill host results (plan creation, mu_inner, solve,
+ *     loglik) wait for the stream before returning.
+ *   - Errors: 0 on success, a negative CPAPR_E* code otherwise, with a
+ *     message from cpapr_last_error() (thread-local). No C++ exception
+ *     crosses this boundary. Non-convergence is not an error.
+ *   - Limits: 2 <= N <= CPAPR_MAX_MODES, 1 <= R <= CPAPR_MAX_RANK,
+ *     0 <= nnz < 2^31, 1 <= I_n < 2^31.
+ */
+#ifndef CPAPR_H
+#define CPAPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CPAPR_MAX_MODES 8
+#define CPAPR_MAX_RANK 256
+#define CPAPR_MAX_LMAX 4096
+
+enum {
+    CPAPR_OK = 0,
+    CPAPR_EINVAL = -1,      /* bad argument (null pointer, size, mode, rank) */
+    CPAPR_EINDEX = -2,      /* a coordinate lies outside [0, I_m) */
+    CPAPR_EVALUE = -3,      /* a tensor value is not finite and > 0 */
+    CPAPR_EWORKSPACE = -4,  /* workspace missing, misaligned or too small */
+    CPAPR_EHIP = -5,        /* a HIP runtime call failed */
+    CPAPR_EUNSUPPORTED = -6 /* size outside the documented limits */
+};
+
+enum { CPAPR_FP64 = 0, CPAPR_MIXED = 1 };
+
+/* Phi kernel variants. SEGMENTED: mode-sorted nonzeros, in-register and
+ * in-workgroup segmented reduction, atomics only for rows that cross a tile
+ * boundary. ATOMIC: the per-nonzero atomic scatter of the paper's GPU kernel
+ * (Algorithm 3), kept for comparison. AUTO picks SEGMENTED. */
+enum { CPAPR_VARIANT_AUTO = 0, CPAPR_VARIANT_SEGMENTED = 1, CPAPR_VARIANT_ATOMIC = 2 };
+
+/* Sparse count tensor in coordinate format (the paper's I[n][j], X[j]). */
+typedef struct cpapr_coo {
+    int32_t nmodes;      /* N */
+    const int64_t* dims; /* host [N]: I_1..I_N */
+    int64_t nnz;         /* number of stored entries; duplicates are allowed */
+    const int32_t* idx;  /* device [N * nnz], 0-based */
+    const double* vals;  /* device [nnz], finite and > 0 */
+} cpapr_coo;
+
+/* Algorithm parameters. */
+typedef struct cpapr_params {
+    int32_t kmax;      /* outer iterations (Algorithm 1), >= 1 */
+    int32_t lmax;      /* inner iterations per mode, 1..CPAPR_MAX_LMAX */
+    double tol;        /* KKT tolerance tau; <= 0: fixed kmax x lmax schedule */
+    double eps;        /* divisor floor of Algorithm 2 (1e-10) */
+    double kappa;      /* inadmissible-zero shift (0.01) */
+    double kappa_tol;  /* entries below this count as zero (1e-10) */
+    int32_t precision; /* CPAPR_FP64 or CPAPR_MIXED */
+    int32_t variant;   /* CPAPR_VARIANT_* */
+    int32_t group;     /* lanes per nonzero (0 = by rank; else 4, 8, 16, 32 or 64) */
+    int32_t chunk;     /* nonzeros per lane group per tile (0 = default) */
+} cpapr_params;
+
+/* Result summary of cpapr_mu_inner / cpapr_solve (host). */
+typedef struct cpapr_stats {
+    int32_t outer_iters;  /* outer iterations run */
+    int32_t converged;    /* 1 if an outer sweep made no update (tol > 0) */
+    int64_t inner_iters;  /* MU updates performed, summed over modes */
+    double kkt_violation; /* largest last-seen max|min(B, 1-Phi)| over modes of the final sweep */
+    double loglik;        /* Poisson log-likelihood of the result (solve only) */
+} cpapr_stats;
+
+typedef struct cpapr_plan cpapr_plan;
+
+/* Fill *p with the defaults: kmax 10, lmax 10, tol 1e-4, eps 1e-10,
+ * kappa 0.01, kappa_tol 1e-10, FP64, AUTO, group 0, chunk 0. */
+void cpapr_params_default(cpapr_params* p);
+
+/* Bytes of device workspace a plan for X at rank R and parameters p needs
+ * (written to *bytes). X->idx and X->vals may be NULL here. */
+int cpapr_plan_workspace_size(const cpapr_coo* X, int32_t R, const cpapr_params* p, size_t* bytes);
+
+/* Build a plan: checks every coordinate and value on the device, then sorts
+ * the nonzeros by each mode's coordinate into N stable, physically permuted
+ * copies kept in the workspace (the paper's sort-by-mode strategy: sorting
+ * once per mode at the start, Section 3.1). ws (device, 256-byte aligned,
+ * ws_bytes >= cpapr_plan_workspace_size) must outlive the plan; X's buffers
+ * may be freed once this returns. Waits for `stream`. *out receives the plan. */
+int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void* ws,
+                      size_t ws_bytes, void* stream, cpapr_plan** out);
+int cpapr_plan_destroy(cpapr_plan* plan);
+
+/* Number of nonempty rows (segments) of mode `mode` (host query). */
+int64_t cpapr_plan_segments(const cpapr_plan* plan, int32_t mode);
+
+/* Phi(n) (Algorithm 2) for mode `mode` of the plan's tensor.
+ *   B   device [I_n x R], nonnegative.
+ *   A   host array of N device pointers to A(m) [I_m x R]; A[mode] is unused.
+ *   eps divisor floor, > 0.
+ *   Phi device [I_n x R], overwritten (rows without nonzeros become 0).
+ * In CPAPR_MIXED the other factors are first rounded to FP32 copies in the
+ * workspace; products and sums run in FP32 with compensation, Phi is FP64.
+ * Stream-ordered; does not wait. */
+int cpapr_phi(cpapr_plan* plan, int32_t mode, const double* B, const double* const* A, double eps,
+              double* Phi, void* stream);
+
+/* MU inner loop of Algorithm 1 for one mode, params lmax / tol / eps of the plan:
+ * for l < lmax: Phi = phi(B); viol = max|min(B, 1 - Phi)|; stop if tol > 0 and
+ * viol < tol; else B <- B .* Phi.
+ *   B        device [I_n x R], in/out.
+ *   A        host array of N device pointers (A[mode] unused).
+ *   Phi_last device [I_n x R], out: the last Phi computed.
+ *   out      host, may be NULL: inner_iters = updates made, kkt_violation =
+ *            last violation, outer_iters = 0.
+ * The loop's stop decision stays on the device; waits for the stream once. */
+int cpapr_mu_inner(cpapr_plan* plan, int32_t mode, double* B, const double* const* A,
+                   double* Phi_last, cpapr_stats* out, void* stream);
+
+/* Full CP-APR MU (Algorithm 1) with the plan's parameters.
+ *   lambda device [R], in/out.  A host array of N device pointers, in/out.
+ * From the second outer iteration on, entries with A(n)[i,r] < kappa_tol whose
+ * previous Phi(n)[i,r] > 1 are raised by kappa before B = (A(n)+S) diag(lambda)
+ * is formed; after the inner loop lambda = column sums of B and A(n) = B
+ * diag(lambda)^-1 (zero columns stay zero). With tol > 0 the solve stops after
+ * an outer sweep with no update. out (host, may be NULL) receives the stats,
+ * including the log-likelihood of the result. Waits for the stream at most
+ * once per outer iteration (tol > 0) or once at the end (tol <= 0). */
+int cpapr_solve(cpapr_plan* plan, double* lambda, double* const* A, cpapr_stats* out, void* stream);
+
+/* Poisson log-likelihood sum_k x_k log(max(m_k, eps)) - sum_r lambda_r
+ * prod_m sum_i A(m)[i,r], with m_k the model value at nonzero k (the constant
+ * -sum log x_k! is omitted). lambda device [R]; A host array of N device
+ * pointers; *out host. Waits for the stream. */
+int cpapr_loglik(cpapr_plan* plan, const double* lambda, const double* const* A, double eps,
+                 double* out, void* stream);
+
+/* MTTKRP for CP-ALS (the paper's Eqs. 10-12): M[i_n, :] = sum over nonzeros in
+ * row i_n of x_k * prod_{m != n} A(m)[i_m, :]. Same sorted engine as Phi
+ * without the divide. M device [I_n x R], overwritten. Stream-ordered. */
+int cpapr_mttkrp(cpapr_plan* plan, int32_t mode, const double* const* A, double* M, void* stream);
+
+/* Kernel timing for measurement: while enabled, every Phi kernel launch is
+ * bracketed by HIP events on its stream (up to `capacity` launches).
+ * cpapr_prof_read waits for the recorded events and writes, per launch, the
+ * mode and the kernel's duration in milliseconds; returns the number of
+ * launches written (<= cap) or a negative error. Not thread-safe. */
+int cpapr_prof_enable(int32_t capacity);
+int cpapr_prof_disable(void);
+int cpapr_prof_read(int32_t* modes, float* ms, int32_t cap);
+
+const char* cpapr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPAPR_H */

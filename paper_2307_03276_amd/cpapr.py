@@ -1,0 +1,274 @@
+"""Python binding of libcpapr (include/cpapr.h): ctypes marshalling only.
+
+Functions carry the C names (``cpapr_phi``, ``cpapr_mu_inner``, ``cpapr_solve``,
+...). Device buffers are ``torch.Tensor`` on the GPU (their ``data_ptr`` is
+passed); PyTorch supplies device memory and the current stream, every step of
+the computation runs in the library's HIP kernels. There is no CPU fallback:
+if the library is not built, or no GPU is present, calls raise.
+
+:class:`Plan` owns a plan and its workspace tensor and offers the same calls
+as methods.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcpapr.so")
+
+CPAPR_FP64 = 0
+CPAPR_MIXED = 1
+CPAPR_VARIANT_AUTO = 0
+CPAPR_VARIANT_SEGMENTED = 1
+CPAPR_VARIANT_ATOMIC = 2
+MAX_MODES = 8
+
+
+class CpaprError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"cpapr error {code}: {msg}")
+        self.code = code
+
+
+class cpapr_coo(C.Structure):
+    _fields_ = [("nmodes", C.c_int32), ("dims", C.POINTER(C.c_int64)), ("nnz", C.c_int64),
+                ("idx", C.c_void_p), ("vals", C.c_void_p)]
+
+
+class cpapr_params(C.Structure):
+    _fields_ = [("kmax", C.c_int32), ("lmax", C.c_int32), ("tol", C.c_double), ("eps", C.c_double),
+                ("kappa", C.c_double), ("kappa_tol", C.c_double), ("precision", C.c_int32),
+                ("variant", C.c_int32), ("group", C.c_int32), ("chunk", C.c_int32)]
+
+
+class cpapr_stats(C.Structure):
+    _fields_ = [("outer_iters", C.c_int32), ("converged", C.c_int32), ("inner_iters", C.c_int64),
+                ("kkt_violation", C.c_double), ("loglik", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libcpapr.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2307_03276_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER
+    sig = {
+        "cpapr_params_default": (None, [P(cpapr_params)]),
+        "cpapr_plan_workspace_size": (C.c_int, [P(cpapr_coo), i32, P(cpapr_params), P(C.c_size_t)]),
+        "cpapr_plan_create": (C.c_int, [P(cpapr_coo), i32, P(cpapr_params), vp, C.c_size_t, vp, P(vp)]),
+        "cpapr_plan_destroy": (C.c_int, [vp]),
+        "cpapr_plan_segments": (i64, [vp, i32]),
+        "cpapr_phi": (C.c_int, [vp, i32, vp, P(vp), dbl, vp, vp]),
+        "cpapr_mu_inner": (C.c_int, [vp, i32, vp, P(vp), vp, P(cpapr_stats), vp]),
+        "cpapr_solve": (C.c_int, [vp, vp, P(vp), P(cpapr_stats), vp]),
+        "cpapr_loglik": (C.c_int, [vp, vp, P(vp), dbl, P(dbl), vp]),
+        "cpapr_mttkrp": (C.c_int, [vp, i32, P(vp), vp, vp]),
+        "cpapr_prof_enable": (C.c_int, [i32]),
+        "cpapr_prof_disable": (C.c_int, []),
+        "cpapr_prof_read": (C.c_int, [P(i32), P(C.c_float), i32]),
+        "cpapr_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+EXPORTED = ("cpapr_params_default", "cpapr_plan_workspace_size", "cpapr_plan_create", "cpapr_plan_destroy",
+            "cpapr_plan_segments", "cpapr_phi", "cpapr_mu_inner", "cpapr_solve", "cpapr_loglik",
+            "cpapr_mttkrp", "cpapr_prof_enable", "cpapr_prof_disable", "cpapr_prof_read",
+            "cpapr_last_error")
+
+
+def _check(rc: int):
+    if rc < 0:
+        raise CpaprError(rc, load().cpapr_last_error().decode())
+    return rc
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr_array(tensors: Sequence) -> C.Array:
+    arr = (C.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+def _need_cuda(t, name, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA/HIP tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}")
+
+
+def cpapr_params_default(**overrides) -> cpapr_params:
+    p = cpapr_params()
+    load().cpapr_params_default(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def make_coo(dims: Sequence[int], idx, vals):
+    """COO descriptor for device tensors idx (int32 [N, nnz]) and vals (float64 [nnz])."""
+    import torch
+    _need_cuda(idx, "idx", torch.int32)
+    _need_cuda(vals, "vals", torch.float64)
+    d = (C.c_int64 * len(dims))(*[int(x) for x in dims])
+    coo = cpapr_coo(len(dims), C.cast(d, C.POINTER(C.c_int64)), int(vals.shape[0]), idx.data_ptr(),
+                    vals.data_ptr())
+    coo._keep = (d, idx, vals)
+    return coo
+
+
+def cpapr_plan_workspace_size(coo: cpapr_coo, R: int, params: cpapr_params) -> int:
+    n = C.c_size_t(0)
+    _check(load().cpapr_plan_workspace_size(C.byref(coo), R, C.byref(params), C.byref(n)))
+    return n.value
+
+
+def cpapr_plan_create(coo, R, params, ws, stream=None):
+    h = C.c_void_p()
+    _check(load().cpapr_plan_create(C.byref(coo), R, C.byref(params), ws.data_ptr(), ws.numel() * ws.element_size(),
+                                    _stream(stream), C.byref(h)))
+    return h
+
+
+def cpapr_plan_destroy(h):
+    return _check(load().cpapr_plan_destroy(h))
+
+
+def cpapr_plan_segments(h, mode: int) -> int:
+    return int(load().cpapr_plan_segments(h, mode))
+
+
+def cpapr_phi(h, mode, B, A, eps, Phi, stream=None):
+    return _check(load().cpapr_phi(h, mode, B.data_ptr(), _ptr_array(A), eps, Phi.data_ptr(), _stream(stream)))
+
+
+def cpapr_mu_inner(h, mode, B, A, Phi_last, stream=None) -> dict:
+    st = cpapr_stats()
+    _check(load().cpapr_mu_inner(h, mode, B.data_ptr(), _ptr_array(A), Phi_last.data_ptr(), C.byref(st),
+                                 _stream(stream)))
+    return st.as_dict()
+
+
+def cpapr_solve(h, lam, A, stream=None) -> dict:
+    st = cpapr_stats()
+    _check(load().cpapr_solve(h, lam.data_ptr(), _ptr_array(A), C.byref(st), _stream(stream)))
+    return st.as_dict()
+
+
+def cpapr_loglik(h, lam, A, eps, stream=None) -> float:
+    out = C.c_double(0)
+    _check(load().cpapr_loglik(h, lam.data_ptr(), _ptr_array(A), eps, C.byref(out), _stream(stream)))
+    return out.value
+
+
+def cpapr_mttkrp(h, mode, A, M, stream=None):
+    return _check(load().cpapr_mttkrp(h, mode, _ptr_array(A), M.data_ptr(), _stream(stream)))
+
+
+def cpapr_prof_enable(capacity: int):
+    return _check(load().cpapr_prof_enable(capacity))
+
+
+def cpapr_prof_disable():
+    return _check(load().cpapr_prof_disable())
+
+
+def cpapr_prof_read(cap: int = 1 << 16):
+    modes = (C.c_int32 * cap)()
+    ms = (C.c_float * cap)()
+    n = _check(load().cpapr_prof_read(modes, ms, cap))
+    return [(modes[i], ms[i]) for i in range(n)]
+
+
+def cpapr_last_error() -> str:
+    return load().cpapr_last_error().decode()
+
+
+class Plan:
+    """A plan for one tensor (device COO) at rank R, owning its workspace tensor."""
+
+    def __init__(self, dims, idx, vals, R: int, params: Optional[cpapr_params] = None, stream=None, **kw):
+        import torch
+        self.dims = tuple(int(d) for d in dims)
+        self.R = int(R)
+        self.params = params if params is not None else cpapr_params_default(**kw)
+        coo = make_coo(self.dims, idx, vals)
+        self.nnz = int(vals.shape[0])
+        nbytes = cpapr_plan_workspace_size(coo, self.R, self.params)
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=idx.device)
+        self.handle = cpapr_plan_create(coo, self.R, self.params, self.ws, stream)
+
+    @classmethod
+    def from_tensor(cls, X, R, device="cuda", **kw):
+        import torch
+        idx = torch.from_numpy(X.idx).to(device)
+        vals = torch.from_numpy(X.vals).to(device)
+        return cls(X.dims, idx, vals, R, **kw)
+
+    def segments(self, mode):
+        return cpapr_plan_segments(self.handle, mode)
+
+    def phi(self, mode, B, A, eps=None, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.dims[mode], self.R), dtype=torch.float64, device=B.device)
+        cpapr_phi(self.handle, mode, B, A, self.params.eps if eps is None else eps, out, stream)
+        return out
+
+    def mu_inner(self, mode, B, A, phi_last=None, stream=None):
+        import torch
+        if phi_last is None:
+            phi_last = torch.empty((self.dims[mode], self.R), dtype=torch.float64, device=B.device)
+        st = cpapr_mu_inner(self.handle, mode, B, A, phi_last, stream)
+        return phi_last, st
+
+    def solve(self, lam, A, stream=None):
+        return cpapr_solve(self.handle, lam, A, stream)
+
+    def loglik(self, lam, A, eps=None, stream=None):
+        return cpapr_loglik(self.handle, lam, A, self.params.eps if eps is None else eps, stream)
+
+    def mttkrp(self, mode, A, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.dims[mode], self.R), dtype=torch.float64, device=A[0].device)
+        cpapr_mttkrp(self.handle, mode, A, out, stream)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            cpapr_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

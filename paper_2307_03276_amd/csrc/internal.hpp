@@ -1,0 +1,111 @@
+// Internal declarations shared by the HIP translation units of libcpapr.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/cpapr.h"
+
+namespace cpapr {
+
+constexpr int kBlock = 256;  // threads per workgroup for every kernel here (4 wave64s)
+constexpr int kXcds = 8;     // MI355X: 8 accelerator complex dies, each with its own L2
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+// Device-side state block of one inner loop (lives in the plan workspace).
+struct DevState {
+    unsigned long long viol[CPAPR_MAX_LMAX];  // bit patterns of nonnegative doubles (max via u64)
+    double last_viol[CPAPR_MAX_MODES];        // last KKT violation seen per mode
+    int done;                                 // inner loop of the current mode has stopped
+    int updates;                              // MU updates in the current inner loop
+    int sweep_updates;                        // MU updates in the current outer sweep
+    long long total_updates;                  // MU updates since the last reset
+    double ll;                                // log-likelihood result
+};
+
+struct PlanMode {
+    int32_t* rows;  // [nnz] sorted mode-n coordinates
+    int32_t* cidx;  // [(N-1) * nnz] the other modes' coordinates in sorted order, ascending m
+    double* vals;   // [nnz]
+    int64_t segments;
+};
+
+}  // namespace cpapr
+
+struct cpapr_plan {
+    int32_t N;
+    int64_t nnz;
+    int32_t R;
+    int64_t dims[CPAPR_MAX_MODES];
+    cpapr_params params;
+    cpapr::PlanMode mode[CPAPR_MAX_MODES];
+    float* f32[CPAPR_MAX_MODES];      // FP32 factor copies (mixed precision)
+    double* B;                        // [maxI x R] solve work matrix
+    double* phi_prev[CPAPR_MAX_MODES];  // [I_m x R] last Phi per mode (solve)
+    double* partial;                  // [kPartials x R] column-sum / reduction partials
+    double* colsums;                  // [N x R]
+    cpapr::DevState* state;
+    char* ws;
+    size_t ws_bytes;
+    int group, chunk;                 // resolved launch shape of the Phi kernel
+};
+
+namespace cpapr {
+
+constexpr int kPartials = 512;  // blocks of the two-level deterministic reductions
+
+// ---- plan construction (sort.hip) ----
+int64_t sort_scratch_bytes(int64_t nnz);
+// Validates coordinates/values, then builds the sorted copies of every mode.
+Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t s);
+
+// ---- Phi (phi.hip) ----
+// Resolve the lane-group size for rank R (the `group` parameter, 0 = automatic).
+int resolve_group(int R, int requested);
+int resolve_chunk(int group, int requested);
+// Rank columns per lane (1, 2 or 4) for rank R on `group` lanes; -1 if R > 4 * group.
+int rank_block(int R, int group);
+Error launch_phi(const cpapr_plan* P, int mode, const double* B, const void* const* fac, bool mixed,
+                 double eps, double* Phi, const int* done, hipStream_t s);
+Error launch_mttkrp(const cpapr_plan* P, int mode, const double* const* A, double* M, hipStream_t s);
+
+// ---- elementwise and reduction kernels (mu.hip) ----
+Error launch_fill(double* p, int64_t n, double v, const int* done, hipStream_t s);
+Error launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+Error launch_reset_state(DevState* st, int lmax, bool new_sweep, bool all, hipStream_t s);
+Error launch_kkt(const double* B, const double* Phi, int64_t n, DevState* st, int l, hipStream_t s);
+Error launch_mu_update(double* B, const double* Phi, int64_t n, DevState* st, int l, int mode, double tol,
+                       hipStream_t s);
+Error launch_shift_scale(double* A, const double* phi_prev, const double* lam, double* B, int64_t I, int R,
+                         double kappa, double kappa_tol, bool shift, hipStream_t s);
+Error launch_colsum(const double* M, int64_t I, int R, double* partial, double* out, hipStream_t s);
+Error launch_normalize(const double* B, const double* lam, double* A, float* A32, int64_t I, int R,
+                       hipStream_t s);
+Error launch_loglik(const cpapr_plan* P, const double* lam, const double* const* A, double eps,
+                    hipStream_t s);
+
+// ---- profiling hooks (api.hip) ----
+void prof_begin(int mode, hipStream_t s);
+void prof_end(hipStream_t s);
+
+}  // namespace cpapr
+
+#define CPAPR_HIP(call)                                                                 \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return ::cpapr::Error{CPAPR_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define CPAPR_LAUNCHED()                                                                \
+    do {                                                                                \
+        hipError_t e_ = hipGetLastError();                                              \
+        if (e_ != hipSuccess)                                                           \
+            return ::cpapr::Error{CPAPR_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_)}; \
+    } while (0)

@@ -1,0 +1,327 @@
+// Kernels around Phi in Algorithm 1: the MU step B <- B .* Phi, the KKT
+// violation max |min(B, 1 - Phi)|, the inadmissible-zero shift and
+// B = (A + S) Lambda, lambda = e^T B with A = B Lambda^-1, FP32 factor copies,
+// and the Poisson log-likelihood.
+//
+// The inner loop's stop decision never leaves the device: the KKT kernel
+// max-reduces the violation into a per-iteration slot; the update kernel reads
+// it, and when it is below tol raises a `done` flag that every later kernel of
+// the same inner loop checks before doing any work. The host enqueues lmax
+// iterations without waiting.
+//
+// All reductions are two-level with a fixed partition and a fixed order, so
+// their results are bitwise reproducible run to run.
+#include "internal.hpp"
+
+namespace cpapr {
+namespace {
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline unsigned grid_for(int64_t n, int64_t cap = 4096)
+{
+    int64_t g = cdiv(n, kBlock);
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+__global__ __launch_bounds__(kBlock) void fill_kernel(double* p, int64_t n, double v, const int* done)
+{
+    if (done != nullptr && *done) return;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst,
+                                                        int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        dst[i] = (float)src[i];
+}
+
+__global__ __launch_bounds__(kBlock) void reset_state_kernel(DevState* st, int lmax, int new_sweep, int all)
+{
+    for (int l = threadIdx.x; l < lmax; l += kBlock) st->viol[l] = 0ull;
+    if (threadIdx.x == 0) {
+        st->done = 0;
+        st->updates = 0;
+        if (new_sweep) st->sweep_updates = 0;
+        if (all) {
+            st->total_updates = 0;
+            for (int m = 0; m < CPAPR_MAX_MODES; ++m) st->last_viol[m] = 0.0;
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+// viol[l] = max over entries of |min(B, 1 - Phi)|, as the ordered bit pattern
+// of a nonnegative double.
+__global__ __launch_bounds__(kBlock) void kkt_kernel(const double* __restrict__ B, const double* __restrict__ Phi,
+                                                     int64_t n, DevState* st, int l)
+{
+    if (st->done) return;
+    double v = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const double b = B[i], q = 1.0 - Phi[i];
+        v = fmax(v, fabs(b < q ? b : q));
+    }
+    __shared__ double red[kBlock / 64];
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < kBlock / 64; ++w) m = fmax(m, red[w]);
+        atomicMax(&st->viol[l], (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// B <- B .* Phi unless the KKT test says stop. Only block 0 records the
+// violation and raises `done`; other blocks of this launch that see `done`
+// early skip work they would have skipped anyway.
+__global__ __launch_bounds__(kBlock) void mu_update_kernel(double* __restrict__ B, const double* __restrict__ Phi,
+                                                           int64_t n, DevState* st, int l, int mode, double tol)
+{
+    if (st->done) return;
+    const double viol = __longlong_as_double((long long)st->viol[l]);
+    const bool stop = tol > 0.0 && viol < tol;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->last_viol[mode] = viol;
+        if (stop) {
+            st->done = 1;
+        } else {
+            st->updates += 1;
+            st->sweep_updates += 1;
+            st->total_updates += 1;
+        }
+    }
+    if (stop) return;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        B[i] *= Phi[i];
+}
+
+// A(n) += kappa where A < kappa_tol and the previous Phi > 1 (from the second
+// outer iteration on), then B = A(n) diag(lambda).
+__global__ __launch_bounds__(kBlock) void shift_scale_kernel(double* __restrict__ A,
+                                                             const double* __restrict__ phi_prev,
+                                                             const double* __restrict__ lam, double* __restrict__ B,
+                                                             int64_t n, int R, double kappa, double kappa_tol,
+                                                             int shift)
+{
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+        double a = A[e];
+        if (shift && a < kappa_tol && phi_prev[e] > 1.0) {
+            a += kappa;
+            A[e] = a;
+        }
+        B[e] = a * lam[e % R];
+    }
+}
+
+// Column sums, level 1: block b sums rows [b*rpb, (b+1)*rpb) with Q = 256/R
+// threads per column, then reduces the Q partials in order.
+__global__ __launch_bounds__(kBlock) void colsum_partial_kernel(const double* __restrict__ M, int64_t I, int R,
+                                                                int64_t rpb, double* __restrict__ partial)
+{
+    __shared__ double sm[kBlock];
+    const int Q = kBlock / R;
+    const int t = threadIdx.x;
+    const int c = t % R, q = t / R;
+    const int64_t r0 = (int64_t)blockIdx.x * rpb;
+    const int64_t r1 = min(r0 + rpb, I);
+    double s = 0.0;
+    if (q < Q)
+        for (int64_t i = r0 + q; i < r1; i += Q) s += M[i * R + c];
+    sm[t] = q < Q ? s : 0.0;
+    __syncthreads();
+    if (t < R) {
+        double tot = 0.0;
+        for (int qq = 0; qq < Q; ++qq) tot += sm[qq * R + t];
+        partial[(int64_t)blockIdx.x * R + t] = tot;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void colsum_final_kernel(const double* __restrict__ partial, int nparts, int R,
+                                                              double* __restrict__ out)
+{
+    for (int c = threadIdx.x; c < R; c += kBlock) {
+        double s = 0.0;
+        for (int b = 0; b < nparts; ++b) s += partial[(int64_t)b * R + c];
+        out[c] = s;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void normalize_kernel(const double* __restrict__ B,
+                                                           const double* __restrict__ lam, double* __restrict__ A,
+                                                           float* __restrict__ A32, int64_t n, int R)
+{
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+        const double l = lam[e % R];
+        const double a = l > 0.0 ? B[e] / l : 0.0;
+        A[e] = a;
+        if (A32) A32[e] = (float)a;
+    }
+}
+
+struct LLArgs {
+    const int32_t* rows;
+    const int32_t* cidx;
+    const double* vals;
+    const double* fac0;
+    const double* fac[CPAPR_MAX_MODES - 1];
+    const double* lam;
+    int64_t nnz;
+    int R;
+    int NM1;
+    double eps;
+    double* partial;
+};
+
+// sum_k x_k log(max(m_k, eps)), m_k = sum_r lam_r prod_m A(m)[i_m, r]; a
+// 16-lane group per nonzero, fixed grid-stride order, ordered block reduction.
+__global__ __launch_bounds__(kBlock) void loglik_partial_kernel(LLArgs a)
+{
+    constexpr int G = 16, NG = kBlock / G;
+    __shared__ double red[NG];
+    const int t = threadIdx.x, g = t / G, lane = t % G;
+    double acc = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * NG + g; p < a.nnz; p += (int64_t)gridDim.x * NG) {
+        const int32_t i0 = a.rows[p];
+        double part = 0.0;
+        for (int r = lane; r < a.R; r += G) {
+            double v = a.lam[r] * a.fac0[(int64_t)i0 * a.R + r];
+            for (int m = 0; m < a.NM1; ++m) v *= a.fac[m][(int64_t)a.cidx[(int64_t)m * a.nnz + p] * a.R + r];
+            part += v;
+        }
+        for (int off = 1; off < G; off <<= 1) part += __shfl_xor(part, off, G);
+        acc += a.vals[p] * log(part > a.eps ? part : a.eps);
+    }
+    if (lane == 0) red[g] = acc;
+    __syncthreads();
+    if (t == 0) {
+        double s = 0.0;
+        for (int q = 0; q < NG; ++q) s += red[q];
+        a.partial[blockIdx.x] = s;
+    }
+}
+
+__global__ void loglik_final_kernel(const double* __restrict__ partial, int nparts, const double* __restrict__ lam,
+                                    const double* __restrict__ colsums, int N, int R, DevState* st)
+{
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nparts; ++b) s += partial[b];
+    double mass = 0.0;
+    for (int r = 0; r < R; ++r) {
+        double p = lam[r];
+        for (int m = 0; m < N; ++m) p *= colsums[(int64_t)m * R + r];
+        mass += p;
+    }
+    st->ll = s - mass;
+}
+
+}  // namespace
+
+Error launch_fill(double* p, int64_t n, double v, const int* done, hipStream_t s)
+{
+    if (n <= 0) return {CPAPR_OK, ""};
+    fill_kernel<<<grid_for(n, 8192), kBlock, 0, s>>>(p, n, v, done);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+Error launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return {CPAPR_OK, ""};
+    to_f32_kernel<<<grid_for(n, 8192), kBlock, 0, s>>>(src, dst, n);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+Error launch_reset_state(DevState* st, int lmax, bool new_sweep, bool all, hipStream_t s)
+{
+    reset_state_kernel<<<1, kBlock, 0, s>>>(st, lmax, new_sweep ? 1 : 0, all ? 1 : 0);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+Error launch_kkt(const double* B, const double* Phi, int64_t n, DevState* st, int l, hipStream_t s)
+{
+    kkt_kernel<<<grid_for(n, 2048), kBlock, 0, s>>>(B, Phi, n, st, l);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+Error launch_mu_update(double* B, const double* Phi, int64_t n, DevState* st, int l, int mode, double tol,
+                       hipStream_t s)
+{
+    mu_update_kernel<<<grid_for(n, 4096), kBlock, 0, s>>>(B, Phi, n, st, l, mode, tol);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+Error launch_shift_scale(double* A, const double* phi_prev, const double* lam, double* B, int64_t I, int R,
+                         double kappa, double kappa_tol, bool shift, hipStream_t s)
+{
+    const int64_t n = I * R;
+    shift_scale_kernel<<<grid_for(n, 4096), kBlock, 0, s>>>(A, phi_prev, lam, B, n, R, kappa, kappa_tol,
+                                                            shift ? 1 : 0);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+Error launch_colsum(const double* M, int64_t I, int R, double* partial, double* out, hipStream_t s)
+{
+    int64_t nparts = cdiv(I, 64);
+    if (nparts > kPartials) nparts = kPartials;
+    if (nparts < 1) nparts = 1;
+    const int64_t rpb = cdiv(I, nparts);
+    colsum_partial_kernel<<<(unsigned)nparts, kBlock, 0, s>>>(M, I, R, rpb, partial);
+    CPAPR_LAUNCHED();
+    colsum_final_kernel<<<1, kBlock, 0, s>>>(partial, (int)nparts, R, out);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+Error launch_normalize(const double* B, const double* lam, double* A, float* A32, int64_t I, int R, hipStream_t s)
+{
+    const int64_t n = I * R;
+    normalize_kernel<<<grid_for(n, 4096), kBlock, 0, s>>>(B, lam, A, A32, n, R);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+Error launch_loglik(const cpapr_plan* P, const double* lam, const double* const* A, double eps, hipStream_t s)
+{
+    const int N = P->N, R = P->R;
+    for (int m = 0; m < N; ++m) {
+        Error e = launch_colsum(A[m], P->dims[m], R, P->partial, P->colsums + (int64_t)m * R, s);
+        if (e.code) return e;
+    }
+    LLArgs a{};
+    a.rows = P->mode[0].rows;
+    a.cidx = P->mode[0].cidx;
+    a.vals = P->mode[0].vals;
+    a.fac0 = A[0];
+    for (int m = 1; m < N; ++m) a.fac[m - 1] = A[m];
+    a.lam = lam;
+    a.nnz = P->nnz;
+    a.R = R;
+    a.NM1 = N - 1;
+    a.eps = eps;
+    a.partial = P->partial;
+    const int nparts = kPartials;
+    loglik_partial_kernel<<<nparts, kBlock, 0, s>>>(a);
+    CPAPR_LAUNCHED();
+    loglik_final_kernel<<<1, 64, 0, s>>>(P->partial, nparts, lam, P->colsums, N, R, P->state);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+}  // namespace cpapr

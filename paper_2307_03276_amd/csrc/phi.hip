@@ -1,0 +1,511 @@
+// Phi(n) = (X_(n) ./ max(B Pi, eps)) Pi^T  (Algorithm 2), one nonzero at a time.
+//
+// Work decomposition (gfx950, wave64):
+//  * A lane group of G lanes owns one nonzero at a time; each lane holds RPL
+//    consecutive rank columns (rank blocking: R <= G * RPL). A wave runs 64/G
+//    nonzeros side by side.
+//  * Nonzeros are pre-sorted by the mode-n coordinate (plan). A workgroup takes
+//    a tile of consecutive sorted nonzeros; each of its lane groups walks a
+//    contiguous sub-chunk of `chunk` nonzeros sequentially, keeping the Phi row
+//    being built in registers. This is the paper's CPU "atomic mitigation"
+//    idea (Algorithm 4: accumulate locally while the row is unchanged) mapped to
+//    lane groups: a row that starts and ends inside the sub-chunk is owned by
+//    the group and written with a plain store.
+//  * A sub-chunk's first and last rows may continue in the neighbouring
+//    sub-chunks; their partial rows go to LDS and are merged in order across
+//    the workgroup. After the merge only rows that cross the tile boundary are
+//    written with FP64 atomics (the paper's atomic update strategy, Section 3.1,
+//    now confined to tile ends); every other row is a plain store.
+//  * The dot product B[i,:] . pi_k is an all-reduce across the lane group with
+//    DPP row permutations (xor-1, xor-2, half-mirror, mirror) and, for 32/64
+//    lanes, ds_swizzle / ds_bpermute; every lane ends with the same bits.
+//  * Tiles are mapped XCD-aware: consecutive tiles (which share B and Phi rows)
+//    are given to the same XCD so their rows stay in one L2.
+//
+// Mixed precision: factors and pi are FP32; products and sums carry an FP32
+// error term (TwoProd by FMA, Knuth TwoSum), and Phi partials leave registers
+// as FP64 hi + lo.
+#include <type_traits>
+
+#include "internal.hpp"
+
+namespace cpapr {
+namespace {
+
+constexpr int kMaxOther = CPAPR_MAX_MODES - 1;
+
+struct PhiArgs {
+    const int32_t* rows;
+    const int32_t* cidx;
+    const double* vals;
+    const void* fac[kMaxOther];
+    const double* B;
+    double* Phi;
+    const int* done;
+    int64_t nnz;
+    int R;
+    int NM1;
+    int L;
+    double eps;
+};
+
+__device__ __forceinline__ int xcd_remap(int bid, int nb)
+{
+    const int q = nb / kXcds, rmd = nb % kXcds;
+    const int xcd = bid % kXcds, local = bid / kXcds;
+    return (xcd < rmd ? xcd * (q + 1) : rmd * (q + 1) + (xcd - rmd) * q) + local;
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// lane ^ 16 inside each 32-lane half (ds_swizzle bitmask mode: and 0x1f, xor 0x10)
+__device__ __forceinline__ double xor16_f64(double v)
+{
+    int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
+    int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float xor16_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+}
+__device__ __forceinline__ double xor32_f64(double v)
+{
+    const int addr = ((int)(threadIdx.x & 63) ^ 32) << 2;
+    int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+    int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float xor32_f32(float v)
+{
+    const int addr = ((int)(threadIdx.x & 63) ^ 32) << 2;
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+
+// DPP controls: quad_perm [1,0,3,2] = 0xB1, quad_perm [2,3,0,1] = 0x4E,
+// row_half_mirror = 0x141, row_mirror = 0x140.
+template <int G>
+__device__ __forceinline__ double group_sum(double v)
+{
+    if constexpr (G >= 2) v += dpp_f64<0xB1>(v);
+    if constexpr (G >= 4) v += dpp_f64<0x4E>(v);
+    if constexpr (G >= 8) v += dpp_f64<0x141>(v);
+    if constexpr (G >= 16) v += dpp_f64<0x140>(v);
+    if constexpr (G >= 32) v += xor16_f64(v);
+    if constexpr (G >= 64) v += xor32_f64(v);
+    return v;
+}
+
+#pragma clang fp contract(off)
+// Knuth TwoSum: s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e)
+{
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void pair_add(float& hi, float& lo, float ohi, float olo)
+{
+    float s, e;
+    two_sum(hi, ohi, s, e);
+    hi = s;
+    lo = (lo + olo) + e;
+}
+
+template <int G>
+__device__ __forceinline__ void group_sum_pair(float& hi, float& lo)
+{
+    if constexpr (G >= 2) pair_add(hi, lo, dpp_f32<0xB1>(hi), dpp_f32<0xB1>(lo));
+    if constexpr (G >= 4) pair_add(hi, lo, dpp_f32<0x4E>(hi), dpp_f32<0x4E>(lo));
+    if constexpr (G >= 8) pair_add(hi, lo, dpp_f32<0x141>(hi), dpp_f32<0x141>(lo));
+    if constexpr (G >= 16) pair_add(hi, lo, dpp_f32<0x140>(hi), dpp_f32<0x140>(lo));
+    if constexpr (G >= 32) pair_add(hi, lo, xor16_f32(hi), xor16_f32(lo));
+    if constexpr (G >= 64) pair_add(hi, lo, xor32_f32(hi), xor32_f32(lo));
+}
+
+// Compensated accumulate of a*b into (hi, lo): TwoProd via FMA, then TwoSum.
+__device__ __forceinline__ void acc_prod(float& hi, float& lo, float a, float b)
+{
+    const float p = a * b;
+    const float pe = __builtin_fmaf(a, b, -p);
+    float s, e;
+    two_sum(hi, p, s, e);
+    hi = s;
+    lo = lo + (e + pe);
+}
+#pragma clang fp contract(fast)
+
+// Per-lane accumulator of one Phi row slice: FP64, or FP32 hi + lo.
+template <bool MIXED>
+struct Acc;
+
+template <>
+struct Acc<false> {
+    double v;
+    __device__ void zero() { v = 0.0; }
+    __device__ void add(double s, double pi) { v = __builtin_fma(s, pi, v); }
+    __device__ double value() const { return v; }
+};
+
+template <>
+struct Acc<true> {
+    float hi, lo;
+    __device__ void zero() { hi = lo = 0.f; }
+    __device__ void add(float s, float pi) { acc_prod(hi, lo, s, pi); }
+    __device__ double value() const { return (double)hi + (double)lo; }
+};
+
+// One nonzero's pi slice, dot product and scale. Returns s_k (or x_k for MTTKRP).
+template <int G, int RPL, bool MIXED, bool MTTKRP, typename T>
+__device__ __forceinline__ T nonzero_scale(const T (&b)[RPL], const T (&pi)[RPL], double x, double eps)
+{
+    if constexpr (MTTKRP) {
+        return (T)x;
+    } else if constexpr (!MIXED) {
+        double d = 0.0;
+#pragma unroll
+        for (int c = 0; c < RPL; ++c) d = __builtin_fma(b[c], pi[c], d);
+        d = group_sum<G>(d);
+        return x / (d > eps ? d : eps);
+    } else {
+        float hi = 0.f, lo = 0.f;
+#pragma unroll
+        for (int c = 0; c < RPL; ++c) acc_prod(hi, lo, b[c], pi[c]);
+        group_sum_pair<G>(hi, lo);
+        const float m = hi + lo;
+        const float e = (float)eps;
+        return (float)x / (m > e ? m : e);
+    }
+}
+
+template <int G, int RPL, bool MIXED, bool MTTKRP>
+__global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
+{
+    using T = typename std::conditional<MIXED, float, double>::type;
+    constexpr int NG = kBlock / G;
+    constexpr int W = G * RPL;
+    __shared__ double part[2 * NG][W];
+    __shared__ int prow[2 * NG];
+
+    if (a.done != nullptr && *a.done) return;
+
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int t = threadIdx.x;
+    const int g = t / G;
+    const int lane = t % G;
+    const int R = a.R;
+    const int64_t nnz = a.nnz;
+    const int64_t tile_start = (int64_t)tile * NG * a.L;
+    const int64_t tile_end = min(tile_start + (int64_t)NG * a.L, nnz);
+    const int64_t p0 = tile_start + (int64_t)g * a.L;
+    const int64_t p1 = min(p0 + (int64_t)a.L, nnz);
+
+    if (lane == 0) {
+        prow[2 * g] = -1;
+        prow[2 * g + 1] = -1;
+    }
+
+    bool valid[RPL];
+#pragma unroll
+    for (int c = 0; c < RPL; ++c) valid[c] = lane * RPL + c < R;
+
+    int cur = -1;
+    int nseg = 0;
+    Acc<MIXED> acc[RPL];
+    T b[RPL];
+#pragma unroll
+    for (int c = 0; c < RPL; ++c) {
+        acc[c].zero();
+        b[c] = (T)0;
+    }
+
+    // Flush kinds: 0 = head partial (LDS), 1 = tail partial (LDS), 2 = owned row (store).
+    auto flush = [&](int row, int kind) {
+        if (kind == 2) {
+            double* dst = a.Phi + (int64_t)row * R + lane * RPL;
+#pragma unroll
+            for (int c = 0; c < RPL; ++c)
+                if (valid[c]) dst[c] = acc[c].value();
+        } else {
+            const int e = 2 * g + kind;
+#pragma unroll
+            for (int c = 0; c < RPL; ++c) part[e][lane * RPL + c] = acc[c].value();
+            if (lane == 0) prow[e] = row;
+        }
+    };
+
+    for (int64_t p = p0; p < p1; ++p) {
+        const int row = a.rows[p];
+        const double x = a.vals[p];
+        T pi[RPL];
+#pragma unroll
+        for (int c = 0; c < RPL; ++c) pi[c] = valid[c] ? (T)1 : (T)0;
+        for (int m = 0; m < a.NM1; ++m) {
+            const int32_t ci = a.cidx[(int64_t)m * nnz + p];
+            const T* f = (const T*)a.fac[m] + (int64_t)ci * R + lane * RPL;
+#pragma unroll
+            for (int c = 0; c < RPL; ++c)
+                if (valid[c]) pi[c] *= f[c];
+        }
+        if (row != cur) {
+            if (cur >= 0) flush(cur, nseg == 1 ? 0 : 2);
+            cur = row;
+            ++nseg;
+#pragma unroll
+            for (int c = 0; c < RPL; ++c) acc[c].zero();
+            if constexpr (!MTTKRP) {
+                const double* brow = a.B + (int64_t)row * R + lane * RPL;
+#pragma unroll
+                for (int c = 0; c < RPL; ++c) b[c] = valid[c] ? (T)brow[c] : (T)0;
+            }
+        }
+        const T s = nonzero_scale<G, RPL, MIXED, MTTKRP, T>(b, pi, x, a.eps);
+#pragma unroll
+        for (int c = 0; c < RPL; ++c) acc[c].add(s, pi[c]);
+    }
+    if (cur >= 0) flush(cur, nseg == 1 ? 0 : 1);
+    __syncthreads();
+
+    // Ordered merge of the head/tail partials; rows crossing the tile boundary
+    // go out with atomics, all others with plain stores.
+    if (t < R && t < W) {
+        const int prev_row = tile_start > 0 ? a.rows[tile_start - 1] : -1;
+        const int next_row = tile_end < nnz ? a.rows[tile_end] : -1;
+        int run = -1;
+        double v = 0.0;
+        auto emit = [&](int row, double val) {
+            double* dst = a.Phi + (int64_t)row * R + t;
+            if (row == prev_row || row == next_row)
+                unsafeAtomicAdd(dst, val);
+            else
+                *dst = val;
+        };
+        for (int e = 0; e < 2 * NG; ++e) {
+            const int re = prow[e];
+            if (re < 0) continue;
+            if (re == run) {
+                v += part[e][t];
+            } else {
+                if (run >= 0) emit(run, v);
+                run = re;
+                v = part[e][t];
+            }
+        }
+        if (run >= 0) emit(run, v);
+    }
+}
+
+// The paper's GPU kernel shape (Algorithm 3): one lane group per nonzero and an
+// atomic add of every Phi entry it touches. Kept as a comparison variant.
+template <int G, int RPL>
+__global__ __launch_bounds__(kBlock) void phi_atomic_kernel(PhiArgs a)
+{
+    constexpr int NG = kBlock / G;
+    if (a.done != nullptr && *a.done) return;
+    const int t = threadIdx.x;
+    const int g = t / G;
+    const int lane = t % G;
+    const int R = a.R;
+    bool valid[RPL];
+#pragma unroll
+    for (int c = 0; c < RPL; ++c) valid[c] = lane * RPL + c < R;
+    const int64_t stride = (int64_t)gridDim.x * NG;
+    for (int64_t p = (int64_t)blockIdx.x * NG + g; p < a.nnz; p += stride) {
+        const int row = a.rows[p];
+        const double x = a.vals[p];
+        double pi[RPL], b[RPL];
+#pragma unroll
+        for (int c = 0; c < RPL; ++c) pi[c] = valid[c] ? 1.0 : 0.0;
+        for (int m = 0; m < a.NM1; ++m) {
+            const int32_t ci = a.cidx[(int64_t)m * a.nnz + p];
+            const double* f = (const double*)a.fac[m] + (int64_t)ci * R + lane * RPL;
+#pragma unroll
+            for (int c = 0; c < RPL; ++c)
+                if (valid[c]) pi[c] *= f[c];
+        }
+        const double* brow = a.B + (int64_t)row * R + lane * RPL;
+#pragma unroll
+        for (int c = 0; c < RPL; ++c) b[c] = valid[c] ? brow[c] : 0.0;
+        const double s = nonzero_scale<G, RPL, false, false, double>(b, pi, x, a.eps);
+        double* dst = a.Phi + (int64_t)row * R + lane * RPL;
+#pragma unroll
+        for (int c = 0; c < RPL; ++c)
+            if (valid[c]) unsafeAtomicAdd(dst + c, s * pi[c]);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void zero_kernel(double* p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = 0.0;
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <bool MIXED, bool MTTKRP>
+Error dispatch_seg(int G, int RPL, const PhiArgs& a, hipStream_t s)
+{
+    const int NG = kBlock / G;
+    const int64_t tiles = cdiv(a.nnz, (int64_t)NG * a.L);
+    if (tiles <= 0) return {CPAPR_OK, ""};
+    if (tiles > 0x7fffffff) return {CPAPR_EUNSUPPORTED, "too many tiles"};
+    const dim3 grid((unsigned)tiles);
+#define CPAPR_SEG_CASE(GG, RR)                                                        \
+    if (G == GG && RPL == RR) {                                                       \
+        phi_seg_kernel<GG, RR, MIXED, MTTKRP><<<grid, kBlock, 0, s>>>(a);             \
+        CPAPR_LAUNCHED();                                                             \
+        return {CPAPR_OK, ""};                                                        \
+    }
+    CPAPR_SEG_CASE(4, 1)
+    CPAPR_SEG_CASE(4, 2)
+    CPAPR_SEG_CASE(4, 4)
+    CPAPR_SEG_CASE(8, 1)
+    CPAPR_SEG_CASE(8, 2)
+    CPAPR_SEG_CASE(8, 4)
+    CPAPR_SEG_CASE(16, 1)
+    CPAPR_SEG_CASE(16, 2)
+    CPAPR_SEG_CASE(16, 4)
+    CPAPR_SEG_CASE(32, 1)
+    CPAPR_SEG_CASE(32, 2)
+    CPAPR_SEG_CASE(32, 4)
+    CPAPR_SEG_CASE(64, 1)
+    CPAPR_SEG_CASE(64, 2)
+    CPAPR_SEG_CASE(64, 4)
+#undef CPAPR_SEG_CASE
+    return {CPAPR_EUNSUPPORTED, "no Phi kernel for this lane-group / rank-block shape"};
+}
+
+Error dispatch_atomic(int G, int RPL, const PhiArgs& a, hipStream_t s)
+{
+    const int NG = kBlock / G;
+    int64_t blocks = cdiv(a.nnz, (int64_t)NG);
+    if (blocks > 65536) blocks = 65536;
+    if (blocks <= 0) return {CPAPR_OK, ""};
+#define CPAPR_AT_CASE(GG, RR)                                                         \
+    if (G == GG && RPL == RR) {                                                       \
+        phi_atomic_kernel<GG, RR><<<(unsigned)blocks, kBlock, 0, s>>>(a);             \
+        CPAPR_LAUNCHED();                                                             \
+        return {CPAPR_OK, ""};                                                        \
+    }
+    CPAPR_AT_CASE(4, 1)
+    CPAPR_AT_CASE(4, 2)
+    CPAPR_AT_CASE(4, 4)
+    CPAPR_AT_CASE(8, 1)
+    CPAPR_AT_CASE(8, 2)
+    CPAPR_AT_CASE(8, 4)
+    CPAPR_AT_CASE(16, 1)
+    CPAPR_AT_CASE(16, 2)
+    CPAPR_AT_CASE(16, 4)
+    CPAPR_AT_CASE(32, 1)
+    CPAPR_AT_CASE(32, 2)
+    CPAPR_AT_CASE(32, 4)
+    CPAPR_AT_CASE(64, 1)
+    CPAPR_AT_CASE(64, 2)
+    CPAPR_AT_CASE(64, 4)
+#undef CPAPR_AT_CASE
+    return {CPAPR_EUNSUPPORTED, "no atomic Phi kernel for this shape"};
+}
+
+PhiArgs make_args(const cpapr_plan* P, int mode, const double* B, const void* const* fac, double eps,
+                  double* Phi, const int* done)
+{
+    PhiArgs a{};
+    const PlanMode& pm = P->mode[mode];
+    a.rows = pm.rows;
+    a.cidx = pm.cidx;
+    a.vals = pm.vals;
+    int j = 0;
+    for (int m = 0; m < P->N; ++m)
+        if (m != mode) a.fac[j++] = fac[m];
+    a.B = B;
+    a.Phi = Phi;
+    a.done = done;
+    a.nnz = P->nnz;
+    a.R = P->R;
+    a.NM1 = P->N - 1;
+    a.L = P->chunk;
+    a.eps = eps;
+    return a;
+}
+
+Error zero_matrix(double* p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return {CPAPR_OK, ""};
+    int64_t g = cdiv(n, kBlock);
+    if (g > 8192) g = 8192;
+    zero_kernel<<<(unsigned)g, kBlock, 0, s>>>(p, n);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+}  // namespace
+
+int resolve_group(int R, int requested)
+{
+    if (requested != 0) return requested;
+    if (R <= 4) return 4;
+    if (R <= 8) return 8;
+    if (R <= 16) return 16;
+    if (R <= 32) return 32;
+    return 64;
+}
+
+int rank_block(int R, int group)
+{
+    const int need = (R + group - 1) / group;
+    if (need <= 1) return 1;
+    if (need <= 2) return 2;
+    if (need <= 4) return 4;
+    return -1;
+}
+
+int resolve_chunk(int group, int requested)
+{
+    if (requested > 0) return requested;
+    // ~1024 nonzeros per workgroup tile
+    return 1024 / (kBlock / group);
+}
+
+Error launch_phi(const cpapr_plan* P, int mode, const double* B, const void* const* fac, bool mixed,
+                 double eps, double* Phi, const int* done, hipStream_t s)
+{
+    const int G = P->group;
+    const int RPL = rank_block(P->R, G);
+    PhiArgs a = make_args(P, mode, B, fac, eps, Phi, done);
+    if (P->params.variant == CPAPR_VARIANT_ATOMIC) {
+        if (mixed) return {CPAPR_EUNSUPPORTED, "the atomic variant is FP64 only"};
+        prof_begin(mode, s);
+        Error e = dispatch_atomic(G, RPL, a, s);
+        prof_end(s);
+        return e;
+    }
+    prof_begin(mode, s);
+    Error e = mixed ? dispatch_seg<true, false>(G, RPL, a, s) : dispatch_seg<false, false>(G, RPL, a, s);
+    prof_end(s);
+    return e;
+}
+
+Error launch_mttkrp(const cpapr_plan* P, int mode, const double* const* A, double* M, hipStream_t s)
+{
+    const int G = P->group;
+    const int RPL = rank_block(P->R, G);
+    PhiArgs a = make_args(P, mode, nullptr, (const void* const*)A, 0.0, M, nullptr);
+    Error e = zero_matrix(M, P->dims[mode] * (int64_t)P->R, s);
+    if (e.code) return e;
+    return dispatch_seg<false, true>(G, RPL, a, s);
+}
+
+}  // namespace cpapr

@@ -1,0 +1,331 @@
+// Plan construction: input validation and the per-mode sort of the nonzeros.
+//
+// The paper avoids the Phi-row write race by storing the nonzeros of one Phi
+// row contiguously, sorting once per mode at the start (Section 3.1, the
+// sort-by-mode strategy). SparTen keeps N permutation arrays and reads through
+// them; the indirection is the scattered access the paper flags as slow. Here
+// each mode instead gets a physically permuted structure-of-arrays copy, so the
+// Phi kernel streams coordinates and values in order.
+//
+// Sort: stable least-significant-digit radix sort of (i_n, k) pairs with
+// 8-bit digits, one pass per digit of ceil(log2 I_n) bits. Each pass is
+// (1) per-tile digit histograms, (2) an exclusive scan of the digit-major
+// histogram table, (3) a stable scatter that ranks equal digits inside a wave
+// with ballots and across the workgroup's waves through LDS. Stability keeps
+// nonzeros of a row in input order, so plans and Phi are deterministic.
+#include "internal.hpp"
+
+namespace cpapr {
+namespace {
+
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortRounds = 16;                // items per thread per tile
+constexpr int kSortTile = kBlock * kSortRounds;  // 4096 keys per tile
+constexpr int kScanChunk = 4096;                 // elements per block in the scan
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct DimsArg {
+    int64_t d[CPAPR_MAX_MODES];
+};
+
+// flags bit 0: coordinate out of range; bit 1: value not finite or <= 0.
+__global__ __launch_bounds__(kBlock) void validate_kernel(const int32_t* __restrict__ idx,
+                                                          const double* __restrict__ vals, int64_t nnz,
+                                                          int N, DimsArg dims, int* flags)
+{
+    int bad = 0;
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kBlock) {
+        for (int m = 0; m < N; ++m) {
+            int32_t c = idx[(int64_t)m * nnz + k];
+            if (c < 0 || (int64_t)c >= dims.d[m]) bad |= 1;
+        }
+        double v = vals[k];
+        if (!(v > 0.0) || !(v <= 1.7976931348623157e308)) bad |= 2;
+    }
+    if (bad) atomicOr(flags, bad);
+}
+
+// Digit histogram of one 4096-key tile, written digit-major: counts[d * ntiles + tile].
+__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const int32_t* __restrict__ keys, int64_t n,
+                                                            int shift, int* __restrict__ counts, int ntiles)
+{
+    __shared__ int h[kRadix];
+    const int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int q = 0; q < kSortRounds; ++q) {
+        int64_t e = base + q * kBlock + t;
+        if (e < n) atomicAdd(&h[(keys[e] >> shift) & (kRadix - 1)], 1);
+    }
+    __syncthreads();
+    counts[(int64_t)t * ntiles + blockIdx.x] = h[t];
+}
+
+// Block-wide exclusive scan of one value per thread; returns the block total.
+__device__ int block_exclusive_scan(int v, int* tmp, int& total)
+{
+    const int t = threadIdx.x;
+    tmp[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        int add = t >= off ? tmp[t - off] : 0;
+        __syncthreads();
+        tmp[t] += add;
+        __syncthreads();
+    }
+    int incl = tmp[t];
+    total = tmp[kBlock - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+// Scan phase 1: sums of kScanChunk-element chunks.
+__global__ __launch_bounds__(kBlock) void scan_reduce_kernel(const int* __restrict__ a, int64_t n,
+                                                             int* __restrict__ sums)
+{
+    __shared__ int red[kBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    int s = 0;
+    for (int q = threadIdx.x; q < kScanChunk; q += kBlock)
+        if (base + q < n) s += a[base + q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+// Scan phase 2: exclusive scan of the chunk sums by one workgroup.
+__global__ __launch_bounds__(kBlock) void scan_sums_kernel(int* sums, int nsums)
+{
+    __shared__ int tmp[kBlock];
+    int carry = 0;
+    for (int base = 0; base < nsums; base += kBlock) {
+        int i = base + threadIdx.x;
+        int v = i < nsums ? sums[i] : 0;
+        int total;
+        int ex = block_exclusive_scan(v, tmp, total);
+        if (i < nsums) sums[i] = carry + ex;
+        carry += total;
+    }
+}
+
+// Scan phase 3: exclusive scan inside each chunk, offset by the chunk's prefix.
+__global__ __launch_bounds__(kBlock) void scan_chunks_kernel(int* a, int64_t n, const int* __restrict__ sums)
+{
+    __shared__ int tmp[kBlock];
+    constexpr int per = kScanChunk / kBlock;  // consecutive elements per thread
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * per;
+    int loc[per];
+    int s = 0;
+    for (int q = 0; q < per; ++q) {
+        loc[q] = base + q < n ? a[base + q] : 0;
+        s += loc[q];
+    }
+    int total;
+    int ex = block_exclusive_scan(s, tmp, total) + sums[blockIdx.x];
+    for (int q = 0; q < per; ++q) {
+        if (base + q < n) a[base + q] = ex;
+        ex += loc[q];
+    }
+}
+
+// Stable scatter of one tile. Items are visited in rounds of 256 consecutive
+// keys (round-major, thread-minor = input order). Within a round, lanes of a
+// wave with equal digits are matched by 8 ballots; a lane's rank is the number
+// of matching lower lanes plus the counts of earlier waves, plus the digit's
+// running offset from earlier rounds and from earlier tiles (the scan).
+__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const int32_t* __restrict__ keys_in,
+                                                               const int32_t* __restrict__ pay_in,
+                                                               int32_t* __restrict__ keys_out,
+                                                               int32_t* __restrict__ pay_out, int64_t n,
+                                                               int shift, const int* __restrict__ offsets,
+                                                               int ntiles)
+{
+    constexpr int kWaves = kBlock / 64;
+    __shared__ int run[kRadix];
+    __shared__ int wcnt[kWaves][kRadix];
+    const int t = threadIdx.x;
+    const int wave = t >> 6;
+    const int lane = t & 63;
+    run[t] = offsets[(int64_t)t * ntiles + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int q = 0; q < kSortRounds; ++q) {
+        const int64_t e = base + q * kBlock + t;
+        const bool valid = e < n;
+        int32_t key = valid ? keys_in[e] : 0;
+        int32_t pay = valid ? (pay_in ? pay_in[e] : (int32_t)e) : 0;
+        const int d = (key >> shift) & (kRadix - 1);
+        for (int w = 0; w < kWaves; ++w) wcnt[w][t] = 0;
+        __syncthreads();
+        unsigned long long match = __ballot(valid);
+        for (int b = 0; b < kRadixBits; ++b) {
+            unsigned long long ones = __ballot((d >> b) & 1);
+            match &= ((d >> b) & 1) ? ones : ~ones;
+        }
+        const int rank = __popcll(match & below);
+        if (valid && rank == 0) wcnt[wave][d] = __popcll(match);
+        __syncthreads();
+        if (valid) {
+            int64_t pos = (int64_t)run[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            if (pos >= 0 && pos < n) {  // always true when the histogram scan is consistent
+                keys_out[pos] = key;
+                pay_out[pos] = pay;
+            }
+        }
+        __syncthreads();
+        int add = 0;
+        for (int w = 0; w < kWaves; ++w) add += wcnt[w][t];
+        run[t] += add;
+        __syncthreads();
+    }
+}
+
+// Copy sorted keys to the row array and gather values and the other modes'
+// coordinates through the permutation (perm == nullptr: identity).
+__global__ __launch_bounds__(kBlock) void gather_sorted_kernel(
+    const int32_t* __restrict__ idx, const double* __restrict__ vals, int64_t nnz, int N, int mode,
+    const int32_t* __restrict__ perm, int32_t* __restrict__ rows, int32_t* __restrict__ cidx,
+    double* __restrict__ svals)
+{
+    for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * kBlock) {
+        int64_t k = perm ? perm[p] : p;
+        if (k < 0 || k >= nnz) k = p;  // a permutation never leaves [0, nnz); keeps reads in bounds
+        rows[p] = idx[(int64_t)mode * nnz + k];
+        svals[p] = vals[k];
+        int j = 0;
+        for (int m = 0; m < N; ++m) {
+            if (m == mode) continue;
+            cidx[(int64_t)j * nnz + p] = idx[(int64_t)m * nnz + k];
+            ++j;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void count_segments_kernel(const int32_t* __restrict__ rows, int64_t nnz,
+                                                                unsigned long long* out)
+{
+    unsigned long long c = 0;
+    for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * kBlock)
+        c += (p == 0 || rows[p] != rows[p - 1]) ? 1 : 0;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+int grid_for(int64_t n)
+{
+    int64_t g = cdiv(n, kBlock);
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+Error exclusive_scan(int* a, int64_t n, int* sums, hipStream_t s)
+{
+    const int nchunks = (int)cdiv(n, kScanChunk);
+    scan_reduce_kernel<<<nchunks, kBlock, 0, s>>>(a, n, sums);
+    CPAPR_LAUNCHED();
+    scan_sums_kernel<<<1, kBlock, 0, s>>>(sums, nchunks);
+    CPAPR_LAUNCHED();
+    scan_chunks_kernel<<<nchunks, kBlock, 0, s>>>(a, n, sums);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+}  // namespace
+
+int64_t sort_scratch_bytes(int64_t nnz)
+{
+    const int64_t ntiles = cdiv(nnz > 0 ? nnz : 1, kSortTile);
+    const int64_t ncounts = ntiles * kRadix;
+    size_t b = 0;
+    b += 4 * align256((size_t)nnz * 4);                     // keys/payload ping-pong
+    b += align256((size_t)ncounts * 4);                     // histogram table
+    b += align256((size_t)cdiv(ncounts, kScanChunk) * 4 + 4);  // scan chunk sums
+    b += 256;                                                // flags / counters
+    return (int64_t)b;
+}
+
+Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t s)
+{
+    const int64_t nnz = P->nnz;
+    const int N = P->N;
+    const int64_t ntiles = cdiv(nnz > 0 ? nnz : 1, kSortTile);
+    const int64_t ncounts = ntiles * kRadix;
+    char* q = scratch;
+    auto take = [&](size_t bytes) {
+        char* r = q;
+        q += align256(bytes);
+        return r;
+    };
+    int32_t* ka = (int32_t*)take((size_t)nnz * 4);
+    int32_t* kb = (int32_t*)take((size_t)nnz * 4);
+    int32_t* pa = (int32_t*)take((size_t)nnz * 4);
+    int32_t* pb = (int32_t*)take((size_t)nnz * 4);
+    int* counts = (int*)take((size_t)ncounts * 4);
+    int* sums = (int*)take((size_t)cdiv(ncounts, kScanChunk) * 4 + 4);
+    int* flags = (int*)take(256);
+    unsigned long long* segc = (unsigned long long*)(flags + 8);
+
+    // flags and segment counters start at zero (plain kernel-free path: a tiny fill)
+    CPAPR_HIP(hipMemsetAsync(flags, 0, 256, s));
+    if (nnz > 0) {
+        DimsArg d{};
+        for (int m = 0; m < N; ++m) d.d[m] = P->dims[m];
+        validate_kernel<<<grid_for(nnz), kBlock, 0, s>>>(X->idx, X->vals, nnz, N, d, flags);
+        CPAPR_LAUNCHED();
+    }
+    int hflags = 0;
+    CPAPR_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    CPAPR_HIP(hipStreamSynchronize(s));
+    if (hflags & 1) return {CPAPR_EINDEX, "a coordinate lies outside its mode's range"};
+    if (hflags & 2) return {CPAPR_EVALUE, "a tensor value is not finite and positive"};
+
+    for (int n = 0; n < N; ++n) {
+        PlanMode& pm = P->mode[n];
+        if (nnz == 0) {
+            pm.segments = 0;
+            continue;
+        }
+        int bits = 0;
+        while (bits < 31 && ((int64_t)1 << bits) < P->dims[n]) ++bits;
+        const int passes = (bits + kRadixBits - 1) / kRadixBits;
+        const int32_t* kin = X->idx + (int64_t)n * nnz;
+        const int32_t* pin = nullptr;  // identity payload on the first pass
+        int32_t *kout = ka, *pout = pa;
+        for (int ps = 0; ps < passes; ++ps) {
+            const int shift = ps * kRadixBits;
+            radix_hist_kernel<<<(int)ntiles, kBlock, 0, s>>>(kin, nnz, shift, counts, (int)ntiles);
+            CPAPR_LAUNCHED();
+            Error e = exclusive_scan(counts, ncounts, sums, s);
+            if (e.code) return e;
+            radix_scatter_kernel<<<(int)ntiles, kBlock, 0, s>>>(kin, pin, kout, pout, nnz, shift, counts,
+                                                                (int)ntiles);
+            CPAPR_LAUNCHED();
+            kin = kout;
+            pin = pout;
+            kout = (kout == ka) ? kb : ka;
+            pout = (pout == pa) ? pb : pa;
+        }
+        gather_sorted_kernel<<<grid_for(nnz), kBlock, 0, s>>>(X->idx, X->vals, nnz, N, n, pin, pm.rows, pm.cidx,
+                                                              pm.vals);
+        CPAPR_LAUNCHED();
+        count_segments_kernel<<<grid_for(nnz), kBlock, 0, s>>>(pm.rows, nnz, segc + n);
+        CPAPR_LAUNCHED();
+    }
+    unsigned long long hseg[CPAPR_MAX_MODES] = {};
+    CPAPR_HIP(hipMemcpyAsync(hseg, segc, sizeof(unsigned long long) * N, hipMemcpyDeviceToHost, s));
+    CPAPR_HIP(hipStreamSynchronize(s));
+    for (int n = 0; n < N; ++n) P->mode[n].segments = (int64_t)hseg[n];
+    return {CPAPR_OK, ""};
+}
+
+}  // namespace cpapr

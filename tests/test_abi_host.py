@@ -1,0 +1,114 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function that
+include/cpapr.h declares, and rejects bad arguments on the host before any
+device work (no compute calls are made here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2307_03276_amd import cpapr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cpapr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cpapr_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(cpapr.LIB_PATH):
+        from paper_2307_03276_amd import build
+        build.build()
+    return cpapr.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert "cpapr_phi" in names and "cpapr_mu_inner" in names and "cpapr_solve" in names
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in cpapr.h but not exported"
+    assert set(names) == set(cpapr.EXPORTED)
+
+
+def test_params_default(lib):
+    p = cpapr.cpapr_params_default()
+    assert (p.kmax, p.lmax, p.tol, p.eps, p.kappa, p.kappa_tol) == (10, 10, 1e-4, 1e-10, 0.01, 1e-10)
+    assert p.precision == cpapr.CPAPR_FP64 and p.variant == 0 and p.group == 0 and p.chunk == 0
+
+
+def _coo(dims, nnz):
+    d = (C.c_int64 * len(dims))(*dims)
+    c = cpapr.cpapr_coo(len(dims), C.cast(d, C.POINTER(C.c_int64)), nnz, None, None)
+    c._keep = d
+    return c
+
+
+def _size(coo, R, p):
+    n = C.c_size_t(0)
+    return cpapr.load().cpapr_plan_workspace_size(C.byref(coo), R, C.byref(p), C.byref(n)), n.value
+
+
+def test_workspace_size_grows_with_problem(lib):
+    p = cpapr.cpapr_params_default()
+    rc, a = _size(_coo([100, 80, 60], 10_000), 10, p)
+    assert rc == 0 and a > 0
+    rc, b = _size(_coo([100, 80, 60], 20_000), 10, p)
+    assert rc == 0 and b > a
+    # three sorted copies of (3 x int32 + fp64) per nonzero at least
+    assert b >= 3 * 20_000 * (3 * 4 + 8)
+    pm = cpapr.cpapr_params_default(precision=cpapr.CPAPR_MIXED)
+    rc, c = _size(_coo([100, 80, 60], 20_000), 10, pm)
+    assert rc == 0 and c > b  # FP32 factor copies
+
+
+@pytest.mark.parametrize("dims,nnz,R,field,val,code", [
+    ([100], 10, 4, None, None, -1),                       # one mode
+    ([5] * 9, 10, 4, None, None, -1),                     # nine modes
+    ([0, 4, 5], 10, 4, None, None, -6),                   # empty mode
+    ([4, 5, 6], -1, 4, None, None, -1),                   # negative nnz
+    ([4, 5, 6], 2 ** 31, 4, None, None, -6),              # nnz too large
+    ([4, 5, 6], 10, 0, None, None, -6),                   # rank 0
+    ([4, 5, 6], 10, 257, None, None, -6),                 # rank too large
+    ([4, 5, 6], 10, 4, "lmax", 0, -1),
+    ([4, 5, 6], 10, 4, "lmax", 5000, -1),
+    ([4, 5, 6], 10, 4, "kmax", 0, -1),
+    ([4, 5, 6], 10, 4, "eps", 0.0, -1),
+    ([4, 5, 6], 10, 4, "precision", 7, -1),
+    ([4, 5, 6], 10, 4, "group", 12, -1),
+    ([4, 5, 6], 10, 40, "group", 8, -6),                  # R > 4 * group
+    ([4, 5, 6], 10, 4, "variant", 9, -1),
+])
+def test_workspace_size_rejects(lib, dims, nnz, R, field, val, code):
+    p = cpapr.cpapr_params_default()
+    if field:
+        setattr(p, field, val)
+    rc, _ = _size(_coo(dims, nnz), R, p)
+    assert rc == code
+    assert cpapr.cpapr_last_error()
+
+
+def test_plan_create_host_checks(lib):
+    p = cpapr.cpapr_params_default()
+    coo = _coo([4, 5, 6], 10)
+    h = C.c_void_p()
+    # idx / vals NULL with nnz > 0
+    assert lib.cpapr_plan_create(C.byref(coo), 4, C.byref(p), None, 0, None, C.byref(h)) == -1
+    coo0 = _coo([4, 5, 6], 0)
+    assert lib.cpapr_plan_create(C.byref(coo0), 4, C.byref(p), None, 0, None, C.byref(h)) == -4
+    assert lib.cpapr_plan_create(C.byref(coo0), 4, C.byref(p), 0x1001, 1 << 20, None, C.byref(h)) == -4
+    assert lib.cpapr_plan_create(C.byref(coo0), 4, C.byref(p), 0x1000, 16, None, C.byref(h)) == -4
+    assert "small" in cpapr.cpapr_last_error()
+
+
+def test_calls_reject_null_plan(lib):
+    arr = (C.c_void_p * 3)()
+    assert lib.cpapr_phi(None, 0, None, arr, 1e-10, None, None) == -1
+    assert lib.cpapr_mu_inner(None, 0, None, arr, None, None, None) == -1
+    assert lib.cpapr_solve(None, None, arr, None, None) == -1
+    assert lib.cpapr_loglik(None, None, arr, 1e-10, None, None) == -1
+    assert lib.cpapr_mttkrp(None, 0, arr, None, None) == -1
+    assert lib.cpapr_plan_segments(None, 0) == -1

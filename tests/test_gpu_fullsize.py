@@ -1,0 +1,70 @@
+"""Parity at full benchmark size (3-way 200k x 150k x 20k, 20M Zipf(1.1)
+nonzeros, R = 16) in the launch configuration the benchmark times.
+
+The oracle computes sampled rows one by one (Phi rows and, because the inner
+loop is row-separable under a fixed schedule, inner-loop rows); the mass
+identity sum(B .* Phi) = sum(x) checks every row at once."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_03276_amd import cpapr, synth
+from tests.gpu_util import assert_parity, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def big():
+    import torch
+    assert torch.cuda.is_available()
+    oracle.build(force=False)
+    X, M, sched = synth.config_zipf3()
+    return X, M, sched
+
+
+def _sample_rows(X, n, rng, k_random=24):
+    counts = np.bincount(X.idx[n], minlength=X.dims[n])
+    heavy = np.argsort(counts)[-6:]
+    nonempty = np.flatnonzero(counts)
+    empty = np.flatnonzero(counts == 0)
+    pick = [heavy, rng.choice(nonempty, size=k_random, replace=False)]
+    if empty.size:
+        pick.append(rng.choice(empty, size=min(4, empty.size), replace=False))
+    return np.unique(np.concatenate(pick)), counts
+
+
+@pytest.mark.parametrize("precision,tol", [(cpapr.CPAPR_FP64, 1e-12), (cpapr.CPAPR_MIXED, 1e-5)])
+def test_phi_fullsize_sampled_rows_and_mass(big, precision, tol):
+    X, M, sched = big
+    P = cpapr.Plan.from_tensor(X, M.rank, precision=precision, lmax=sched["lmax"], tol=0.0)
+    A = [dev(a) for a in M.factors]
+    rng = np.random.default_rng(0)
+    total = X.vals.sum()
+    for n in range(3):
+        Bh = M.factors[n] * M.lam
+        got = host(P.phi(n, dev(Bh), A))
+        rows, counts = _sample_rows(X, n, rng)
+        ref = oracle.phi(X, n, Bh, M.factors, rows=rows)
+        assert_parity(got[rows], ref[rows], tol, f"mode {n} sampled rows")
+        mass = float(np.sum(Bh * got))
+        assert abs(mass - total) <= tol * total, f"mode {n} mass {mass} vs {total}"
+        assert np.all(got[counts == 0] == 0)
+    P.close()
+
+
+def test_mu_inner_fullsize_sampled_rows(big):
+    X, M, sched = big
+    P = cpapr.Plan.from_tensor(X, M.rank, lmax=sched["lmax"], tol=0.0)
+    A = [dev(a) for a in M.factors]
+    rng = np.random.default_rng(1)
+    n = 0
+    Bh = M.factors[n] * M.lam
+    B = dev(Bh)
+    phi_last, st = P.mu_inner(n, B, A)
+    assert st["inner_iters"] == sched["lmax"]
+    rows, _ = _sample_rows(X, n, rng, k_random=12)
+    Bo, Po, _, _ = oracle.mu_inner(X, n, Bh, M.factors, lmax=sched["lmax"], rows=rows)
+    assert_parity(host(B)[rows], Bo[rows], 1e-12, "B rows")
+    assert_parity(host(phi_last)[rows], Po[rows], 1e-12, "Phi rows")
+    P.close()
