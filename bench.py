@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--nnz", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-phi", action="store_true",
+                    help="counter-collection driver: two Phi launches per mode on the benchmark tensor, "
+                         "then a 1 GiB device copy that calibrates the byte counters; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -103,6 +106,21 @@ def main():
     coo = cpapr.make_coo(X.dims, idx, vals)
     ws = torch.empty(cpapr.cpapr_plan_workspace_size(coo, R, params), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
+
+    if args.profile_phi:
+        h = cpapr.cpapr_plan_create(coo, R, params, ws, stream)
+        phi = torch.empty((max(X.dims), R), dtype=torch.float64, device=dev)
+        for n in range(N):
+            B = (A0[n] * lam0).contiguous()
+            for _ in range(2):
+                cpapr.cpapr_phi(h, n, B, A0, sched["eps"], phi, stream)
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        cpapr.cpapr_plan_destroy(h)
+        print("profile-phi done", flush=True)
+        return
 
     def step():
         h = cpapr.cpapr_plan_create(coo, R, params, ws, stream)

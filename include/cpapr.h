@@ -116,6 +116,13 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
                       size_t ws_bytes, void* stream, cpapr_plan** out);
 int cpapr_plan_destroy(cpapr_plan* plan);
 
+/* Change the Phi launch shape of an existing plan (lanes per nonzero `group`:
+ * 0 = by rank, else 4, 8, 16, 32 or 64; nonzeros per lane group per tile
+ * `chunk`: 0 = default, else 1..65536). Host-only; used by the autotuner to
+ * time shapes without re-sorting. Returns CPAPR_EUNSUPPORTED for shapes with
+ * no kernel at this rank and mode count. */
+int cpapr_plan_set_shape(cpapr_plan* plan, int32_t group, int32_t chunk);
+
 /* Number of nonempty rows (segments) of mode `mode` (host query). */
 int64_t cpapr_plan_segments(const cpapr_plan* plan, int32_t mode);
 

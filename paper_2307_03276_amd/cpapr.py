@@ -71,6 +71,7 @@ def load():
         "cpapr_plan_create": (C.c_int, [P(cpapr_coo), i32, P(cpapr_params), vp, C.c_size_t, vp, P(vp)]),
         "cpapr_plan_destroy": (C.c_int, [vp]),
         "cpapr_plan_segments": (i64, [vp, i32]),
+        "cpapr_plan_set_shape": (C.c_int, [vp, i32, i32]),
         "cpapr_phi": (C.c_int, [vp, i32, vp, P(vp), dbl, vp, vp]),
         "cpapr_mu_inner": (C.c_int, [vp, i32, vp, P(vp), vp, P(cpapr_stats), vp]),
         "cpapr_solve": (C.c_int, [vp, vp, P(vp), P(cpapr_stats), vp]),
@@ -90,7 +91,7 @@ def load():
 
 
 EXPORTED = ("cpapr_params_default", "cpapr_plan_workspace_size", "cpapr_plan_create", "cpapr_plan_destroy",
-            "cpapr_plan_segments", "cpapr_phi", "cpapr_mu_inner", "cpapr_solve", "cpapr_loglik",
+            "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_phi", "cpapr_mu_inner", "cpapr_solve", "cpapr_loglik",
             "cpapr_mttkrp", "cpapr_prof_enable", "cpapr_prof_disable", "cpapr_prof_read",
             "cpapr_last_error")
 
@@ -159,6 +160,10 @@ def cpapr_plan_create(coo, R, params, ws, stream=None):
 
 def cpapr_plan_destroy(h):
     return _check(load().cpapr_plan_destroy(h))
+
+
+def cpapr_plan_set_shape(h, group: int, chunk: int):
+    return _check(load().cpapr_plan_set_shape(h, group, chunk))
 
 
 def cpapr_plan_segments(h, mode: int) -> int:
@@ -231,6 +236,10 @@ class Plan:
         idx = torch.from_numpy(X.idx).to(device)
         vals = torch.from_numpy(X.vals).to(device)
         return cls(X.dims, idx, vals, R, **kw)
+
+    def set_shape(self, group, chunk):
+        cpapr_plan_set_shape(self.handle, group, chunk)
+        self.params.group, self.params.chunk = group, chunk
 
     def segments(self, mode):
         return cpapr_plan_segments(self.handle, mode)

@@ -52,7 +52,7 @@ Error check_coo(const cpapr_coo* X, int32_t R, bool need_data)
     return {CPAPR_OK, ""};
 }
 
-Error check_params(const cpapr_params* p, int32_t R)
+Error check_params(const cpapr_params* p, int32_t R, int nmodes)
 {
     if (!p) return {CPAPR_EINVAL, "params is NULL"};
     if (p->kmax < 1) return {CPAPR_EINVAL, "kmax must be >= 1"};
@@ -63,9 +63,11 @@ Error check_params(const cpapr_params* p, int32_t R)
     if (p->variant < CPAPR_VARIANT_AUTO || p->variant > CPAPR_VARIANT_ATOMIC) return {CPAPR_EINVAL, "unknown variant"};
     if (p->variant == CPAPR_VARIANT_ATOMIC && p->precision == CPAPR_MIXED)
         return {CPAPR_EUNSUPPORTED, "the atomic variant is FP64 only"};
-    const int g = cpapr::resolve_group(R, p->group);
+    const int g = cpapr::resolve_group(R, p->group, nmodes - 1);
     if (g != 4 && g != 8 && g != 16 && g != 32 && g != 64) return {CPAPR_EINVAL, "group must be 0, 4, 8, 16, 32 or 64"};
     if (cpapr::rank_block(R, g) < 0) return {CPAPR_EUNSUPPORTED, "rank too large for this lane group (R > 4 * group)"};
+    if (!cpapr::phi_shape_supported(g, cpapr::rank_block(R, g), nmodes - 1))
+        return {CPAPR_EUNSUPPORTED, "no Phi kernel for this lane group and rank block at this mode count"};
     if (p->chunk < 0 || p->chunk > 65536) return {CPAPR_EINVAL, "chunk must be in [0, 65536]"};
     return {CPAPR_OK, ""};
 }
@@ -78,7 +80,7 @@ struct Layout {
     size_t mode_rows[CPAPR_MAX_MODES], mode_cidx[CPAPR_MAX_MODES], mode_vals[CPAPR_MAX_MODES];
     size_t f32[CPAPR_MAX_MODES];
     size_t region2;
-    size_t B, phi_prev[CPAPR_MAX_MODES], partial, colsums, state;
+    size_t B, phi_prev[CPAPR_MAX_MODES], partial, llpart, colsums, state;
     size_t total;
 };
 
@@ -110,6 +112,8 @@ Layout layout(int N, int64_t nnz, const int64_t* dims, int R, bool mixed)
     }
     L.partial = off + s;
     s += align256((size_t)cpapr::kPartials * R * 8);
+    L.llpart = off + s;
+    s += align256((size_t)cpapr::kLLBlocks * 8);
     L.colsums = off + s;
     s += align256((size_t)N * R * 8);
     L.state = off + s;
@@ -239,7 +243,7 @@ int cpapr_plan_workspace_size(const cpapr_coo* X, int32_t R, const cpapr_params*
     try {
         Error e = check_coo(X, R, false);
         if (e.code) return report(e);
-        e = check_params(p, R);
+        e = check_params(p, R, X->nmodes);
         if (e.code) return report(e);
         if (!bytes) return fail(CPAPR_EINVAL, "bytes is NULL");
         *bytes = layout(X->nmodes, X->nnz, X->dims, R, p->precision == CPAPR_MIXED).total;
@@ -257,7 +261,7 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
         *out = nullptr;
         Error e = check_coo(X, R, true);
         if (e.code) return report(e);
-        e = check_params(p, R);
+        e = check_params(p, R, X->nmodes);
         if (e.code) return report(e);
         const bool mixed = p->precision == CPAPR_MIXED;
         const Layout L = layout(X->nmodes, X->nnz, X->dims, R, mixed);
@@ -275,7 +279,7 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
         P->params = *p;
         P->ws = w;
         P->ws_bytes = ws_bytes;
-        P->group = cpapr::resolve_group(R, p->group);
+        P->group = cpapr::resolve_group(R, p->group, X->nmodes - 1);
         P->chunk = cpapr::resolve_chunk(P->group, p->chunk);
         for (int n = 0; n < P->N; ++n) {
             P->mode[n].rows = (int32_t*)(w + L.mode_rows[n]);
@@ -286,6 +290,7 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
         }
         P->B = (double*)(w + L.B);
         P->partial = (double*)(w + L.partial);
+        P->llpart = (double*)(w + L.llpart);
         P->colsums = (double*)(w + L.colsums);
         P->state = (cpapr::DevState*)(w + L.state);
 
@@ -295,7 +300,7 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
             delete P;
             return report(e);
         }
-        e = cpapr::launch_reset_state(P->state, P->params.lmax, true, true, s);
+        e = cpapr::launch_reset_state(P->state, true, true, s);
         if (e.code) {
             delete P;
             return report(e);
@@ -314,6 +319,20 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
 int cpapr_plan_destroy(cpapr_plan* plan)
 {
     delete plan;
+    return CPAPR_OK;
+}
+
+int cpapr_plan_set_shape(cpapr_plan* plan, int32_t group, int32_t chunk)
+{
+    if (!plan) return fail(CPAPR_EINVAL, "plan is NULL");
+    cpapr_params p = plan->params;
+    p.group = group;
+    p.chunk = chunk;
+    Error e = check_params(&p, plan->R, plan->N);
+    if (e.code) return report(e);
+    plan->params = p;
+    plan->group = cpapr::resolve_group(plan->R, group, plan->N - 1);
+    plan->chunk = cpapr::resolve_chunk(plan->group, chunk);
     return CPAPR_OK;
 }
 
@@ -359,7 +378,7 @@ int cpapr_mu_inner(cpapr_plan* plan, int32_t mode, double* B, const double* cons
         const void* fac[CPAPR_MAX_MODES];
         e = phi_factors(plan, mode, A, fac, s);
         if (e.code) return report(e);
-        e = cpapr::launch_reset_state(plan->state, plan->params.lmax, true, true, s);
+        e = cpapr::launch_reset_state(plan->state, true, true, s);
         if (e.code) return report(e);
         e = enqueue_inner(plan, mode, B, fac, Phi_last, s);
         if (e.code) return report(e);
@@ -401,13 +420,13 @@ int cpapr_solve(cpapr_plan* plan, double* lambda, double* const* A, cpapr_stats*
                 fac[m] = A[m];
             }
         }
-        e = cpapr::launch_reset_state(P->state, P->params.lmax, true, true, s);
+        e = cpapr::launch_reset_state(P->state, true, true, s);
         if (e.code) return report(e);
         int k = 1, converged = 0;
         for (; k <= P->params.kmax; ++k) {
             for (int n = 0; n < N; ++n) {
                 const int64_t In = P->dims[n];
-                e = cpapr::launch_reset_state(P->state, P->params.lmax, n == 0, false, s);
+                e = cpapr::launch_reset_state(P->state, n == 0, false, s);
                 if (e.code) return report(e);
                 e = cpapr::launch_shift_scale(A[n], P->phi_prev[n], lambda, P->B, In, R, P->params.kappa,
                                               P->params.kappa_tol, k > 1, s);

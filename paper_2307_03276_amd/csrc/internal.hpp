@@ -18,15 +18,22 @@ struct Error {
     std::string msg;
 };
 
+// Slots of the KKT max-reduction: blocks spread their atomics over kViolSlots
+// addresses, one per 128-byte line, because same-address device atomics
+// serialise; consumers take the max over the slots.
+constexpr int kViolSlots = 64;
+constexpr int kViolStride = 16;  // u64 words per slot (128 bytes)
+
 // Device-side state block of one inner loop (lives in the plan workspace).
 struct DevState {
-    unsigned long long viol[CPAPR_MAX_LMAX];  // bit patterns of nonnegative doubles (max via u64)
-    double last_viol[CPAPR_MAX_MODES];        // last KKT violation seen per mode
-    int done;                                 // inner loop of the current mode has stopped
-    int updates;                              // MU updates in the current inner loop
-    int sweep_updates;                        // MU updates in the current outer sweep
-    long long total_updates;                  // MU updates since the last reset
-    double ll;                                // log-likelihood result
+    unsigned long long viol[2][kViolSlots * kViolStride];  // per-parity slots, ordered bits of doubles >= 0
+    double last_viol[CPAPR_MAX_MODES];                      // last KKT violation seen per mode
+    int done;                                               // inner loop of the current mode has stopped
+    int updates;                                            // MU updates in the current inner loop
+    int sweep_updates;                                      // MU updates in the current outer sweep
+    int pad;
+    long long total_updates;                                // MU updates since the last reset
+    double ll;                                              // log-likelihood result
 };
 
 struct PlanMode {
@@ -49,6 +56,7 @@ struct cpapr_plan {
     double* B;                        // [maxI x R] solve work matrix
     double* phi_prev[CPAPR_MAX_MODES];  // [I_m x R] last Phi per mode (solve)
     double* partial;                  // [kPartials x R] column-sum / reduction partials
+    double* llpart;                   // [kLLBlocks] log-likelihood partials
     double* colsums;                  // [N x R]
     cpapr::DevState* state;
     char* ws;
@@ -58,7 +66,8 @@ struct cpapr_plan {
 
 namespace cpapr {
 
-constexpr int kPartials = 512;  // blocks of the two-level deterministic reductions
+constexpr int kPartials = 512;   // blocks of the two-level deterministic column sums
+constexpr int kLLBlocks = 4096;  // blocks of the log-likelihood pass
 
 // ---- plan construction (sort.hip) ----
 int64_t sort_scratch_bytes(int64_t nnz);
@@ -66,8 +75,10 @@ int64_t sort_scratch_bytes(int64_t nnz);
 Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t s);
 
 // ---- Phi (phi.hip) ----
+// Whether a Phi kernel exists for this lane group, rank block and mode count.
+bool phi_shape_supported(int group, int rpl, int nmodes_other);
 // Resolve the lane-group size for rank R (the `group` parameter, 0 = automatic).
-int resolve_group(int R, int requested);
+int resolve_group(int R, int requested, int nm1);
 int resolve_chunk(int group, int requested);
 // Rank columns per lane (1, 2 or 4) for rank R on `group` lanes; -1 if R > 4 * group.
 int rank_block(int R, int group);
@@ -78,7 +89,7 @@ Error launch_mttkrp(const cpapr_plan* P, int mode, const double* const* A, doubl
 // ---- elementwise and reduction kernels (mu.hip) ----
 Error launch_fill(double* p, int64_t n, double v, const int* done, hipStream_t s);
 Error launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
-Error launch_reset_state(DevState* st, int lmax, bool new_sweep, bool all, hipStream_t s);
+Error launch_reset_state(DevState* st, bool new_sweep, bool all, hipStream_t s);
 Error launch_kkt(const double* B, const double* Phi, int64_t n, DevState* st, int l, hipStream_t s);
 Error launch_mu_update(double* B, const double* Phi, int64_t n, DevState* st, int l, int mode, double tol,
                        hipStream_t s);

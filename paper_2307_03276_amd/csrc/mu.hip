@@ -40,9 +40,9 @@ __global__ __launch_bounds__(kBlock) void to_f32_kernel(const double* __restrict
         dst[i] = (float)src[i];
 }
 
-__global__ __launch_bounds__(kBlock) void reset_state_kernel(DevState* st, int lmax, int new_sweep, int all)
+__global__ __launch_bounds__(kBlock) void reset_state_kernel(DevState* st, int new_sweep, int all)
 {
-    for (int l = threadIdx.x; l < lmax; l += kBlock) st->viol[l] = 0ull;
+    for (int i = threadIdx.x; i < 2 * kViolSlots * kViolStride; i += kBlock) (&st->viol[0][0])[i] = 0ull;
     if (threadIdx.x == 0) {
         st->done = 0;
         st->updates = 0;
@@ -60,8 +60,8 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// viol[l] = max over entries of |min(B, 1 - Phi)|, as the ordered bit pattern
-// of a nonnegative double.
+// Max over entries of |min(B, 1 - Phi)|, folded into the slots of parity l & 1
+// (ordered bit patterns of nonnegative doubles, so u64 max is double max).
 __global__ __launch_bounds__(kBlock) void kkt_kernel(const double* __restrict__ B, const double* __restrict__ Phi,
                                                      int64_t n, DevState* st, int l)
 {
@@ -78,27 +78,39 @@ __global__ __launch_bounds__(kBlock) void kkt_kernel(const double* __restrict__ 
     if (threadIdx.x == 0) {
         double m = red[0];
         for (int w = 1; w < kBlock / 64; ++w) m = fmax(m, red[w]);
-        atomicMax(&st->viol[l], (unsigned long long)__double_as_longlong(m));
+        const int slot = blockIdx.x % kViolSlots;
+        atomicMax(&st->viol[l & 1][slot * kViolStride], (unsigned long long)__double_as_longlong(m));
     }
 }
 
-// B <- B .* Phi unless the KKT test says stop. Only block 0 records the
-// violation and raises `done`; other blocks of this launch that see `done`
-// early skip work they would have skipped anyway.
+// B <- B .* Phi unless the KKT test says stop. Every block folds the slots to
+// the same violation; only block 0 records it, raises `done` and clears the
+// other parity's slots for the next iteration. Other blocks of this launch
+// that see `done` early skip work they would have skipped anyway.
 __global__ __launch_bounds__(kBlock) void mu_update_kernel(double* __restrict__ B, const double* __restrict__ Phi,
                                                            int64_t n, DevState* st, int l, int mode, double tol)
 {
     if (st->done) return;
-    const double viol = __longlong_as_double((long long)st->viol[l]);
+    __shared__ double viol_sh;
+    if (threadIdx.x < 64) {
+        double v = __longlong_as_double((long long)st->viol[l & 1][threadIdx.x * kViolStride]);
+        v = wave_max(v);
+        if (threadIdx.x == 0) viol_sh = v;
+    }
+    __syncthreads();
+    const double viol = viol_sh;
     const bool stop = tol > 0.0 && viol < tol;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->last_viol[mode] = viol;
-        if (stop) {
-            st->done = 1;
-        } else {
-            st->updates += 1;
-            st->sweep_updates += 1;
-            st->total_updates += 1;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < kViolSlots) st->viol[(l + 1) & 1][threadIdx.x * kViolStride] = 0ull;
+        if (threadIdx.x == 0) {
+            st->last_viol[mode] = viol;
+            if (stop) {
+                st->done = 1;
+            } else {
+                st->updates += 1;
+                st->sweep_updates += 1;
+                st->total_updates += 1;
+            }
         }
     }
     if (stop) return;
@@ -147,13 +159,24 @@ __global__ __launch_bounds__(kBlock) void colsum_partial_kernel(const double* __
     }
 }
 
+// Column sums, level 2: Q = 256/R threads per column each sum a fixed stride of
+// the partials, then one thread per column adds the Q results in order.
 __global__ __launch_bounds__(kBlock) void colsum_final_kernel(const double* __restrict__ partial, int nparts, int R,
                                                               double* __restrict__ out)
 {
-    for (int c = threadIdx.x; c < R; c += kBlock) {
-        double s = 0.0;
-        for (int b = 0; b < nparts; ++b) s += partial[(int64_t)b * R + c];
-        out[c] = s;
+    __shared__ double sm[kBlock];
+    const int Q = kBlock / R;
+    const int t = threadIdx.x;
+    const int c = t % R, q = t / R;
+    double s = 0.0;
+    if (q < Q)
+        for (int b = q; b < nparts; b += Q) s += partial[(int64_t)b * R + c];
+    sm[t] = q < Q ? s : 0.0;
+    __syncthreads();
+    if (t < R) {
+        double tot = 0.0;
+        for (int qq = 0; qq < Q; ++qq) tot += sm[qq * R + t];
+        out[t] = tot;
     }
 }
 
@@ -211,12 +234,19 @@ __global__ __launch_bounds__(kBlock) void loglik_partial_kernel(LLArgs a)
     }
 }
 
-__global__ void loglik_final_kernel(const double* __restrict__ partial, int nparts, const double* __restrict__ lam,
-                                    const double* __restrict__ colsums, int N, int R, DevState* st)
+__global__ __launch_bounds__(kBlock) void loglik_final_kernel(const double* __restrict__ partial, int nparts,
+                                                              const double* __restrict__ lam,
+                                                              const double* __restrict__ colsums, int N, int R,
+                                                              DevState* st)
 {
+    __shared__ double sm[kBlock];
+    double part = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += kBlock) part += partial[b];
+    sm[threadIdx.x] = part;
+    __syncthreads();
     if (threadIdx.x != 0) return;
     double s = 0.0;
-    for (int b = 0; b < nparts; ++b) s += partial[b];
+    for (int q = 0; q < kBlock; ++q) s += sm[q];
     double mass = 0.0;
     for (int r = 0; r < R; ++r) {
         double p = lam[r];
@@ -244,9 +274,9 @@ Error launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s)
     return {CPAPR_OK, ""};
 }
 
-Error launch_reset_state(DevState* st, int lmax, bool new_sweep, bool all, hipStream_t s)
+Error launch_reset_state(DevState* st, bool new_sweep, bool all, hipStream_t s)
 {
-    reset_state_kernel<<<1, kBlock, 0, s>>>(st, lmax, new_sweep ? 1 : 0, all ? 1 : 0);
+    reset_state_kernel<<<1, kBlock, 0, s>>>(st, new_sweep ? 1 : 0, all ? 1 : 0);
     CPAPR_LAUNCHED();
     return {CPAPR_OK, ""};
 }
@@ -315,11 +345,11 @@ Error launch_loglik(const cpapr_plan* P, const double* lam, const double* const*
     a.R = R;
     a.NM1 = N - 1;
     a.eps = eps;
-    a.partial = P->partial;
-    const int nparts = kPartials;
+    a.partial = P->llpart;
+    const int nparts = kLLBlocks;
     loglik_partial_kernel<<<nparts, kBlock, 0, s>>>(a);
     CPAPR_LAUNCHED();
-    loglik_final_kernel<<<1, 64, 0, s>>>(P->partial, nparts, lam, P->colsums, N, R, P->state);
+    loglik_final_kernel<<<1, kBlock, 0, s>>>(P->llpart, nparts, lam, P->colsums, N, R, P->state);
     CPAPR_LAUNCHED();
     return {CPAPR_OK, ""};
 }

@@ -191,14 +191,36 @@ __device__ __forceinline__ T nonzero_scale(const T (&b)[RPL], const T (&pi)[RPL]
     }
 }
 
-template <int G, int RPL, bool MIXED, bool MTTKRP>
+// Staged nonzero: its row, the other modes' coordinates and its value. A lane
+// group loads G consecutive nonzeros cooperatively (coalesced) into its slice
+// of LDS and then reads them back one at a time as broadcasts.
+template <int NM1>
+struct alignas(8) Staged {
+    int row;
+    int c[NM1];
+    double x;
+};
+
+// Nonzeros whose factor rows are gathered before any of them is consumed, so
+// that U x NM1 gathers are in flight per lane group.
+template <int NM1, int RPL>
+constexpr int gather_depth()
+{
+    return NM1 * RPL <= 2 ? 4 : (NM1 * RPL <= 4 ? 2 : 1);
+}
+
+template <int G, int RPL, int NM1, bool MIXED, bool MTTKRP>
 __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
     constexpr int NG = kBlock / G;
     constexpr int W = G * RPL;
+    constexpr int U = gather_depth<NM1, RPL>();
+    constexpr int BATCH = G >= 8 ? G : 8;  // nonzeros staged per lane group per round
+    constexpr int EPL = BATCH / G;         // staged entries loaded by each lane
     __shared__ double part[2 * NG][W];
     __shared__ int prow[2 * NG];
+    __shared__ Staged<NM1> stage[NG * BATCH];
 
     if (a.done != nullptr && *a.done) return;
 
@@ -218,9 +240,16 @@ __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
         prow[2 * g + 1] = -1;
     }
 
+    // Lanes past the rank gather a clamped (in-row) column instead of being
+    // masked, so the hot loop carries no selects; their B entries are zero, so
+    // they add nothing to the dot product, and their accumulators are never stored.
     bool valid[RPL];
+    int col[RPL];
 #pragma unroll
-    for (int c = 0; c < RPL; ++c) valid[c] = lane * RPL + c < R;
+    for (int c = 0; c < RPL; ++c) {
+        valid[c] = lane * RPL + c < R;
+        col[c] = min(lane * RPL + c, R - 1);
+    }
 
     int cur = -1;
     int nseg = 0;
@@ -247,34 +276,88 @@ __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
         }
     };
 
-    for (int64_t p = p0; p < p1; ++p) {
-        const int row = a.rows[p];
-        const double x = a.vals[p];
-        T pi[RPL];
+    const T* fac[NM1];
 #pragma unroll
-        for (int c = 0; c < RPL; ++c) pi[c] = valid[c] ? (T)1 : (T)0;
-        for (int m = 0; m < a.NM1; ++m) {
-            const int32_t ci = a.cidx[(int64_t)m * nnz + p];
-            const T* f = (const T*)a.fac[m] + (int64_t)ci * R + lane * RPL;
+    for (int m = 0; m < NM1; ++m) fac[m] = (const T*)a.fac[m];
+    Staged<NM1>* my = stage + g * BATCH;
+
+    // Metadata of the next round is loaded into registers while the current
+    // round is processed (coalesced: lane j of the group takes entries j, j+G, ...).
+    Staged<NM1> pre[EPL];
+    auto load_meta = [&](int64_t base) {
 #pragma unroll
-            for (int c = 0; c < RPL; ++c)
-                if (valid[c]) pi[c] *= f[c];
-        }
-        if (row != cur) {
-            if (cur >= 0) flush(cur, nseg == 1 ? 0 : 2);
-            cur = row;
-            ++nseg;
+        for (int k = 0; k < EPL; ++k) {
+            const int64_t p = base + k * G + lane;
+            if (p < p1) {
+                pre[k].row = a.rows[p];
 #pragma unroll
-            for (int c = 0; c < RPL; ++c) acc[c].zero();
-            if constexpr (!MTTKRP) {
-                const double* brow = a.B + (int64_t)row * R + lane * RPL;
-#pragma unroll
-                for (int c = 0; c < RPL; ++c) b[c] = valid[c] ? (T)brow[c] : (T)0;
+                for (int m = 0; m < NM1; ++m) pre[k].c[m] = a.cidx[(int64_t)m * nnz + p];
+                pre[k].x = a.vals[p];
             }
         }
-        const T s = nonzero_scale<G, RPL, MIXED, MTTKRP, T>(b, pi, x, a.eps);
+    };
+    if (p0 < p1) load_meta(p0);
+
+    for (int64_t base = p0; base < p1; base += BATCH) {
+        const int cnt = (int)min((int64_t)BATCH, p1 - base);
 #pragma unroll
-        for (int c = 0; c < RPL; ++c) acc[c].add(s, pi[c]);
+        for (int k = 0; k < EPL; ++k)
+            if (k * G + lane < cnt) my[k * G + lane] = pre[k];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (base + BATCH < p1) load_meta(base + BATCH);
+
+        for (int q0 = 0; q0 < cnt; q0 += U) {
+            int rowu[U];
+            double xu[U];
+            T fu[U][NM1][RPL];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (q0 + u < cnt) {
+                    const Staged<NM1> e = my[q0 + u];
+                    rowu[u] = e.row;
+                    xu[u] = e.x;
+#pragma unroll
+                    for (int m = 0; m < NM1; ++m) {
+                        const T* f = fac[m] + (int64_t)e.c[m] * R;
+#pragma unroll
+                        for (int c = 0; c < RPL; ++c) fu[u][m][c] = f[col[c]];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (q0 + u < cnt) {
+                    const int row = rowu[u];
+                    T pi[RPL];
+#pragma unroll
+                    for (int c = 0; c < RPL; ++c) {
+                        pi[c] = fu[u][0][c];
+#pragma unroll
+                        for (int m = 1; m < NM1; ++m) pi[c] *= fu[u][m][c];
+                    }
+                    if (row != cur) {
+                        if (cur >= 0) flush(cur, nseg == 1 ? 0 : 2);
+                        cur = row;
+                        ++nseg;
+#pragma unroll
+                        for (int c = 0; c < RPL; ++c) acc[c].zero();
+                        if constexpr (!MTTKRP) {
+                            const double* brow = a.B + (int64_t)row * R;
+#pragma unroll
+                            for (int c = 0; c < RPL; ++c) b[c] = valid[c] ? (T)brow[col[c]] : (T)0;
+                        }
+                    }
+                    const T s = nonzero_scale<G, RPL, MIXED, MTTKRP, T>(b, pi, xu[u], a.eps);
+#pragma unroll
+                    for (int c = 0; c < RPL; ++c) acc[c].add(s, pi[c]);
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (cur >= 0) flush(cur, nseg == 1 ? 0 : 1);
     __syncthreads();
@@ -355,6 +438,36 @@ __global__ __launch_bounds__(kBlock) void zero_kernel(double* p, int64_t n)
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+template <int NM1, bool MIXED, bool MTTKRP>
+Error dispatch_seg_n(int G, int RPL, const PhiArgs& a, dim3 grid, hipStream_t s)
+{
+#define CPAPR_SEG_CASE(GG, RR)                                                        \
+    if (G == GG && RPL == RR) {                                                       \
+        phi_seg_kernel<GG, RR, NM1, MIXED, MTTKRP><<<grid, kBlock, 0, s>>>(a);        \
+        CPAPR_LAUNCHED();                                                             \
+        return {CPAPR_OK, ""};                                                        \
+    }
+    CPAPR_SEG_CASE(4, 1)
+    CPAPR_SEG_CASE(8, 1)
+    CPAPR_SEG_CASE(16, 1)
+    CPAPR_SEG_CASE(32, 1)
+    CPAPR_SEG_CASE(64, 1)
+    CPAPR_SEG_CASE(64, 2)
+    CPAPR_SEG_CASE(64, 4)
+    CPAPR_SEG_CASE(8, 2)
+    CPAPR_SEG_CASE(16, 2)
+    if constexpr (NM1 <= 3) {
+        CPAPR_SEG_CASE(4, 2)
+        CPAPR_SEG_CASE(4, 4)
+        CPAPR_SEG_CASE(8, 4)
+        CPAPR_SEG_CASE(16, 4)
+        CPAPR_SEG_CASE(32, 2)
+        CPAPR_SEG_CASE(32, 4)
+    }
+#undef CPAPR_SEG_CASE
+    return {CPAPR_EUNSUPPORTED, "no Phi kernel for this lane-group / rank-block shape and mode count"};
+}
+
 template <bool MIXED, bool MTTKRP>
 Error dispatch_seg(int G, int RPL, const PhiArgs& a, hipStream_t s)
 {
@@ -363,29 +476,16 @@ Error dispatch_seg(int G, int RPL, const PhiArgs& a, hipStream_t s)
     if (tiles <= 0) return {CPAPR_OK, ""};
     if (tiles > 0x7fffffff) return {CPAPR_EUNSUPPORTED, "too many tiles"};
     const dim3 grid((unsigned)tiles);
-#define CPAPR_SEG_CASE(GG, RR)                                                        \
-    if (G == GG && RPL == RR) {                                                       \
-        phi_seg_kernel<GG, RR, MIXED, MTTKRP><<<grid, kBlock, 0, s>>>(a);             \
-        CPAPR_LAUNCHED();                                                             \
-        return {CPAPR_OK, ""};                                                        \
+    switch (a.NM1) {
+        case 1: return dispatch_seg_n<1, MIXED, MTTKRP>(G, RPL, a, grid, s);
+        case 2: return dispatch_seg_n<2, MIXED, MTTKRP>(G, RPL, a, grid, s);
+        case 3: return dispatch_seg_n<3, MIXED, MTTKRP>(G, RPL, a, grid, s);
+        case 4: return dispatch_seg_n<4, MIXED, MTTKRP>(G, RPL, a, grid, s);
+        case 5: return dispatch_seg_n<5, MIXED, MTTKRP>(G, RPL, a, grid, s);
+        case 6: return dispatch_seg_n<6, MIXED, MTTKRP>(G, RPL, a, grid, s);
+        case 7: return dispatch_seg_n<7, MIXED, MTTKRP>(G, RPL, a, grid, s);
+        default: return {CPAPR_EUNSUPPORTED, "unsupported number of modes"};
     }
-    CPAPR_SEG_CASE(4, 1)
-    CPAPR_SEG_CASE(4, 2)
-    CPAPR_SEG_CASE(4, 4)
-    CPAPR_SEG_CASE(8, 1)
-    CPAPR_SEG_CASE(8, 2)
-    CPAPR_SEG_CASE(8, 4)
-    CPAPR_SEG_CASE(16, 1)
-    CPAPR_SEG_CASE(16, 2)
-    CPAPR_SEG_CASE(16, 4)
-    CPAPR_SEG_CASE(32, 1)
-    CPAPR_SEG_CASE(32, 2)
-    CPAPR_SEG_CASE(32, 4)
-    CPAPR_SEG_CASE(64, 1)
-    CPAPR_SEG_CASE(64, 2)
-    CPAPR_SEG_CASE(64, 4)
-#undef CPAPR_SEG_CASE
-    return {CPAPR_EUNSUPPORTED, "no Phi kernel for this lane-group / rank-block shape"};
 }
 
 Error dispatch_atomic(int G, int RPL, const PhiArgs& a, hipStream_t s)
@@ -453,14 +553,30 @@ Error zero_matrix(double* p, int64_t n, hipStream_t s)
 
 }  // namespace
 
-int resolve_group(int R, int requested)
+// Default launch shapes, from a sweep of lanes per nonzero and chunk on the
+// 3-way 20M-nonzero Zipf workload (R = 8, 10, 16, 32): fewer lanes per
+// nonzero with more rank columns per lane win because the kernel is bound by
+// instruction issue, and the per-nonzero dot all-reduce and FP64 divide are
+// shared by more nonzeros per wave.
+int resolve_group(int R, int requested, int nm1)
 {
     if (requested != 0) return requested;
     if (R <= 4) return 4;
     if (R <= 8) return 8;
-    if (R <= 16) return 16;
-    if (R <= 32) return 32;
+    if (R <= 16) return 8;
+    if (R <= 32) return 16;
+    if (R <= 64) return nm1 <= 3 ? 16 : 64;
     return 64;
+}
+
+bool phi_shape_supported(int group, int rpl, int nmodes_other)
+{
+    if (nmodes_other < 1 || nmodes_other > kMaxOther) return false;
+    if (group != 4 && group != 8 && group != 16 && group != 32 && group != 64) return false;
+    if (rpl != 1 && rpl != 2 && rpl != 4) return false;
+    if (rpl == 1 || group == 64) return true;
+    if (nmodes_other <= 3) return true;
+    return rpl == 2 && (group == 8 || group == 16);  // N >= 5: the default shapes only
 }
 
 int rank_block(int R, int group)
@@ -475,8 +591,8 @@ int rank_block(int R, int group)
 int resolve_chunk(int group, int requested)
 {
     if (requested > 0) return requested;
-    // ~1024 nonzeros per workgroup tile
-    return 1024 / (kBlock / group);
+    // 512 nonzeros per workgroup tile
+    return 512 / (kBlock / group);
 }
 
 Error launch_phi(const cpapr_plan* P, int mode, const double* B, const void* const* fac, bool mixed,

@@ -13,6 +13,8 @@
 // histogram table, (3) a stable scatter that ranks equal digits inside a wave
 // with ballots and across the workgroup's waves through LDS. Stability keeps
 // nonzeros of a row in input order, so plans and Phi are deterministic.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace cpapr {
@@ -23,6 +25,7 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortRounds = 16;                // items per thread per tile
 constexpr int kSortTile = kBlock * kSortRounds;  // 4096 keys per tile
 constexpr int kScanChunk = 4096;                 // elements per block in the scan
+constexpr int kSegPartials = 1024;               // blocks of the segment count
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -210,14 +213,38 @@ __global__ __launch_bounds__(kBlock) void gather_sorted_kernel(
     }
 }
 
+// Number of row changes in the sorted row array, two-level: per-block counts,
+// then one block adds them (no same-address atomics).
 __global__ __launch_bounds__(kBlock) void count_segments_kernel(const int32_t* __restrict__ rows, int64_t nnz,
-                                                                unsigned long long* out)
+                                                                unsigned long long* partial)
 {
+    __shared__ unsigned long long red[kBlock / 64];
     unsigned long long c = 0;
     for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * kBlock)
         c += (p == 0 || rows[p] != rows[p - 1]) ? 1 : 0;
     for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+        partial[blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void sum_partials_kernel(const unsigned long long* __restrict__ partial, int n,
+                                                              unsigned long long* out)
+{
+    __shared__ unsigned long long red[kBlock];
+    unsigned long long s = 0;
+    for (int i = threadIdx.x; i < n; i += kBlock) s += partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < kBlock; ++i) t += red[i];
+        *out = t;
+    }
 }
 
 int grid_for(int64_t n)
@@ -251,6 +278,7 @@ int64_t sort_scratch_bytes(int64_t nnz)
     b += align256((size_t)ncounts * 4);                     // histogram table
     b += align256((size_t)cdiv(ncounts, kScanChunk) * 4 + 4);  // scan chunk sums
     b += 256;                                                // flags / counters
+    b += align256(kSegPartials * 8);                         // segment-count partials
     return (int64_t)b;
 }
 
@@ -274,6 +302,7 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
     int* sums = (int*)take((size_t)cdiv(ncounts, kScanChunk) * 4 + 4);
     int* flags = (int*)take(256);
     unsigned long long* segc = (unsigned long long*)(flags + 8);
+    unsigned long long* segpart = (unsigned long long*)take(kSegPartials * 8);
 
     // flags and segment counters start at zero (plain kernel-free path: a tiny fill)
     CPAPR_HIP(hipMemsetAsync(flags, 0, 256, s));
@@ -318,7 +347,10 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
         gather_sorted_kernel<<<grid_for(nnz), kBlock, 0, s>>>(X->idx, X->vals, nnz, N, n, pin, pm.rows, pm.cidx,
                                                               pm.vals);
         CPAPR_LAUNCHED();
-        count_segments_kernel<<<grid_for(nnz), kBlock, 0, s>>>(pm.rows, nnz, segc + n);
+        const int gseg = std::min(grid_for(nnz), kSegPartials);
+        count_segments_kernel<<<gseg, kBlock, 0, s>>>(pm.rows, nnz, segpart);
+        CPAPR_LAUNCHED();
+        sum_partials_kernel<<<1, kBlock, 0, s>>>(segpart, gseg, segc + n);
         CPAPR_LAUNCHED();
     }
     unsigned long long hseg[CPAPR_MAX_MODES] = {};
