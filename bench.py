@@ -30,10 +30,21 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phi_traffic.json")
 
 
-def phi_kernel_bytes(N, R, nnz, segments, word=8):
-    """Algorithmic bytes of one Phi launch on the mode-sorted copy."""
-    per_nnz = 4 * N + 8 + (N - 1) * R * word
-    return nnz * per_nnz + segments * 2 * R * word
+def phi_kernel_bytes(N, R, nnz, segs, mode, word=8):
+    """Compulsory (algorithmic) HBM bytes of one Phi launch for `mode`: every
+    nonzero's coordinates and value once (4N + 8 bytes), every referenced row of
+    the other modes' factors once (segments of mode m = distinct rows of mode m),
+    and per nonempty row of this mode one B row read and one Phi row write."""
+    per_nnz = 4 * N + 8
+    fac = sum(segs[m] for m in range(N) if m != mode) * R * word
+    return nnz * per_nnz + fac + segs[mode] * R * (8 + 8)
+
+
+def phi_issued_bytes(N, R, nnz, segs, mode, word=8):
+    """Bytes the kernel issues with no reuse at all (every gathered factor row
+    counted per nonzero): the fused-kernel model of the paper's Section 3.2
+    applied to this kernel."""
+    return nnz * (4 * N + 8 + (N - 1) * R * word) + segs[mode] * R * (8 + 8)
 
 
 def kernel_source_hash():
@@ -45,8 +56,9 @@ def kernel_source_hash():
 
 
 def measured_traffic(workload, precision):
-    """HBM bytes per Phi launch from committed rocprofv3 counter runs, or None
-    if they were taken on another kernel source."""
+    """Bytes per Phi launch past L2 (FETCH_SIZE and WRITE_SIZE, scaled by the
+    factors a 1 GiB device copy gives) from committed rocprofv3 counter runs,
+    or None if they were taken on another kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)
@@ -150,11 +162,14 @@ def main():
     visits = launches_per_step * X.nnz
     value = visits / (ms_per_step / 1000.0)
     word = 4 if prec == cpapr.CPAPR_MIXED else 8
-    tot_bytes = sum(phi_kernel_bytes(N, R, X.nnz, segs[m], word) for m, _ in recs)
+    tot_bytes = sum(phi_kernel_bytes(N, R, X.nnz, segs, m, word) for m, _ in recs)
+    issued = sum(phi_issued_bytes(N, R, X.nnz, segs, m, word) for m, _ in recs)
     tot_ms = sum(ms for _, ms in recs)
     achieved = tot_bytes / (tot_ms / 1000.0) / 1e9
     avg_ms = tot_ms / max(1, len(recs))
-    traffic = measured_traffic("zipf3-20M-R16", args.precision)
+    per_mode_ms = [sum(ms for m, ms in recs if m == n) / max(1, sum(1 for m, _ in recs if m == n)) for n in range(N)]
+    traffic_bytes = measured_traffic("zipf3-20M-R16", args.precision)
+    traffic = None if traffic_bytes is None else traffic_bytes / (avg_ms / 1000.0) / 1e9
     out = {
         "metric": "Phi^(n) nonzeros/s",
         "value": value,
@@ -174,8 +189,12 @@ def main():
                    "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
-        "phi_kernel": {"launches": len(recs), "avg_ms": avg_ms, "nnz_per_s": X.nnz / (avg_ms / 1000.0),
-                       "bytes_per_launch_model": tot_bytes / max(1, len(recs)),
+        "phi_kernel": {"launches": len(recs), "avg_ms": avg_ms, "avg_ms_per_mode": per_mode_ms,
+                       "nnz_per_s": X.nnz / (avg_ms / 1000.0),
+                       "compulsory_bytes_per_launch": tot_bytes / max(1, len(recs)),
+                       "issued_bytes_per_launch": issued / max(1, len(recs)),
+                       "issued_GBs": issued / (tot_ms / 1000.0) / 1e9,
+                       "measured_bytes_per_launch": traffic_bytes,
                        "segments": segs, "share_of_step": tot_ms / (ms_per_step * args.steps)},
         "solve": {"outer": st["outer_iters"], "inner_updates": st["inner_iters"],
                   "kkt": st["kkt_violation"], "loglik": st["loglik"]},

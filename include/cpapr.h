@@ -64,6 +64,12 @@ enum { CPAPR_FP64 = 0, CPAPR_MIXED = 1 };
  * (Algorithm 3), kept for comparison. AUTO picks SEGMENTED. */
 enum { CPAPR_VARIANT_AUTO = 0, CPAPR_VARIANT_SEGMENTED = 1, CPAPR_VARIANT_ATOMIC = 2 };
 
+/* Order of the nonzeros inside a row of the mode-n sorted copy (Phi's sum over
+ * a row is order-free). ROW: input order (a stable sort by i_n). ROW_COL: by
+ * the coordinate of the largest other mode, so long rows sweep that factor in
+ * order. */
+enum { CPAPR_SORT_ROW = 0, CPAPR_SORT_ROW_COL = 1 };
+
 /* Sparse count tensor in coordinate format (the paper's I[n][j], X[j]). */
 typedef struct cpapr_coo {
     int32_t nmodes;      /* N */
@@ -85,6 +91,7 @@ typedef struct cpapr_params {
     int32_t variant;   /* CPAPR_VARIANT_* */
     int32_t group;     /* lanes per nonzero (0 = by rank; else 4, 8, 16, 32 or 64) */
     int32_t chunk;     /* nonzeros per lane group per tile (0 = default) */
+    int32_t sort;      /* CPAPR_SORT_*: order of the nonzeros inside each row of a mode */
 } cpapr_params;
 
 /* Result summary of cpapr_mu_inner / cpapr_solve (host). */
@@ -99,7 +106,7 @@ typedef struct cpapr_stats {
 typedef struct cpapr_plan cpapr_plan;
 
 /* Fill *p with the defaults: kmax 10, lmax 10, tol 1e-4, eps 1e-10,
- * kappa 0.01, kappa_tol 1e-10, FP64, AUTO, group 0, chunk 0. */
+ * kappa 0.01, kappa_tol 1e-10, FP64, AUTO, group 0, chunk 0, sort ROW_COL. */
 void cpapr_params_default(cpapr_params* p);
 
 /* Bytes of device workspace a plan for X at rank R and parameters p needs

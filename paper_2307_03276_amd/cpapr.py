@@ -24,6 +24,8 @@ CPAPR_MIXED = 1
 CPAPR_VARIANT_AUTO = 0
 CPAPR_VARIANT_SEGMENTED = 1
 CPAPR_VARIANT_ATOMIC = 2
+CPAPR_SORT_ROW = 0
+CPAPR_SORT_ROW_COL = 1
 MAX_MODES = 8
 
 
@@ -41,7 +43,7 @@ class cpapr_coo(C.Structure):
 class cpapr_params(C.Structure):
     _fields_ = [("kmax", C.c_int32), ("lmax", C.c_int32), ("tol", C.c_double), ("eps", C.c_double),
                 ("kappa", C.c_double), ("kappa_tol", C.c_double), ("precision", C.c_int32),
-                ("variant", C.c_int32), ("group", C.c_int32), ("chunk", C.c_int32)]
+                ("variant", C.c_int32), ("group", C.c_int32), ("chunk", C.c_int32), ("sort", C.c_int32)]
 
 
 class cpapr_stats(C.Structure):

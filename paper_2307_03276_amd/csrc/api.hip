@@ -69,6 +69,7 @@ Error check_params(const cpapr_params* p, int32_t R, int nmodes)
     if (!cpapr::phi_shape_supported(g, cpapr::rank_block(R, g), nmodes - 1))
         return {CPAPR_EUNSUPPORTED, "no Phi kernel for this lane group and rank block at this mode count"};
     if (p->chunk < 0 || p->chunk > 65536) return {CPAPR_EINVAL, "chunk must be in [0, 65536]"};
+    if (p->sort != CPAPR_SORT_ROW && p->sort != CPAPR_SORT_ROW_COL) return {CPAPR_EINVAL, "unknown sort"};
     return {CPAPR_OK, ""};
 }
 
@@ -234,6 +235,7 @@ void cpapr_params_default(cpapr_params* p)
     p->variant = CPAPR_VARIANT_AUTO;
     p->group = 0;
     p->chunk = 0;
+    p->sort = CPAPR_SORT_ROW_COL;
 }
 
 const char* cpapr_last_error(void) { return g_error.c_str(); }

@@ -240,16 +240,16 @@ __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
         prow[2 * g + 1] = -1;
     }
 
-    // Lanes past the rank gather a clamped (in-row) column instead of being
-    // masked, so the hot loop carries no selects; their B entries are zero, so
-    // they add nothing to the dot product, and their accumulators are never stored.
-    bool valid[RPL];
-    int col[RPL];
+    // Each lane owns the rank columns [lane*RPL, lane*RPL + RPL) that are < R,
+    // but always reads a window of RPL contiguous, in-row columns starting at
+    // colbase (shifted left for lanes at or past the end of the row). One
+    // address per gathered row, no selects in the hot loop; slots the lane
+    // does not own get B = 0 (no contribution to the dot product) and are
+    // never stored.
+    const int colbase = min(lane * RPL, R - RPL);
+    bool own[RPL];
 #pragma unroll
-    for (int c = 0; c < RPL; ++c) {
-        valid[c] = lane * RPL + c < R;
-        col[c] = min(lane * RPL + c, R - 1);
-    }
+    for (int c = 0; c < RPL; ++c) own[c] = colbase + c >= lane * RPL && colbase + c < R;
 
     int cur = -1;
     int nseg = 0;
@@ -264,14 +264,15 @@ __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
     // Flush kinds: 0 = head partial (LDS), 1 = tail partial (LDS), 2 = owned row (store).
     auto flush = [&](int row, int kind) {
         if (kind == 2) {
-            double* dst = a.Phi + (int64_t)row * R + lane * RPL;
+            double* dst = a.Phi + (int64_t)row * R + colbase;
 #pragma unroll
             for (int c = 0; c < RPL; ++c)
-                if (valid[c]) dst[c] = acc[c].value();
+                if (own[c]) dst[c] = acc[c].value();
         } else {
             const int e = 2 * g + kind;
 #pragma unroll
-            for (int c = 0; c < RPL; ++c) part[e][lane * RPL + c] = acc[c].value();
+            for (int c = 0; c < RPL; ++c)
+                if (own[c]) part[e][colbase + c] = acc[c].value();
             if (lane == 0) prow[e] = row;
         }
     };
@@ -320,9 +321,9 @@ __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
                     xu[u] = e.x;
 #pragma unroll
                     for (int m = 0; m < NM1; ++m) {
-                        const T* f = fac[m] + (int64_t)e.c[m] * R;
+                        const T* f = fac[m] + (int64_t)e.c[m] * R + colbase;
 #pragma unroll
-                        for (int c = 0; c < RPL; ++c) fu[u][m][c] = f[col[c]];
+                        for (int c = 0; c < RPL; ++c) fu[u][m][c] = f[c];
                     }
                 }
             }
@@ -344,9 +345,9 @@ __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
 #pragma unroll
                         for (int c = 0; c < RPL; ++c) acc[c].zero();
                         if constexpr (!MTTKRP) {
-                            const double* brow = a.B + (int64_t)row * R;
+                            const double* brow = a.B + (int64_t)row * R + colbase;
 #pragma unroll
-                            for (int c = 0; c < RPL; ++c) b[c] = valid[c] ? (T)brow[col[c]] : (T)0;
+                            for (int c = 0; c < RPL; ++c) b[c] = own[c] ? (T)brow[c] : (T)0;
                         }
                     }
                     const T s = nonzero_scale<G, RPL, MIXED, MTTKRP, T>(b, pi, xu[u], a.eps);
@@ -564,7 +565,7 @@ int resolve_group(int R, int requested, int nm1)
     if (R <= 4) return 4;
     if (R <= 8) return 8;
     if (R <= 16) return 8;
-    if (R <= 32) return 16;
+    if (R <= 32) return nm1 <= 3 ? 8 : 16;
     if (R <= 64) return nm1 <= 3 ? 16 : 64;
     return 64;
 }

@@ -192,6 +192,18 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const int32_t* __
     }
 }
 
+// keys_out[p] = keys[perm[p]]: a key array in the order of an earlier sort.
+__global__ __launch_bounds__(kBlock) void permute_keys_kernel(const int32_t* __restrict__ keys,
+                                                              const int32_t* __restrict__ perm, int64_t nnz,
+                                                              int32_t* __restrict__ keys_out)
+{
+    for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * kBlock) {
+        int64_t k = perm[p];
+        if (k < 0 || k >= nnz) k = p;  // a permutation never leaves [0, nnz); keeps reads in bounds
+        keys_out[p] = keys[k];
+    }
+}
+
 // Copy sorted keys to the row array and gather values and the other modes'
 // coordinates through the permutation (perm == nullptr: identity).
 __global__ __launch_bounds__(kBlock) void gather_sorted_kernel(
@@ -324,25 +336,54 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
             pm.segments = 0;
             continue;
         }
-        int bits = 0;
-        while (bits < 31 && ((int64_t)1 << bits) < P->dims[n]) ++bits;
-        const int passes = (bits + kRadixBits - 1) / kRadixBits;
-        const int32_t* kin = X->idx + (int64_t)n * nnz;
-        const int32_t* pin = nullptr;  // identity payload on the first pass
-        int32_t *kout = ka, *pout = pa;
-        for (int ps = 0; ps < passes; ++ps) {
-            const int shift = ps * kRadixBits;
-            radix_hist_kernel<<<(int)ntiles, kBlock, 0, s>>>(kin, nnz, shift, counts, (int)ntiles);
-            CPAPR_LAUNCHED();
-            Error e = exclusive_scan(counts, ncounts, sums, s);
+        // LSD passes over the low `bits` bits of the keys in (kin, pin); outputs
+        // alternate between (ka, kb) and (pa, pb), never aliasing the inputs.
+        const int32_t* kin = nullptr;
+        const int32_t* pin = nullptr;  // nullptr: identity payload
+        auto passes = [&](int64_t dim) -> Error {
+            int bits = 0;
+            while (bits < 31 && ((int64_t)1 << bits) < dim) ++bits;
+            for (int ps = 0; ps < (bits + kRadixBits - 1) / kRadixBits; ++ps) {
+                const int shift = ps * kRadixBits;
+                int32_t* kout = (kin == ka) ? kb : ka;
+                int32_t* pout = (pin == pa) ? pb : pa;
+                radix_hist_kernel<<<(int)ntiles, kBlock, 0, s>>>(kin, nnz, shift, counts, (int)ntiles);
+                CPAPR_LAUNCHED();
+                Error e = exclusive_scan(counts, ncounts, sums, s);
+                if (e.code) return e;
+                radix_scatter_kernel<<<(int)ntiles, kBlock, 0, s>>>(kin, pin, kout, pout, nnz, shift, counts,
+                                                                    (int)ntiles);
+                CPAPR_LAUNCHED();
+                kin = kout;
+                pin = pout;
+            }
+            return {CPAPR_OK, ""};
+        };
+        // Secondary key first (stable LSD order): within each row of mode n the
+        // nonzeros then follow the largest other mode's coordinate, so that
+        // mode's factor rows are swept in order inside long rows.
+        int sec = -1;
+        if (P->params.sort == CPAPR_SORT_ROW_COL)
+            for (int m = 0; m < N; ++m)
+                if (m != n && (sec < 0 || P->dims[m] > P->dims[sec])) sec = m;
+        if (sec >= 0) {
+            kin = X->idx + (int64_t)sec * nnz;
+            Error e = passes(P->dims[sec]);
             if (e.code) return e;
-            radix_scatter_kernel<<<(int)ntiles, kBlock, 0, s>>>(kin, pin, kout, pout, nnz, shift, counts,
-                                                                (int)ntiles);
-            CPAPR_LAUNCHED();
-            kin = kout;
-            pin = pout;
-            kout = (kout == ka) ? kb : ka;
-            pout = (pout == pa) ? pb : pa;
+            if (pin != nullptr) {  // keys of mode n in the secondary order
+                int32_t* kout = (kin == ka) ? kb : ka;
+                permute_keys_kernel<<<grid_for(nnz), kBlock, 0, s>>>(X->idx + (int64_t)n * nnz, pin, nnz, kout);
+                CPAPR_LAUNCHED();
+                kin = kout;
+            } else {
+                kin = X->idx + (int64_t)n * nnz;
+            }
+        } else {
+            kin = X->idx + (int64_t)n * nnz;
+        }
+        {
+            Error e = passes(P->dims[n]);
+            if (e.code) return e;
         }
         gather_sorted_kernel<<<grid_for(nnz), kBlock, 0, s>>>(X->idx, X->vals, nnz, N, n, pin, pm.rows, pm.cidx,
                                                               pm.vals);

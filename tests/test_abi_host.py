@@ -38,6 +38,7 @@ def test_params_default(lib):
     p = cpapr.cpapr_params_default()
     assert (p.kmax, p.lmax, p.tol, p.eps, p.kappa, p.kappa_tol) == (10, 10, 1e-4, 1e-10, 0.01, 1e-10)
     assert p.precision == cpapr.CPAPR_FP64 and p.variant == 0 and p.group == 0 and p.chunk == 0
+    assert p.sort == cpapr.CPAPR_SORT_ROW_COL
 
 
 def _coo(dims, nnz):
@@ -81,6 +82,9 @@ def test_workspace_size_grows_with_problem(lib):
     ([4, 5, 6], 10, 4, "group", 12, -1),
     ([4, 5, 6], 10, 40, "group", 8, -6),                  # R > 4 * group
     ([4, 5, 6], 10, 4, "variant", 9, -1),
+    ([4, 5, 6], 10, 4, "sort", 5, -1),
+    ([4, 5, 6, 7, 8], 10, 32, "group", 16, 0),           # N = 5: 16 lanes x 2 ranks is built
+    ([4, 5, 6, 7, 8], 10, 64, "group", 16, -6),          # N = 5: 16 lanes x 4 ranks is not
 ])
 def test_workspace_size_rejects(lib, dims, nnz, R, field, val, code):
     p = cpapr.cpapr_params_default()
@@ -88,7 +92,8 @@ def test_workspace_size_rejects(lib, dims, nnz, R, field, val, code):
         setattr(p, field, val)
     rc, _ = _size(_coo(dims, nnz), R, p)
     assert rc == code
-    assert cpapr.cpapr_last_error()
+    if code:
+        assert cpapr.cpapr_last_error()
 
 
 def test_plan_create_host_checks(lib):

@@ -70,6 +70,14 @@ def test_phi_launch_shapes(group, R, chunk):
     _phi_case(X, M, group=group, chunk=chunk)
 
 
+@pytest.mark.parametrize("sort", [0, 1])
+@pytest.mark.parametrize("dims", [(300, 2000, 50), (40, 30, 20, 10)])
+def test_phi_sort_modes(sort, dims):
+    X = synth.random_tensor(17, dims, 60_000, zipf=(1.1,) * len(dims))
+    M = synth.random_model(17, dims, 16)
+    _phi_case(X, M, sort=sort)
+
+
 def test_phi_one_row_spans_everything():
     """Every nonzero in one row of mode 0: the row crosses every tile boundary."""
     rng = np.random.default_rng(5)
