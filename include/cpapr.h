@@ -30,7 +30,8 @@
  *     message from cpapr_last_error() (thread-local). No C++ exception
  *     crosses this boundary. Non-convergence is not an error.
  *   - Limits: 2 <= N <= CPAPR_MAX_MODES, 1 <= R <= CPAPR_MAX_RANK,
- *     0 <= nnz < 2^31, 1 <= I_n < 2^31.
+ *     0 <= nnz < 2^31, 1 <= I_n < 2^31, I_n * R < 2^32 (factor row offsets
+ *     are stored as 32-bit element offsets).
  */
 #ifndef CPAPR_H
 #define CPAPR_H

@@ -49,6 +49,9 @@ Error check_coo(const cpapr_coo* X, int32_t R, bool need_data)
     if (X->nnz > 0x7fffffffLL) return {CPAPR_EUNSUPPORTED, "nnz must be < 2^31"};
     if (need_data && X->nnz > 0 && (!X->idx || !X->vals)) return {CPAPR_EINVAL, "idx or vals is NULL"};
     if (R < 1 || R > CPAPR_MAX_RANK) return {CPAPR_EUNSUPPORTED, "R must be in [1, 256]"};
+    for (int m = 0; m < X->nmodes; ++m)
+        if (X->dims[m] * (int64_t)R > 0xffffffffLL)
+            return {CPAPR_EUNSUPPORTED, "each factor must have fewer than 2^32 entries (I_m * R)"};
     return {CPAPR_OK, ""};
 }
 
@@ -114,7 +117,7 @@ Layout layout(int N, int64_t nnz, const int64_t* dims, int R, bool mixed)
     L.partial = off + s;
     s += align256((size_t)cpapr::kPartials * R * 8);
     L.llpart = off + s;
-    s += align256((size_t)cpapr::kLLBlocks * 8);
+    s += align256((size_t)cpapr::loglik_partials(nnz) * 8);
     L.colsums = off + s;
     s += align256((size_t)N * R * 8);
     L.state = off + s;
@@ -160,21 +163,23 @@ Error phi_factors(cpapr_plan* P, int mode, const double* const* A, const void** 
     return {CPAPR_OK, ""};
 }
 
-// One inner loop (Algorithm 1): lmax x {zero Phi, Phi, KKT, MU update}, all
-// gated by the device-side `done` flag. No host synchronisation.
+// One inner loop (Algorithm 1): zero Phi, then lmax x {Phi, KKT, MU update},
+// all gated by the device-side `done` flag. No host synchronisation.
 Error enqueue_inner(cpapr_plan* P, int mode, double* B, const void* const* fac, double* Phi, hipStream_t s)
 {
     const int64_t n = P->dims[mode] * (int64_t)P->R;
     const bool mixed = P->params.precision == CPAPR_MIXED;
     const int* done = &P->state->done;
-    for (int l = 0; l < P->params.lmax; ++l) {
-        Error e = cpapr::launch_fill(Phi, n, 0.0, done, s);
-        if (e.code) return e;
+    Error e = cpapr::launch_fill(Phi, n, 0.0, done, s);
+    if (e.code) return e;
+    const int lmax = P->params.lmax;
+    for (int l = 0; l < lmax; ++l) {
         e = cpapr::launch_phi(P, mode, B, fac, mixed, P->params.eps, Phi, done, s);
         if (e.code) return e;
         e = cpapr::launch_kkt(B, Phi, n, P->state, l, s);
         if (e.code) return e;
-        e = cpapr::launch_mu_update(B, Phi, n, P->state, l, mode, P->params.tol, s);
+        // the update clears Phi for the next Phi launch, except after the last one
+        e = cpapr::launch_mu_update(B, Phi, n, P->state, l, mode, P->params.tol, l + 1 < lmax, s);
         if (e.code) return e;
     }
     return {CPAPR_OK, ""};
@@ -285,7 +290,7 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
         P->chunk = cpapr::resolve_chunk(P->group, p->chunk);
         for (int n = 0; n < P->N; ++n) {
             P->mode[n].rows = (int32_t*)(w + L.mode_rows[n]);
-            P->mode[n].cidx = (int32_t*)(w + L.mode_cidx[n]);
+            P->mode[n].cofs = (uint32_t*)(w + L.mode_cidx[n]);
             P->mode[n].vals = (double*)(w + L.mode_vals[n]);
             P->f32[n] = mixed ? (float*)(w + L.f32[n]) : nullptr;
             P->phi_prev[n] = (double*)(w + L.phi_prev[n]);

@@ -38,7 +38,7 @@ struct DevState {
 
 struct PlanMode {
     int32_t* rows;  // [nnz] sorted mode-n coordinates
-    int32_t* cidx;  // [(N-1) * nnz] the other modes' coordinates in sorted order, ascending m
+    uint32_t* cofs;  // [(N-1) * nnz] the other modes' factor row offsets (coordinate x R), ascending m
     double* vals;   // [nnz]
     int64_t segments;
 };
@@ -56,7 +56,7 @@ struct cpapr_plan {
     double* B;                        // [maxI x R] solve work matrix
     double* phi_prev[CPAPR_MAX_MODES];  // [I_m x R] last Phi per mode (solve)
     double* partial;                  // [kPartials x R] column-sum / reduction partials
-    double* llpart;                   // [kLLBlocks] log-likelihood partials
+    double* llpart;                   // [loglik_partials(nnz)] log-likelihood partials, one per tile
     double* colsums;                  // [N x R]
     cpapr::DevState* state;
     char* ws;
@@ -67,7 +67,6 @@ struct cpapr_plan {
 namespace cpapr {
 
 constexpr int kPartials = 512;   // blocks of the two-level deterministic column sums
-constexpr int kLLBlocks = 4096;  // blocks of the log-likelihood pass
 
 // ---- plan construction (sort.hip) ----
 int64_t sort_scratch_bytes(int64_t nnz);
@@ -91,7 +90,7 @@ Error launch_fill(double* p, int64_t n, double v, const int* done, hipStream_t s
 Error launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 Error launch_reset_state(DevState* st, bool new_sweep, bool all, hipStream_t s);
 Error launch_kkt(const double* B, const double* Phi, int64_t n, DevState* st, int l, hipStream_t s);
-Error launch_mu_update(double* B, const double* Phi, int64_t n, DevState* st, int l, int mode, double tol,
+Error launch_mu_update(double* B, double* Phi, int64_t n, DevState* st, int l, int mode, double tol, bool zero_phi,
                        hipStream_t s);
 Error launch_shift_scale(double* A, const double* phi_prev, const double* lam, double* B, int64_t I, int R,
                          double kappa, double kappa_tol, bool shift, hipStream_t s);
@@ -100,6 +99,12 @@ Error launch_normalize(const double* B, const double* lam, double* A, float* A32
                        hipStream_t s);
 Error launch_loglik(const cpapr_plan* P, const double* lam, const double* const* A, double eps,
                     hipStream_t s);
+// Sum of x_k log(max(m_k, eps)) over the nonzeros of the mode-0 copy into
+// `partial` (one entry per tile; returns the number of tiles in *nparts), where
+// m_k = B[i_0(k), :] . pi_k and B = A(0) diag(lambda).
+Error launch_loglik_terms(const cpapr_plan* P, const double* B, const double* const* A, double eps, double* partial,
+                          int* nparts, hipStream_t s);
+int64_t loglik_partials(int64_t nnz);
 
 // ---- profiling hooks (api.hip) ----
 void prof_begin(int mode, hipStream_t s);

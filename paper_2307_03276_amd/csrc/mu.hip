@@ -86,9 +86,12 @@ __global__ __launch_bounds__(kBlock) void kkt_kernel(const double* __restrict__ 
 // B <- B .* Phi unless the KKT test says stop. Every block folds the slots to
 // the same violation; only block 0 records it, raises `done` and clears the
 // other parity's slots for the next iteration. Other blocks of this launch
-// that see `done` early skip work they would have skipped anyway.
-__global__ __launch_bounds__(kBlock) void mu_update_kernel(double* __restrict__ B, const double* __restrict__ Phi,
-                                                           int64_t n, DevState* st, int l, int mode, double tol)
+// that see `done` early skip work they would have skipped anyway. With
+// zero_phi the consumed Phi is cleared for the next iteration's accumulation
+// (never on a stop, so the last Phi survives).
+__global__ __launch_bounds__(kBlock) void mu_update_kernel(double* __restrict__ B, double* __restrict__ Phi,
+                                                           int64_t n, DevState* st, int l, int mode, double tol,
+                                                           int zero_phi)
 {
     if (st->done) return;
     __shared__ double viol_sh;
@@ -114,8 +117,15 @@ __global__ __launch_bounds__(kBlock) void mu_update_kernel(double* __restrict__ 
         }
     }
     if (stop) return;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        B[i] *= Phi[i];
+    if (zero_phi) {
+        for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+            B[i] *= Phi[i];
+            Phi[i] = 0.0;
+        }
+    } else {
+        for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+            B[i] *= Phi[i];
+    }
 }
 
 // A(n) += kappa where A < kappa_tol and the previous Phi > 1 (from the second
@@ -192,48 +202,6 @@ __global__ __launch_bounds__(kBlock) void normalize_kernel(const double* __restr
     }
 }
 
-struct LLArgs {
-    const int32_t* rows;
-    const int32_t* cidx;
-    const double* vals;
-    const double* fac0;
-    const double* fac[CPAPR_MAX_MODES - 1];
-    const double* lam;
-    int64_t nnz;
-    int R;
-    int NM1;
-    double eps;
-    double* partial;
-};
-
-// sum_k x_k log(max(m_k, eps)), m_k = sum_r lam_r prod_m A(m)[i_m, r]; a
-// 16-lane group per nonzero, fixed grid-stride order, ordered block reduction.
-__global__ __launch_bounds__(kBlock) void loglik_partial_kernel(LLArgs a)
-{
-    constexpr int G = 16, NG = kBlock / G;
-    __shared__ double red[NG];
-    const int t = threadIdx.x, g = t / G, lane = t % G;
-    double acc = 0.0;
-    for (int64_t p = (int64_t)blockIdx.x * NG + g; p < a.nnz; p += (int64_t)gridDim.x * NG) {
-        const int32_t i0 = a.rows[p];
-        double part = 0.0;
-        for (int r = lane; r < a.R; r += G) {
-            double v = a.lam[r] * a.fac0[(int64_t)i0 * a.R + r];
-            for (int m = 0; m < a.NM1; ++m) v *= a.fac[m][(int64_t)a.cidx[(int64_t)m * a.nnz + p] * a.R + r];
-            part += v;
-        }
-        for (int off = 1; off < G; off <<= 1) part += __shfl_xor(part, off, G);
-        acc += a.vals[p] * log(part > a.eps ? part : a.eps);
-    }
-    if (lane == 0) red[g] = acc;
-    __syncthreads();
-    if (t == 0) {
-        double s = 0.0;
-        for (int q = 0; q < NG; ++q) s += red[q];
-        a.partial[blockIdx.x] = s;
-    }
-}
-
 __global__ __launch_bounds__(kBlock) void loglik_final_kernel(const double* __restrict__ partial, int nparts,
                                                               const double* __restrict__ lam,
                                                               const double* __restrict__ colsums, int N, int R,
@@ -288,10 +256,10 @@ Error launch_kkt(const double* B, const double* Phi, int64_t n, DevState* st, in
     return {CPAPR_OK, ""};
 }
 
-Error launch_mu_update(double* B, const double* Phi, int64_t n, DevState* st, int l, int mode, double tol,
+Error launch_mu_update(double* B, double* Phi, int64_t n, DevState* st, int l, int mode, double tol, bool zero_phi,
                        hipStream_t s)
 {
-    mu_update_kernel<<<grid_for(n, 4096), kBlock, 0, s>>>(B, Phi, n, st, l, mode, tol);
+    mu_update_kernel<<<grid_for(n, 4096), kBlock, 0, s>>>(B, Phi, n, st, l, mode, tol, zero_phi ? 1 : 0);
     CPAPR_LAUNCHED();
     return {CPAPR_OK, ""};
 }
@@ -334,21 +302,13 @@ Error launch_loglik(const cpapr_plan* P, const double* lam, const double* const*
         Error e = launch_colsum(A[m], P->dims[m], R, P->partial, P->colsums + (int64_t)m * R, s);
         if (e.code) return e;
     }
-    LLArgs a{};
-    a.rows = P->mode[0].rows;
-    a.cidx = P->mode[0].cidx;
-    a.vals = P->mode[0].vals;
-    a.fac0 = A[0];
-    for (int m = 1; m < N; ++m) a.fac[m - 1] = A[m];
-    a.lam = lam;
-    a.nnz = P->nnz;
-    a.R = R;
-    a.NM1 = N - 1;
-    a.eps = eps;
-    a.partial = P->llpart;
-    const int nparts = kLLBlocks;
-    loglik_partial_kernel<<<nparts, kBlock, 0, s>>>(a);
-    CPAPR_LAUNCHED();
+    // m_k = sum_r lambda_r prod_m A(m)[i_m, r] = B[i_0, :] . pi_k with B = A(0) diag(lambda):
+    // the Phi engine's dot product on the mode-0 copy.
+    Error e = launch_shift_scale(const_cast<double*>(A[0]), nullptr, lam, P->B, P->dims[0], R, 0.0, 0.0, false, s);
+    if (e.code) return e;
+    int nparts = 0;
+    e = launch_loglik_terms(P, P->B, A, eps, P->llpart, &nparts, s);
+    if (e.code) return e;
     loglik_final_kernel<<<1, kBlock, 0, s>>>(P->llpart, nparts, lam, P->colsums, N, R, P->state);
     CPAPR_LAUNCHED();
     return {CPAPR_OK, ""};

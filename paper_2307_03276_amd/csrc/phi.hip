@@ -36,7 +36,7 @@ constexpr int kMaxOther = CPAPR_MAX_MODES - 1;
 
 struct PhiArgs {
     const int32_t* rows;
-    const int32_t* cidx;
+    const uint32_t* cofs;
     const double* vals;
     const void* fac[kMaxOther];
     const double* B;
@@ -168,17 +168,24 @@ struct Acc<true> {
     __device__ double value() const { return (double)hi + (double)lo; }
 };
 
-// One nonzero's pi slice, dot product and scale. Returns s_k (or x_k for MTTKRP).
-template <int G, int RPL, bool MIXED, bool MTTKRP, typename T>
+// What the segmented kernel computes per nonzero and where it goes.
+constexpr int kPhi = 0;     // s_k = x_k / max(m_k, eps); Phi[i_n] += s_k pi_k
+constexpr int kMttkrp = 1;  // s_k = x_k;                  M[i_n]  += s_k pi_k
+constexpr int kLoglik = 2;  // x_k log(max(m_k, eps)) summed per tile (no scatter)
+
+// One nonzero's dot product and scale: s_k for Phi, x_k for MTTKRP, the
+// likelihood term for Loglik.
+template <int G, int RPL, bool MIXED, int KIND, typename T>
 __device__ __forceinline__ T nonzero_scale(const T (&b)[RPL], const T (&pi)[RPL], double x, double eps)
 {
-    if constexpr (MTTKRP) {
+    if constexpr (KIND == kMttkrp) {
         return (T)x;
     } else if constexpr (!MIXED) {
         double d = 0.0;
 #pragma unroll
         for (int c = 0; c < RPL; ++c) d = __builtin_fma(b[c], pi[c], d);
         d = group_sum<G>(d);
+        if constexpr (KIND == kLoglik) return x * log(d > eps ? d : eps);
         return x / (d > eps ? d : eps);
     } else {
         float hi = 0.f, lo = 0.f;
@@ -197,7 +204,7 @@ __device__ __forceinline__ T nonzero_scale(const T (&b)[RPL], const T (&pi)[RPL]
 template <int NM1>
 struct alignas(8) Staged {
     int row;
-    int c[NM1];
+    uint32_t c[NM1];  // factor row offsets (coordinate x R)
     double x;
 };
 
@@ -209,7 +216,7 @@ constexpr int gather_depth()
     return NM1 * RPL <= 2 ? 4 : (NM1 * RPL <= 4 ? 2 : 1);
 }
 
-template <int G, int RPL, int NM1, bool MIXED, bool MTTKRP>
+template <int G, int RPL, int NM1, bool MIXED, int KIND>
 __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
@@ -253,6 +260,7 @@ __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
 
     int cur = -1;
     int nseg = 0;
+    double ll = 0.0;  // likelihood terms of this lane group (Loglik)
     Acc<MIXED> acc[RPL];
     T b[RPL];
 #pragma unroll
@@ -292,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
             if (p < p1) {
                 pre[k].row = a.rows[p];
 #pragma unroll
-                for (int m = 0; m < NM1; ++m) pre[k].c[m] = a.cidx[(int64_t)m * nnz + p];
+                for (int m = 0; m < NM1; ++m) pre[k].c[m] = a.cofs[(int64_t)m * nnz + p];
                 pre[k].x = a.vals[p];
             }
         }
@@ -321,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
                     xu[u] = e.x;
 #pragma unroll
                     for (int m = 0; m < NM1; ++m) {
-                        const T* f = fac[m] + (int64_t)e.c[m] * R + colbase;
+                        const T* f = fac[m] + (uint64_t)e.c[m] + colbase;
 #pragma unroll
                         for (int c = 0; c < RPL; ++c) fu[u][m][c] = f[c];
                     }
@@ -339,26 +347,41 @@ __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
                         for (int m = 1; m < NM1; ++m) pi[c] *= fu[u][m][c];
                     }
                     if (row != cur) {
-                        if (cur >= 0) flush(cur, nseg == 1 ? 0 : 2);
+                        if constexpr (KIND != kLoglik)
+                            if (cur >= 0) flush(cur, nseg == 1 ? 0 : 2);
                         cur = row;
                         ++nseg;
 #pragma unroll
                         for (int c = 0; c < RPL; ++c) acc[c].zero();
-                        if constexpr (!MTTKRP) {
+                        if constexpr (KIND != kMttkrp) {
                             const double* brow = a.B + (int64_t)row * R + colbase;
 #pragma unroll
                             for (int c = 0; c < RPL; ++c) b[c] = own[c] ? (T)brow[c] : (T)0;
                         }
                     }
-                    const T s = nonzero_scale<G, RPL, MIXED, MTTKRP, T>(b, pi, xu[u], a.eps);
+                    const T s = nonzero_scale<G, RPL, MIXED, KIND, T>(b, pi, xu[u], a.eps);
+                    if constexpr (KIND == kLoglik) {
+                        ll += s;
+                    } else {
 #pragma unroll
-                    for (int c = 0; c < RPL; ++c) acc[c].add(s, pi[c]);
+                        for (int c = 0; c < RPL; ++c) acc[c].add(s, pi[c]);
+                    }
                 }
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if constexpr (KIND == kLoglik) {
+        if (lane == 0) part[2 * g][0] = ll;
+        __syncthreads();
+        if (t == 0) {
+            double sum = 0.0;
+            for (int q = 0; q < NG; ++q) sum += part[2 * q][0];
+            a.Phi[tile] = sum;  // one partial per tile, reduced in order later
+        }
+        return;
     }
     if (cur >= 0) flush(cur, nseg == 1 ? 0 : 1);
     __syncthreads();
@@ -414,8 +437,7 @@ __global__ __launch_bounds__(kBlock) void phi_atomic_kernel(PhiArgs a)
 #pragma unroll
         for (int c = 0; c < RPL; ++c) pi[c] = valid[c] ? 1.0 : 0.0;
         for (int m = 0; m < a.NM1; ++m) {
-            const int32_t ci = a.cidx[(int64_t)m * a.nnz + p];
-            const double* f = (const double*)a.fac[m] + (int64_t)ci * R + lane * RPL;
+            const double* f = (const double*)a.fac[m] + (uint64_t)a.cofs[(int64_t)m * a.nnz + p] + lane * RPL;
 #pragma unroll
             for (int c = 0; c < RPL; ++c)
                 if (valid[c]) pi[c] *= f[c];
@@ -439,12 +461,12 @@ __global__ __launch_bounds__(kBlock) void zero_kernel(double* p, int64_t n)
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-template <int NM1, bool MIXED, bool MTTKRP>
+template <int NM1, bool MIXED, int KIND>
 Error dispatch_seg_n(int G, int RPL, const PhiArgs& a, dim3 grid, hipStream_t s)
 {
 #define CPAPR_SEG_CASE(GG, RR)                                                        \
     if (G == GG && RPL == RR) {                                                       \
-        phi_seg_kernel<GG, RR, NM1, MIXED, MTTKRP><<<grid, kBlock, 0, s>>>(a);        \
+        phi_seg_kernel<GG, RR, NM1, MIXED, KIND><<<grid, kBlock, 0, s>>>(a);          \
         CPAPR_LAUNCHED();                                                             \
         return {CPAPR_OK, ""};                                                        \
     }
@@ -458,10 +480,12 @@ Error dispatch_seg_n(int G, int RPL, const PhiArgs& a, dim3 grid, hipStream_t s)
     CPAPR_SEG_CASE(8, 2)
     CPAPR_SEG_CASE(16, 2)
     if constexpr (NM1 <= 3) {
-        CPAPR_SEG_CASE(4, 2)
-        CPAPR_SEG_CASE(4, 4)
         CPAPR_SEG_CASE(8, 4)
         CPAPR_SEG_CASE(16, 4)
+    }
+    if constexpr (NM1 <= 3 && KIND != kLoglik) {
+        CPAPR_SEG_CASE(4, 2)
+        CPAPR_SEG_CASE(4, 4)
         CPAPR_SEG_CASE(32, 2)
         CPAPR_SEG_CASE(32, 4)
     }
@@ -469,7 +493,7 @@ Error dispatch_seg_n(int G, int RPL, const PhiArgs& a, dim3 grid, hipStream_t s)
     return {CPAPR_EUNSUPPORTED, "no Phi kernel for this lane-group / rank-block shape and mode count"};
 }
 
-template <bool MIXED, bool MTTKRP>
+template <bool MIXED, int KIND>
 Error dispatch_seg(int G, int RPL, const PhiArgs& a, hipStream_t s)
 {
     const int NG = kBlock / G;
@@ -478,13 +502,13 @@ Error dispatch_seg(int G, int RPL, const PhiArgs& a, hipStream_t s)
     if (tiles > 0x7fffffff) return {CPAPR_EUNSUPPORTED, "too many tiles"};
     const dim3 grid((unsigned)tiles);
     switch (a.NM1) {
-        case 1: return dispatch_seg_n<1, MIXED, MTTKRP>(G, RPL, a, grid, s);
-        case 2: return dispatch_seg_n<2, MIXED, MTTKRP>(G, RPL, a, grid, s);
-        case 3: return dispatch_seg_n<3, MIXED, MTTKRP>(G, RPL, a, grid, s);
-        case 4: return dispatch_seg_n<4, MIXED, MTTKRP>(G, RPL, a, grid, s);
-        case 5: return dispatch_seg_n<5, MIXED, MTTKRP>(G, RPL, a, grid, s);
-        case 6: return dispatch_seg_n<6, MIXED, MTTKRP>(G, RPL, a, grid, s);
-        case 7: return dispatch_seg_n<7, MIXED, MTTKRP>(G, RPL, a, grid, s);
+        case 1: return dispatch_seg_n<1, MIXED, KIND>(G, RPL, a, grid, s);
+        case 2: return dispatch_seg_n<2, MIXED, KIND>(G, RPL, a, grid, s);
+        case 3: return dispatch_seg_n<3, MIXED, KIND>(G, RPL, a, grid, s);
+        case 4: return dispatch_seg_n<4, MIXED, KIND>(G, RPL, a, grid, s);
+        case 5: return dispatch_seg_n<5, MIXED, KIND>(G, RPL, a, grid, s);
+        case 6: return dispatch_seg_n<6, MIXED, KIND>(G, RPL, a, grid, s);
+        case 7: return dispatch_seg_n<7, MIXED, KIND>(G, RPL, a, grid, s);
         default: return {CPAPR_EUNSUPPORTED, "unsupported number of modes"};
     }
 }
@@ -526,7 +550,7 @@ PhiArgs make_args(const cpapr_plan* P, int mode, const double* B, const void* co
     PhiArgs a{};
     const PlanMode& pm = P->mode[mode];
     a.rows = pm.rows;
-    a.cidx = pm.cidx;
+    a.cofs = pm.cofs;
     a.vals = pm.vals;
     int j = 0;
     for (int m = 0; m < P->N; ++m)
@@ -610,7 +634,7 @@ Error launch_phi(const cpapr_plan* P, int mode, const double* B, const void* con
         return e;
     }
     prof_begin(mode, s);
-    Error e = mixed ? dispatch_seg<true, false>(G, RPL, a, s) : dispatch_seg<false, false>(G, RPL, a, s);
+    Error e = mixed ? dispatch_seg<true, kPhi>(G, RPL, a, s) : dispatch_seg<false, kPhi>(G, RPL, a, s);
     prof_end(s);
     return e;
 }
@@ -622,7 +646,23 @@ Error launch_mttkrp(const cpapr_plan* P, int mode, const double* const* A, doubl
     PhiArgs a = make_args(P, mode, nullptr, (const void* const*)A, 0.0, M, nullptr);
     Error e = zero_matrix(M, P->dims[mode] * (int64_t)P->R, s);
     if (e.code) return e;
-    return dispatch_seg<false, true>(G, RPL, a, s);
+    return dispatch_seg<false, kMttkrp>(G, RPL, a, s);
+}
+
+int64_t loglik_partials(int64_t nnz) { return cdiv(nnz, 512) + 1; }
+
+Error launch_loglik_terms(const cpapr_plan* P, const double* B, const double* const* A, double eps, double* partial,
+                          int* nparts, hipStream_t s)
+{
+    // Default shape for this rank (always instantiated), 512 nonzeros per tile.
+    const int G = resolve_group(P->R, 0, P->N - 1);
+    const int RPL = rank_block(P->R, G);
+    PhiArgs a = make_args(P, 0, B, (const void* const*)A, eps, partial, nullptr);
+    a.L = resolve_chunk(G, 0);
+    const int64_t tiles = cdiv(P->nnz, (int64_t)(kBlock / G) * a.L);
+    *nparts = (int)tiles;
+    if (tiles == 0) return {CPAPR_OK, ""};
+    return dispatch_seg<false, kLoglik>(G, RPL, a, s);
 }
 
 }  // namespace cpapr

@@ -205,10 +205,11 @@ __global__ __launch_bounds__(kBlock) void permute_keys_kernel(const int32_t* __r
 }
 
 // Copy sorted keys to the row array and gather values and the other modes'
-// coordinates through the permutation (perm == nullptr: identity).
+// factor row offsets (coordinate x R) through the permutation (perm == nullptr:
+// identity).
 __global__ __launch_bounds__(kBlock) void gather_sorted_kernel(
     const int32_t* __restrict__ idx, const double* __restrict__ vals, int64_t nnz, int N, int mode,
-    const int32_t* __restrict__ perm, int32_t* __restrict__ rows, int32_t* __restrict__ cidx,
+    const int32_t* __restrict__ perm, int R, int32_t* __restrict__ rows, uint32_t* __restrict__ cofs,
     double* __restrict__ svals)
 {
     for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * kBlock) {
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void gather_sorted_kernel(
         int j = 0;
         for (int m = 0; m < N; ++m) {
             if (m == mode) continue;
-            cidx[(int64_t)j * nnz + p] = idx[(int64_t)m * nnz + k];
+            cofs[(int64_t)j * nnz + p] = (uint32_t)idx[(int64_t)m * nnz + k] * (uint32_t)R;
             ++j;
         }
     }
@@ -385,7 +386,7 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
             Error e = passes(P->dims[n]);
             if (e.code) return e;
         }
-        gather_sorted_kernel<<<grid_for(nnz), kBlock, 0, s>>>(X->idx, X->vals, nnz, N, n, pin, pm.rows, pm.cidx,
+        gather_sorted_kernel<<<grid_for(nnz), kBlock, 0, s>>>(X->idx, X->vals, nnz, N, n, pin, P->R, pm.rows, pm.cofs,
                                                               pm.vals);
         CPAPR_LAUNCHED();
         const int gseg = std::min(grid_for(nnz), kSegPartials);
