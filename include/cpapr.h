@@ -180,6 +180,43 @@ int cpapr_loglik(cpapr_plan* plan, const double* lambda, const double* const* A,
  * without the divide. M device [I_n x R], overwritten. Stream-ordered. */
 int cpapr_mttkrp(cpapr_plan* plan, int32_t mode, const double* const* A, double* M, void* stream);
 
+/* ---- Batched Phi over many plans (work items) in persistent launches ----
+ *
+ * A batch is a set of slots; each slot is one Phi(n) work item: a plan, a mode
+ * and its operands (B, the factors, the Phi output). cpapr_batch_run computes
+ * Phi for every set slot with one list-driven fill/conversion launch and one
+ * persistent launch per shape class (lane group, rank block, number of other
+ * modes, precision) present, every launch sized to the device and reading its
+ * work list from device memory. With use_graph the sequence is captured once
+ * into a hipGraph and replayed; the graph stays valid when slots change, as
+ * long as no new shape class appears (then it is re-captured). Caller-provided
+ * workspace; the library allocates no device memory. Slots of one batch must
+ * write disjoint Phi buffers; a plan may appear in several slots. */
+typedef struct cpapr_batch cpapr_batch;
+
+/* Device workspace bytes for up to max_slots slots totalling up to max_tiles
+ * workgroup tiles (a slot of nnz nonzeros takes ceil(nnz / 512) tiles at the
+ * default chunk; cpapr_batch_tiles gives the exact count for a plan). */
+int cpapr_batch_workspace_size(int32_t max_slots, int64_t max_tiles, size_t* bytes);
+int64_t cpapr_batch_tiles(const cpapr_plan* plan);
+int cpapr_batch_create(int32_t max_slots, int64_t max_tiles, void* ws, size_t ws_bytes, cpapr_batch** out);
+int cpapr_batch_destroy(cpapr_batch* batch);
+
+/* Set slot `slot` (host-side only). B device [I_mode x R]; A host array of the
+ * plan's N device factor pointers (A[mode] unused); Phi device [I_mode x R],
+ * overwritten by cpapr_batch_run. The plan must stay alive while set. */
+int cpapr_batch_set(cpapr_batch* batch, int32_t slot, cpapr_plan* plan, int32_t mode, const double* B,
+                    const double* const* A, double* Phi);
+int cpapr_batch_clear(cpapr_batch* batch, int32_t slot);
+
+/* Upload the work lists of the set slots to the device (waits for `stream`).
+ * Required after cpapr_batch_set/clear and before cpapr_batch_run. */
+int cpapr_batch_commit(cpapr_batch* batch, void* stream);
+
+/* Phi for every set slot (stream-ordered, no host wait). use_graph != 0:
+ * replay the captured hipGraph (capturing it first when needed). */
+int cpapr_batch_run(cpapr_batch* batch, int32_t use_graph, void* stream);
+
 /* Kernel timing for measurement: while enabled, every Phi kernel launch is
  * bracketed by HIP events on its stream (up to `capacity` launches).
  * cpapr_prof_read waits for the recorded events and writes, per launch, the

@@ -79,6 +79,14 @@ def load():
         "cpapr_solve": (C.c_int, [vp, vp, P(vp), P(cpapr_stats), vp]),
         "cpapr_loglik": (C.c_int, [vp, vp, P(vp), dbl, P(dbl), vp]),
         "cpapr_mttkrp": (C.c_int, [vp, i32, P(vp), vp, vp]),
+        "cpapr_batch_workspace_size": (C.c_int, [i32, i64, P(C.c_size_t)]),
+        "cpapr_batch_tiles": (i64, [vp]),
+        "cpapr_batch_create": (C.c_int, [i32, i64, vp, C.c_size_t, P(vp)]),
+        "cpapr_batch_destroy": (C.c_int, [vp]),
+        "cpapr_batch_set": (C.c_int, [vp, i32, vp, i32, vp, P(vp), vp]),
+        "cpapr_batch_clear": (C.c_int, [vp, i32]),
+        "cpapr_batch_commit": (C.c_int, [vp, vp]),
+        "cpapr_batch_run": (C.c_int, [vp, i32, vp]),
         "cpapr_prof_enable": (C.c_int, [i32]),
         "cpapr_prof_disable": (C.c_int, []),
         "cpapr_prof_read": (C.c_int, [P(i32), P(C.c_float), i32]),
@@ -94,8 +102,9 @@ def load():
 
 EXPORTED = ("cpapr_params_default", "cpapr_plan_workspace_size", "cpapr_plan_create", "cpapr_plan_destroy",
             "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_phi", "cpapr_mu_inner", "cpapr_solve", "cpapr_loglik",
-            "cpapr_mttkrp", "cpapr_prof_enable", "cpapr_prof_disable", "cpapr_prof_read",
-            "cpapr_last_error")
+            "cpapr_mttkrp", "cpapr_batch_workspace_size", "cpapr_batch_tiles", "cpapr_batch_create",
+            "cpapr_batch_destroy", "cpapr_batch_set", "cpapr_batch_clear", "cpapr_batch_commit", "cpapr_batch_run",
+            "cpapr_prof_enable", "cpapr_prof_disable", "cpapr_prof_read", "cpapr_last_error")
 
 
 def _check(rc: int):
@@ -199,6 +208,79 @@ def cpapr_mttkrp(h, mode, A, M, stream=None):
     return _check(load().cpapr_mttkrp(h, mode, _ptr_array(A), M.data_ptr(), _stream(stream)))
 
 
+def cpapr_batch_workspace_size(max_slots: int, max_tiles: int) -> int:
+    n = C.c_size_t(0)
+    _check(load().cpapr_batch_workspace_size(max_slots, max_tiles, C.byref(n)))
+    return n.value
+
+
+def cpapr_batch_tiles(plan_handle) -> int:
+    return int(load().cpapr_batch_tiles(plan_handle))
+
+
+def cpapr_batch_create(max_slots, max_tiles, ws):
+    h = C.c_void_p()
+    _check(load().cpapr_batch_create(max_slots, max_tiles, ws.data_ptr(), ws.numel() * ws.element_size(), C.byref(h)))
+    return h
+
+
+def cpapr_batch_destroy(h):
+    return _check(load().cpapr_batch_destroy(h))
+
+
+def cpapr_batch_set(h, slot, plan_handle, mode, B, A, Phi):
+    return _check(load().cpapr_batch_set(h, slot, plan_handle, mode, B.data_ptr(), _ptr_array(A), Phi.data_ptr()))
+
+
+def cpapr_batch_clear(h, slot):
+    return _check(load().cpapr_batch_clear(h, slot))
+
+
+def cpapr_batch_commit(h, stream=None):
+    return _check(load().cpapr_batch_commit(h, _stream(stream)))
+
+
+def cpapr_batch_run(h, use_graph=False, stream=None):
+    return _check(load().cpapr_batch_run(h, 1 if use_graph else 0, _stream(stream)))
+
+
+class Batch:
+    """Slots of Phi work items run in persistent launches (optionally as a hipGraph)."""
+
+    def __init__(self, max_slots: int, max_tiles: int, device="cuda"):
+        import torch
+        self.max_slots, self.max_tiles = int(max_slots), int(max_tiles)
+        nbytes = cpapr_batch_workspace_size(self.max_slots, self.max_tiles)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.handle = cpapr_batch_create(self.max_slots, self.max_tiles, self.ws)
+        self._keep = {}
+
+    def set(self, slot, plan, mode, B, A, Phi):
+        cpapr_batch_set(self.handle, slot, plan.handle, mode, B, A, Phi)
+        self._keep[slot] = (plan, B, list(A), Phi)
+
+    def clear(self, slot):
+        cpapr_batch_clear(self.handle, slot)
+        self._keep.pop(slot, None)
+
+    def commit(self, stream=None):
+        cpapr_batch_commit(self.handle, stream)
+
+    def run(self, use_graph=False, stream=None):
+        cpapr_batch_run(self.handle, use_graph, stream)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            cpapr_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def cpapr_prof_enable(capacity: int):
     return _check(load().cpapr_prof_enable(capacity))
 
@@ -242,6 +324,9 @@ class Plan:
     def set_shape(self, group, chunk):
         cpapr_plan_set_shape(self.handle, group, chunk)
         self.params.group, self.params.chunk = group, chunk
+
+    def tiles(self):
+        return cpapr_batch_tiles(self.handle)
 
     def segments(self, mode):
         return cpapr_plan_segments(self.handle, mode)

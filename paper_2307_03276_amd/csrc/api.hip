@@ -207,6 +207,8 @@ Error read_state(const cpapr_plan* P, HostState* h, hipStream_t s)
 
 namespace cpapr {
 
+void set_last_error(const std::string& msg) { g_error = msg; }
+
 void prof_begin(int mode, hipStream_t s)
 {
     if (!g_prof.on || g_prof.count >= g_prof.cap) return;

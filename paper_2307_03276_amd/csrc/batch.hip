@@ -1,0 +1,346 @@
+// Batched Phi: host side of the slot lists, their device copies, and the
+// launch / hipGraph sequence (kernels in phi.hip).
+//
+// Device work lists: one BatchSlot per set slot (operands + first tile in its
+// shape class), a tile -> slot map per class, per-class offsets and tile
+// counts, and the fill / conversion list. Kernels read all of them from
+// device memory, so a captured graph replays correctly after a commit that
+// keeps the same set of shape classes.
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using cpapr::BatchCopy;
+using cpapr::BatchSlot;
+using cpapr::Error;
+
+namespace {
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+constexpr int kMaxClasses = 64;
+
+struct HostSlot {
+    bool set = false;
+    cpapr_plan* plan = nullptr;
+    int mode = 0;
+    const double* B = nullptr;
+    const double* A[CPAPR_MAX_MODES] = {};
+    double* Phi = nullptr;
+};
+
+struct Layout {
+    size_t slots, tile_map, class_off, class_ntiles, copies, ncopies, copy_total, total;
+};
+
+Layout layout(int max_slots, int64_t max_tiles)
+{
+    Layout L{};
+    size_t off = 0;
+    L.slots = off;
+    off += align256(sizeof(BatchSlot) * (size_t)max_slots);
+    L.tile_map = off;
+    off += align256(4 * (size_t)std::max<int64_t>(max_tiles, 1));
+    L.class_off = off;
+    off += align256(8 * kMaxClasses);
+    L.class_ntiles = off;
+    off += align256(8 * kMaxClasses);
+    L.copies = off;
+    off += align256(sizeof(BatchCopy) * (size_t)max_slots * CPAPR_MAX_MODES);
+    L.ncopies = off;
+    off += 256;
+    L.copy_total = off;
+    off += 256;
+    L.total = off;
+    return L;
+}
+
+int64_t plan_tiles(const cpapr_plan* P)
+{
+    const int NG = cpapr::kBlock / P->group;
+    return cdiv(P->nnz, (int64_t)NG * P->chunk);
+}
+
+}  // namespace
+
+struct cpapr_batch {
+    int max_slots;
+    int64_t max_tiles;
+    char* ws;
+    Layout L;
+    BatchSlot* d_slots;
+    int32_t* d_tile_map;
+    int64_t* d_class_off;
+    int64_t* d_class_ntiles;
+    BatchCopy* d_copies;
+    int32_t* d_ncopies;
+    int64_t* d_copy_total;
+    std::vector<HostSlot> slots;
+    bool committed = false;
+    std::vector<int> classes;           // classes with work at the last commit
+    int grid_cache[kMaxClasses] = {};   // persistent grid per class
+    int copy_grid = 0;
+    hipGraphExec_t graph = nullptr;
+    std::vector<int> graph_classes;     // classes captured in `graph`
+};
+
+namespace {
+
+int fail(int code, const std::string& msg)
+{
+    cpapr::set_last_error(msg);
+    return code;
+}
+
+int report(const Error& e)
+{
+    if (e.code) cpapr::set_last_error(e.msg);
+    return e.code;
+}
+
+Error enqueue(cpapr_batch* b, const std::vector<int>& classes, hipStream_t s)
+{
+    if (b->copy_grid <= 0) {
+        int dev = 0, cus = 0;
+        CPAPR_HIP(hipGetDevice(&dev));
+        CPAPR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        b->copy_grid = 4 * std::max(1, cus);
+    }
+    Error e = cpapr::launch_batch_elementwise(b->d_copies, b->d_ncopies, b->d_copy_total, b->copy_grid, s);
+    if (e.code) return e;
+    for (int c : classes) {
+        e = cpapr::launch_phi_batch(c, b->d_slots, b->d_tile_map, b->d_class_off, b->d_class_ntiles,
+                                    &b->grid_cache[c], s);
+        if (e.code) return e;
+    }
+    return {CPAPR_OK, ""};
+}
+
+}  // namespace
+
+extern "C" {
+
+int cpapr_batch_workspace_size(int32_t max_slots, int64_t max_tiles, size_t* bytes)
+{
+    if (max_slots < 1 || max_tiles < 0 || max_tiles > 0x7fffffffLL || !bytes)
+        return fail(CPAPR_EINVAL, "max_slots must be >= 1, max_tiles in [0, 2^31), bytes not NULL");
+    *bytes = layout(max_slots, max_tiles).total;
+    return CPAPR_OK;
+}
+
+int64_t cpapr_batch_tiles(const cpapr_plan* plan)
+{
+    if (!plan) return -1;
+    return plan_tiles(plan);
+}
+
+int cpapr_batch_create(int32_t max_slots, int64_t max_tiles, void* ws, size_t ws_bytes, cpapr_batch** out)
+{
+    try {
+        if (!out) return fail(CPAPR_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (max_slots < 1 || max_tiles < 0 || max_tiles > 0x7fffffffLL)
+            return fail(CPAPR_EINVAL, "max_slots must be >= 1 and max_tiles in [0, 2^31)");
+        const Layout L = layout(max_slots, max_tiles);
+        if (!ws || ((uintptr_t)ws & 255)) return fail(CPAPR_EWORKSPACE, "workspace missing or not 256-byte aligned");
+        if (ws_bytes < L.total) return fail(CPAPR_EWORKSPACE, "workspace too small");
+        cpapr_batch* b = new (std::nothrow) cpapr_batch();
+        if (!b) return fail(CPAPR_EINVAL, "out of host memory");
+        b->max_slots = max_slots;
+        b->max_tiles = max_tiles;
+        b->ws = (char*)ws;
+        b->L = L;
+        b->d_slots = (BatchSlot*)(b->ws + L.slots);
+        b->d_tile_map = (int32_t*)(b->ws + L.tile_map);
+        b->d_class_off = (int64_t*)(b->ws + L.class_off);
+        b->d_class_ntiles = (int64_t*)(b->ws + L.class_ntiles);
+        b->d_copies = (BatchCopy*)(b->ws + L.copies);
+        b->d_ncopies = (int32_t*)(b->ws + L.ncopies);
+        b->d_copy_total = (int64_t*)(b->ws + L.copy_total);
+        b->slots.resize(max_slots);
+        *out = b;
+        return CPAPR_OK;
+    } catch (...) {
+        return fail(CPAPR_EINVAL, "unexpected exception");
+    }
+}
+
+int cpapr_batch_destroy(cpapr_batch* batch)
+{
+    if (!batch) return CPAPR_OK;
+    if (batch->graph) hipGraphExecDestroy(batch->graph);
+    delete batch;
+    return CPAPR_OK;
+}
+
+int cpapr_batch_set(cpapr_batch* batch, int32_t slot, cpapr_plan* plan, int32_t mode, const double* B,
+                    const double* const* A, double* Phi)
+{
+    if (!batch || !plan) return fail(CPAPR_EINVAL, "batch or plan is NULL");
+    if (slot < 0 || slot >= batch->max_slots) return fail(CPAPR_EINVAL, "slot out of range");
+    if (mode < 0 || mode >= plan->N) return fail(CPAPR_EINVAL, "mode out of range");
+    if (!B || !Phi || !A) return fail(CPAPR_EINVAL, "B, A or Phi is NULL");
+    for (int m = 0; m < plan->N; ++m)
+        if (m != mode && !A[m]) return fail(CPAPR_EINVAL, "a factor pointer is NULL");
+    if (plan->params.variant == CPAPR_VARIANT_ATOMIC) return fail(CPAPR_EUNSUPPORTED, "batches run the segmented kernel");
+    const int rpl = cpapr::rank_block(plan->R, plan->group);
+    if (cpapr::batch_class_of(plan->group, rpl, plan->N - 1, plan->params.precision == CPAPR_MIXED) < 0)
+        return fail(CPAPR_EUNSUPPORTED, "no batched kernel for this plan's shape (lane group 4, 8 or 16; N <= 4)");
+    HostSlot& h = batch->slots[slot];
+    h.set = true;
+    h.plan = plan;
+    h.mode = mode;
+    h.B = B;
+    for (int m = 0; m < CPAPR_MAX_MODES; ++m) h.A[m] = m < plan->N ? A[m] : nullptr;
+    h.Phi = Phi;
+    batch->committed = false;
+    return CPAPR_OK;
+}
+
+int cpapr_batch_clear(cpapr_batch* batch, int32_t slot)
+{
+    if (!batch) return fail(CPAPR_EINVAL, "batch is NULL");
+    if (slot < 0 || slot >= batch->max_slots) return fail(CPAPR_EINVAL, "slot out of range");
+    batch->slots[slot] = HostSlot();
+    batch->committed = false;
+    return CPAPR_OK;
+}
+
+int cpapr_batch_commit(cpapr_batch* batch, void* stream)
+{
+    try {
+        if (!batch) return fail(CPAPR_EINVAL, "batch is NULL");
+        cpapr_batch* b = batch;
+        hipStream_t s = (hipStream_t)stream;
+        const int ncls = cpapr::batch_class_count();
+        std::vector<std::vector<int>> by_class(ncls);
+        for (int i = 0; i < b->max_slots; ++i) {
+            const HostSlot& h = b->slots[i];
+            if (!h.set) continue;
+            const cpapr_plan* P = h.plan;
+            const int c = cpapr::batch_class_of(P->group, cpapr::rank_block(P->R, P->group), P->N - 1,
+                                                P->params.precision == CPAPR_MIXED);
+            if (c < 0) return fail(CPAPR_EUNSUPPORTED, "slot with an unsupported shape");
+            by_class[c].push_back(i);
+        }
+        std::vector<BatchSlot> hs;
+        std::vector<int32_t> tmap;
+        std::vector<int64_t> coff(kMaxClasses, 0), cnt(kMaxClasses, 0);
+        std::vector<BatchCopy> copies;
+        int64_t copy_total = 0;
+        std::vector<int> classes;
+        for (int c = 0; c < ncls; ++c) {
+            coff[c] = (int64_t)tmap.size();
+            int64_t tiles = 0;
+            for (int i : by_class[c]) {
+                const HostSlot& h = b->slots[i];
+                const cpapr_plan* P = h.plan;
+                const bool mixed = P->params.precision == CPAPR_MIXED;
+                const void* fac[CPAPR_MAX_MODES] = {};
+                for (int m = 0; m < P->N; ++m) {
+                    if (m == h.mode) continue;
+                    if (mixed) {
+                        BatchCopy cp{h.A[m], P->f32[m], P->dims[m] * (int64_t)P->R, copy_total, 1, 0};
+                        copies.push_back(cp);
+                        copy_total += cp.n;
+                        fac[m] = P->f32[m];
+                    } else {
+                        fac[m] = h.A[m];
+                    }
+                }
+                BatchCopy z{nullptr, h.Phi, P->dims[h.mode] * (int64_t)P->R, copy_total, 0, 0};
+                copies.push_back(z);
+                copy_total += z.n;
+                BatchSlot bs{};
+                bs.args = cpapr::phi_args(P, h.mode, h.B, fac, P->params.eps, h.Phi);
+                bs.tile_begin = tiles;
+                const int64_t nt = plan_tiles(P);
+                const int32_t idx = (int32_t)hs.size();
+                hs.push_back(bs);
+                for (int64_t q = 0; q < nt; ++q) tmap.push_back(idx);
+                tiles += nt;
+                if ((int64_t)tmap.size() > b->max_tiles) return fail(CPAPR_EWORKSPACE, "more tiles than max_tiles");
+            }
+            cnt[c] = tiles;
+            if (tiles > 0) classes.push_back(c);
+        }
+        const int32_t ncopies = (int32_t)copies.size();
+        if (!hs.empty()) {
+            if (hipMemcpyAsync(b->d_slots, hs.data(), sizeof(BatchSlot) * hs.size(), hipMemcpyHostToDevice, s) !=
+                hipSuccess)
+                return fail(CPAPR_EHIP, "upload of batch slots failed");
+        }
+        if (!tmap.empty() &&
+            hipMemcpyAsync(b->d_tile_map, tmap.data(), 4 * tmap.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(CPAPR_EHIP, "upload of the tile map failed");
+        if (hipMemcpyAsync(b->d_class_off, coff.data(), 8 * kMaxClasses, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(b->d_class_ntiles, cnt.data(), 8 * kMaxClasses, hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(CPAPR_EHIP, "upload of class tables failed");
+        if (!copies.empty() && hipMemcpyAsync(b->d_copies, copies.data(), sizeof(BatchCopy) * copies.size(),
+                                              hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(CPAPR_EHIP, "upload of the fill list failed");
+        if (hipMemcpyAsync(b->d_ncopies, &ncopies, 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(b->d_copy_total, &copy_total, 8, hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(CPAPR_EHIP, "upload of list sizes failed");
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(CPAPR_EHIP, "stream synchronisation failed");
+        b->classes = classes;
+        b->committed = true;
+        return CPAPR_OK;
+    } catch (...) {
+        return fail(CPAPR_EINVAL, "unexpected exception");
+    }
+}
+
+int cpapr_batch_run(cpapr_batch* batch, int32_t use_graph, void* stream)
+{
+    try {
+        if (!batch) return fail(CPAPR_EINVAL, "batch is NULL");
+        cpapr_batch* b = batch;
+        if (!b->committed) return fail(CPAPR_EINVAL, "batch not committed since the last change");
+        hipStream_t s = (hipStream_t)stream;
+        if (!use_graph) return report(enqueue(b, b->classes, s));
+        bool covered = b->graph != nullptr;
+        for (int c : b->classes)
+            if (std::find(b->graph_classes.begin(), b->graph_classes.end(), c) == b->graph_classes.end())
+                covered = false;
+        if (!covered) {
+            if (s == nullptr) return fail(CPAPR_EINVAL, "graph capture needs a non-null stream");
+            if (b->graph) {
+                hipGraphExecDestroy(b->graph);
+                b->graph = nullptr;
+            }
+            // First launches outside capture so that occupancy queries and lazy
+            // kernel loading happen before the graph is recorded.
+            Error e = enqueue(b, b->classes, s);
+            if (e.code) return report(e);
+            if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return fail(CPAPR_EHIP, "hipStreamBeginCapture failed");
+            e = enqueue(b, b->classes, s);
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(s, &g);
+            if (e.code) {
+                if (g) hipGraphDestroy(g);
+                return report(e);
+            }
+            if (ec != hipSuccess || !g) return fail(CPAPR_EHIP, "hipStreamEndCapture failed");
+            const hipError_t ei = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (ei != hipSuccess) {
+                b->graph = nullptr;
+                return fail(CPAPR_EHIP, "hipGraphInstantiate failed");
+            }
+            b->graph_classes = b->classes;
+            return CPAPR_OK;  // the direct launch above already computed this commit
+        }
+        if (hipGraphLaunch(b->graph, s) != hipSuccess) return fail(CPAPR_EHIP, "hipGraphLaunch failed");
+        return CPAPR_OK;
+    } catch (...) {
+        return fail(CPAPR_EINVAL, "unexpected exception");
+    }
+}
+
+}  // extern "C"

@@ -43,6 +43,41 @@ struct PlanMode {
     int64_t segments;
 };
 
+constexpr int kMaxOther = CPAPR_MAX_MODES - 1;
+
+// Operands of one Phi launch over one sorted copy (kernel argument).
+struct PhiArgs {
+    const int32_t* rows;
+    const uint32_t* cofs;
+    const double* vals;
+    const void* fac[kMaxOther];
+    const double* B;
+    double* Phi;
+    const int* done;
+    int64_t nnz;
+    int R;
+    int NM1;
+    int L;
+    double eps;
+};
+
+// One work item of a batched launch: operands and its first tile in the
+// class's tile space.
+struct alignas(16) BatchSlot {
+    PhiArgs args;
+    int64_t tile_begin;
+};
+
+// One list entry of the batched fill / conversion kernel.
+struct alignas(16) BatchCopy {
+    const double* src;
+    void* dst;
+    int64_t n;
+    int64_t begin;  // offset in the concatenated element space
+    int32_t op;     // 0: zero FP64 dst; 1: dst (FP32) = src (FP64)
+    int32_t pad;
+};
+
 }  // namespace cpapr
 
 struct cpapr_plan {
@@ -85,6 +120,15 @@ Error launch_phi(const cpapr_plan* P, int mode, const double* B, const void* con
                  double eps, double* Phi, const int* done, hipStream_t s);
 Error launch_mttkrp(const cpapr_plan* P, int mode, const double* const* A, double* M, hipStream_t s);
 
+// ---- batched Phi (phi.hip; host side in batch.hip) ----
+int batch_class_count();
+int batch_class_of(int G, int RPL, int NM1, bool mixed);  // -1: no batched kernel for this shape
+Error launch_phi_batch(int cls, const BatchSlot* slots, const int32_t* tile_map, const int64_t* class_off,
+                       const int64_t* class_ntiles, int* grid_cache, hipStream_t s);
+Error launch_batch_elementwise(const BatchCopy* items, const int32_t* nitems_dev, const int64_t* total_dev, int grid,
+                               hipStream_t s);
+PhiArgs phi_args(const cpapr_plan* P, int mode, const double* B, const void* const* fac, double eps, double* Phi);
+
 // ---- elementwise and reduction kernels (mu.hip) ----
 Error launch_fill(double* p, int64_t n, double v, const int* done, hipStream_t s);
 Error launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
@@ -105,6 +149,9 @@ Error launch_loglik(const cpapr_plan* P, const double* lam, const double* const*
 Error launch_loglik_terms(const cpapr_plan* P, const double* B, const double* const* A, double eps, double* partial,
                           int* nparts, hipStream_t s);
 int64_t loglik_partials(int64_t nnz);
+
+// ---- error message of the last failing entry point (api.hip, thread-local) ----
+void set_last_error(const std::string& msg);
 
 // ---- profiling hooks (api.hip) ----
 void prof_begin(int mode, hipStream_t s);

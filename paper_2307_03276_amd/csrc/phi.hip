@@ -25,29 +25,13 @@
 // Mixed precision: factors and pi are FP32; products and sums carry an FP32
 // error term (TwoProd by FMA, Knuth TwoSum), and Phi partials leave registers
 // as FP64 hi + lo.
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.hpp"
 
 namespace cpapr {
 namespace {
-
-constexpr int kMaxOther = CPAPR_MAX_MODES - 1;
-
-struct PhiArgs {
-    const int32_t* rows;
-    const uint32_t* cofs;
-    const double* vals;
-    const void* fac[kMaxOther];
-    const double* B;
-    double* Phi;
-    const int* done;
-    int64_t nnz;
-    int R;
-    int NM1;
-    int L;
-    double eps;
-};
 
 __device__ __forceinline__ int xcd_remap(int bid, int nb)
 {
@@ -216,22 +200,32 @@ constexpr int gather_depth()
     return NM1 * RPL <= 2 ? 4 : (NM1 * RPL <= 4 ? 2 : 1);
 }
 
+// LDS of one workgroup tile: head/tail partial rows, their row ids, and the
+// staged nonzeros of every lane group.
+template <int G, int RPL, int NM1>
+struct TileShared {
+    static constexpr int NG = kBlock / G;
+    static constexpr int BATCH = G >= 8 ? G : 8;  // nonzeros staged per lane group per round
+    double part[2 * NG][G * RPL];
+    int prow[2 * NG];
+    Staged<NM1> stage[NG * BATCH];
+};
+
+// One workgroup tile of consecutive sorted nonzeros (tile index `tile` of the
+// operand set `a`).
 template <int G, int RPL, int NM1, bool MIXED, int KIND>
-__global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
+__device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileShared<G, RPL, NM1>& sh)
 {
     using T = typename std::conditional<MIXED, float, double>::type;
     constexpr int NG = kBlock / G;
     constexpr int W = G * RPL;
     constexpr int U = gather_depth<NM1, RPL>();
-    constexpr int BATCH = G >= 8 ? G : 8;  // nonzeros staged per lane group per round
-    constexpr int EPL = BATCH / G;         // staged entries loaded by each lane
-    __shared__ double part[2 * NG][W];
-    __shared__ int prow[2 * NG];
-    __shared__ Staged<NM1> stage[NG * BATCH];
+    constexpr int BATCH = TileShared<G, RPL, NM1>::BATCH;
+    constexpr int EPL = BATCH / G;  // staged entries loaded by each lane
+    auto& part = sh.part;
+    auto& prow = sh.prow;
+    auto& stage = sh.stage;
 
-    if (a.done != nullptr && *a.done) return;
-
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int t = threadIdx.x;
     const int g = t / G;
     const int lane = t % G;
@@ -412,6 +406,68 @@ __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
             }
         }
         if (run >= 0) emit(run, v);
+    }
+}
+
+template <int G, int RPL, int NM1, bool MIXED, int KIND>
+__global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
+{
+    __shared__ TileShared<G, RPL, NM1> sh;
+    if (a.done != nullptr && *a.done) return;
+    phi_tile<G, RPL, NM1, MIXED, KIND>(a, xcd_remap(blockIdx.x, gridDim.x), sh);
+}
+
+// Persistent Phi over a batch of operand sets of one shape class: the grid is
+// sized to the device, the tile count and the tile -> slot map are read from
+// device memory (so a captured graph stays valid when the batch changes), and
+// each workgroup walks a contiguous, XCD-mapped range of tiles.
+template <int G, int RPL, int NM1, bool MIXED>
+__global__ __launch_bounds__(kBlock) void phi_batch_kernel(const BatchSlot* __restrict__ slots,
+                                                           const int32_t* __restrict__ tile_map,
+                                                           const int64_t* __restrict__ class_off,
+                                                           const int64_t* __restrict__ class_ntiles, int cls)
+{
+    __shared__ TileShared<G, RPL, NM1> sh;
+    const int64_t total = class_ntiles[cls];
+    const int32_t* __restrict__ tile_slot = tile_map + class_off[cls];
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    const int64_t pos = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t t0 = pos * per, t1 = min(t0 + per, total);
+    for (int64_t tt = t0; tt < t1; ++tt) {
+        const int si = tile_slot[tt];
+        const PhiArgs a = slots[si].args;
+        __syncthreads();  // LDS of the previous tile is no longer read
+        phi_tile<G, RPL, NM1, MIXED, kPhi>(a, tt - slots[si].tile_begin, sh);
+    }
+}
+
+// List-driven fills / conversions for a batch: op 0 zeroes dst (FP64), op 1
+// rounds src (FP64) into dst (FP32). Workgroup b takes a contiguous element range
+// of the concatenated lists and walks the items it spans.
+__global__ __launch_bounds__(kBlock) void batch_elementwise_kernel(const BatchCopy* __restrict__ items,
+                                                                   const int32_t* __restrict__ nitems_dev,
+                                                                   const int64_t* __restrict__ total_dev)
+{
+    const int nitems = *nitems_dev;
+    const int64_t total = *total_dev;
+    const int64_t per = ((total + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
+    const int64_t e0 = blockIdx.x * per, e1 = min(e0 + per, total);
+    if (e0 >= e1) return;
+    int lo = 0, hi = nitems - 1;  // last item with begin <= e0
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (items[mid].begin <= e0) lo = mid; else hi = mid - 1;
+    }
+    for (int it = lo; it < nitems && items[it].begin < e1; ++it) {
+        const BatchCopy c = items[it];
+        const int64_t a0 = max(e0, c.begin) - c.begin, a1 = min(e1, c.begin + c.n) - c.begin;
+        if (c.op == 0) {
+            double* d = (double*)c.dst;
+            for (int64_t i = a0 + threadIdx.x; i < a1; i += kBlock) d[i] = 0.0;
+        } else {
+            float* d = (float*)c.dst;
+            for (int64_t i = a0 + threadIdx.x; i < a1; i += kBlock) d[i] = (float)c.src[i];
+        }
     }
 }
 
@@ -650,6 +706,83 @@ Error launch_mttkrp(const cpapr_plan* P, int mode, const double* const* A, doubl
 }
 
 int64_t loglik_partials(int64_t nnz) { return cdiv(nnz, 512) + 1; }
+
+// ---- batched launches ----
+
+namespace {
+
+template <int G, int RPL, int NM1, bool MIXED>
+Error batch_launch_t(const BatchSlot* slots, const int32_t* tile_map, const int64_t* class_off,
+                     const int64_t* class_ntiles, int cls, int* grid_cache, hipStream_t s)
+{
+    if (*grid_cache <= 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        CPAPR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, phi_batch_kernel<G, RPL, NM1, MIXED>,
+                                                               kBlock, 0));
+        CPAPR_HIP(hipGetDevice(&dev));
+        CPAPR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        *grid_cache = std::max(1, per_cu) * std::max(1, cus);
+    }
+    phi_batch_kernel<G, RPL, NM1, MIXED><<<*grid_cache, kBlock, 0, s>>>(slots, tile_map, class_off, class_ntiles, cls);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+struct BatchShape {
+    int G, RPL, NM1;
+    bool mixed;
+};
+
+constexpr BatchShape kBatchShapes[] = {
+#define CPAPR_BS(GG, RR)                                                                              \
+    {GG, RR, 1, false}, {GG, RR, 2, false}, {GG, RR, 3, false}, {GG, RR, 1, true}, {GG, RR, 2, true}, \
+        {GG, RR, 3, true}
+    CPAPR_BS(4, 1), CPAPR_BS(8, 1), CPAPR_BS(8, 2), CPAPR_BS(8, 4), CPAPR_BS(16, 1), CPAPR_BS(16, 2), CPAPR_BS(16, 4)
+#undef CPAPR_BS
+};
+
+}  // namespace
+
+int batch_class_count() { return (int)(sizeof(kBatchShapes) / sizeof(kBatchShapes[0])); }
+
+int batch_class_of(int G, int RPL, int NM1, bool mixed)
+{
+    for (int c = 0; c < batch_class_count(); ++c) {
+        const BatchShape& b = kBatchShapes[c];
+        if (b.G == G && b.RPL == RPL && b.NM1 == NM1 && b.mixed == mixed) return c;
+    }
+    return -1;
+}
+
+Error launch_phi_batch(int cls, const BatchSlot* slots, const int32_t* tile_map, const int64_t* class_off,
+                       const int64_t* class_ntiles, int* grid_cache, hipStream_t s)
+{
+    if (cls < 0 || cls >= batch_class_count()) return {CPAPR_EINVAL, "bad batch class"};
+    const BatchShape& b = kBatchShapes[cls];
+#define CPAPR_BL(GG, RR, NN, MM)                                                                     \
+    if (b.G == GG && b.RPL == RR && b.NM1 == NN && b.mixed == MM)                                    \
+        return batch_launch_t<GG, RR, NN, MM>(slots, tile_map, class_off, class_ntiles, cls, grid_cache, s);
+#define CPAPR_BL6(GG, RR)                                                                            \
+    CPAPR_BL(GG, RR, 1, false) CPAPR_BL(GG, RR, 2, false) CPAPR_BL(GG, RR, 3, false)                 \
+    CPAPR_BL(GG, RR, 1, true) CPAPR_BL(GG, RR, 2, true) CPAPR_BL(GG, RR, 3, true)
+    CPAPR_BL6(4, 1) CPAPR_BL6(8, 1) CPAPR_BL6(8, 2) CPAPR_BL6(8, 4) CPAPR_BL6(16, 1) CPAPR_BL6(16, 2) CPAPR_BL6(16, 4)
+#undef CPAPR_BL6
+#undef CPAPR_BL
+    return {CPAPR_EUNSUPPORTED, "no batched Phi kernel for this shape"};
+}
+
+Error launch_batch_elementwise(const BatchCopy* items, const int32_t* nitems_dev, const int64_t* total_dev, int grid,
+                               hipStream_t s)
+{
+    batch_elementwise_kernel<<<grid, kBlock, 0, s>>>(items, nitems_dev, total_dev);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+PhiArgs phi_args(const cpapr_plan* P, int mode, const double* B, const void* const* fac, double eps, double* Phi)
+{
+    return make_args(P, mode, B, fac, eps, Phi, nullptr);
+}
 
 Error launch_loglik_terms(const cpapr_plan* P, const double* B, const double* const* A, double eps, double* partial,
                           int* nparts, hipStream_t s)
