@@ -204,9 +204,12 @@ int cpapr_batch_destroy(cpapr_batch* batch);
 
 /* Set slot `slot` (host-side only). B device [I_mode x R]; A host array of the
  * plan's N device factor pointers (A[mode] unused); Phi device [I_mode x R],
- * overwritten by cpapr_batch_run. The plan must stay alive while set. */
+ * overwritten by cpapr_batch_run. The plan must stay alive while set. flags:
+ * CPAPR_BATCH_F32_CURRENT = the plan's FP32 factor copies already hold A
+ * (mixed precision; see cpapr_plan_sync_f32), so runs skip the conversion. */
+#define CPAPR_BATCH_F32_CURRENT 1
 int cpapr_batch_set(cpapr_batch* batch, int32_t slot, cpapr_plan* plan, int32_t mode, const double* B,
-                    const double* const* A, double* Phi);
+                    const double* const* A, double* Phi, int32_t flags);
 int cpapr_batch_clear(cpapr_batch* batch, int32_t slot);
 
 /* Upload the work lists of the set slots to the device (waits for `stream`).
@@ -216,6 +219,32 @@ int cpapr_batch_commit(cpapr_batch* batch, void* stream);
 /* Phi for every set slot (stream-ordered, no host wait). use_graph != 0:
  * replay the captured hipGraph (capturing it first when needed). */
 int cpapr_batch_run(cpapr_batch* batch, int32_t use_graph, void* stream);
+
+/* One MU inner step for every set slot, after cpapr_batch_run: viol = max
+ * |min(B, 1 - Phi)| per slot; B <- B .* Phi unless the slot plan's tol > 0 and
+ * viol < tol (the inner-loop test of cpapr_mu_inner). Stream-ordered. */
+int cpapr_batch_mu(cpapr_batch* batch, void* stream);
+
+/* Per-slot result of the last cpapr_batch_mu (host arrays of max_slots
+ * entries; entries of unset slots are unspecified). Waits for `stream`. */
+int cpapr_batch_status(cpapr_batch* batch, double* viol, int32_t* updated, void* stream);
+
+/* The per-mode steps of Algorithm 1 around the inner loop, for callers that
+ * interleave many solves (cpapr_solve runs the same steps):
+ * cpapr_mode_begin: from the second outer iteration on (outer_iter > 1,
+ *   phi_prev != NULL) raise entries of A_mode below kappa_tol whose previous
+ *   Phi exceeds 1 by kappa; then B = A_mode diag(lambda).
+ * cpapr_mode_end: lambda = column sums of B; A_mode = B diag(lambda)^-1 (and
+ *   the plan's FP32 copy of A_mode in mixed precision).
+ * Device pointers: lambda [R], A_mode / phi_prev / B [I_mode x R].
+ * Stream-ordered. */
+int cpapr_mode_begin(cpapr_plan* plan, int32_t mode, int32_t outer_iter, const double* lambda, double* A_mode,
+                     const double* phi_prev, double* B, void* stream);
+int cpapr_mode_end(cpapr_plan* plan, int32_t mode, const double* B, double* lambda, double* A_mode, void* stream);
+
+/* Mixed precision: refresh the plan's FP32 copies of all N factors from A
+ * (host array of N device pointers). No-op in FP64. Stream-ordered. */
+int cpapr_plan_sync_f32(cpapr_plan* plan, const double* const* A, void* stream);
 
 /* Kernel timing for measurement: while enabled, every Phi kernel launch is
  * bracketed by HIP events on its stream (up to `capacity` launches).

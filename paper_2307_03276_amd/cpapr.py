@@ -83,7 +83,12 @@ def load():
         "cpapr_batch_tiles": (i64, [vp]),
         "cpapr_batch_create": (C.c_int, [i32, i64, vp, C.c_size_t, P(vp)]),
         "cpapr_batch_destroy": (C.c_int, [vp]),
-        "cpapr_batch_set": (C.c_int, [vp, i32, vp, i32, vp, P(vp), vp]),
+        "cpapr_batch_set": (C.c_int, [vp, i32, vp, i32, vp, P(vp), vp, i32]),
+        "cpapr_batch_mu": (C.c_int, [vp, vp]),
+        "cpapr_batch_status": (C.c_int, [vp, P(dbl), P(i32), vp]),
+        "cpapr_mode_begin": (C.c_int, [vp, i32, i32, vp, vp, vp, vp, vp]),
+        "cpapr_mode_end": (C.c_int, [vp, i32, vp, vp, vp, vp]),
+        "cpapr_plan_sync_f32": (C.c_int, [vp, P(vp), vp]),
         "cpapr_batch_clear": (C.c_int, [vp, i32]),
         "cpapr_batch_commit": (C.c_int, [vp, vp]),
         "cpapr_batch_run": (C.c_int, [vp, i32, vp]),
@@ -104,6 +109,7 @@ EXPORTED = ("cpapr_params_default", "cpapr_plan_workspace_size", "cpapr_plan_cre
             "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_phi", "cpapr_mu_inner", "cpapr_solve", "cpapr_loglik",
             "cpapr_mttkrp", "cpapr_batch_workspace_size", "cpapr_batch_tiles", "cpapr_batch_create",
             "cpapr_batch_destroy", "cpapr_batch_set", "cpapr_batch_clear", "cpapr_batch_commit", "cpapr_batch_run",
+            "cpapr_batch_mu", "cpapr_batch_status", "cpapr_mode_begin", "cpapr_mode_end", "cpapr_plan_sync_f32",
             "cpapr_prof_enable", "cpapr_prof_disable", "cpapr_prof_read", "cpapr_last_error")
 
 
@@ -228,8 +234,37 @@ def cpapr_batch_destroy(h):
     return _check(load().cpapr_batch_destroy(h))
 
 
-def cpapr_batch_set(h, slot, plan_handle, mode, B, A, Phi):
-    return _check(load().cpapr_batch_set(h, slot, plan_handle, mode, B.data_ptr(), _ptr_array(A), Phi.data_ptr()))
+CPAPR_BATCH_F32_CURRENT = 1
+
+
+def cpapr_batch_set(h, slot, plan_handle, mode, B, A, Phi, flags=0):
+    return _check(load().cpapr_batch_set(h, slot, plan_handle, mode, B.data_ptr(), _ptr_array(A), Phi.data_ptr(),
+                                         flags))
+
+
+def cpapr_batch_mu(h, stream=None):
+    return _check(load().cpapr_batch_mu(h, _stream(stream)))
+
+
+def cpapr_batch_status(h, max_slots, stream=None):
+    viol = (C.c_double * max_slots)()
+    upd = (C.c_int32 * max_slots)()
+    _check(load().cpapr_batch_status(h, viol, upd, _stream(stream)))
+    return list(viol), list(upd)
+
+
+def cpapr_mode_begin(h, mode, outer_iter, lam, A_mode, phi_prev, B, stream=None):
+    return _check(load().cpapr_mode_begin(h, mode, outer_iter, lam.data_ptr(), A_mode.data_ptr(),
+                                          None if phi_prev is None else phi_prev.data_ptr(), B.data_ptr(),
+                                          _stream(stream)))
+
+
+def cpapr_mode_end(h, mode, B, lam, A_mode, stream=None):
+    return _check(load().cpapr_mode_end(h, mode, B.data_ptr(), lam.data_ptr(), A_mode.data_ptr(), _stream(stream)))
+
+
+def cpapr_plan_sync_f32(h, A, stream=None):
+    return _check(load().cpapr_plan_sync_f32(h, _ptr_array(A), _stream(stream)))
 
 
 def cpapr_batch_clear(h, slot):
@@ -255,8 +290,8 @@ class Batch:
         self.handle = cpapr_batch_create(self.max_slots, self.max_tiles, self.ws)
         self._keep = {}
 
-    def set(self, slot, plan, mode, B, A, Phi):
-        cpapr_batch_set(self.handle, slot, plan.handle, mode, B, A, Phi)
+    def set(self, slot, plan, mode, B, A, Phi, flags=0):
+        cpapr_batch_set(self.handle, slot, plan.handle, mode, B, A, Phi, flags)
         self._keep[slot] = (plan, B, list(A), Phi)
 
     def clear(self, slot):
@@ -268,6 +303,12 @@ class Batch:
 
     def run(self, use_graph=False, stream=None):
         cpapr_batch_run(self.handle, use_graph, stream)
+
+    def mu(self, stream=None):
+        cpapr_batch_mu(self.handle, stream)
+
+    def status(self, stream=None):
+        return cpapr_batch_status(self.handle, self.max_slots, stream)
 
     def close(self):
         if getattr(self, "handle", None) is not None:

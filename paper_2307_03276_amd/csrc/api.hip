@@ -480,6 +480,42 @@ int cpapr_solve(cpapr_plan* plan, double* lambda, double* const* A, cpapr_stats*
     }
 }
 
+int cpapr_mode_begin(cpapr_plan* plan, int32_t mode, int32_t outer_iter, const double* lambda, double* A_mode,
+                     const double* phi_prev, double* B, void* stream)
+{
+    Error e = check_plan_call(plan, mode);
+    if (e.code) return report(e);
+    if (!lambda || !A_mode || !B) return fail(CPAPR_EINVAL, "lambda, A_mode or B is NULL");
+    const bool shift = outer_iter > 1 && phi_prev != nullptr;
+    return report(cpapr::launch_shift_scale(A_mode, phi_prev, lambda, B, plan->dims[mode], plan->R, plan->params.kappa,
+                                            plan->params.kappa_tol, shift, (hipStream_t)stream));
+}
+
+int cpapr_mode_end(cpapr_plan* plan, int32_t mode, const double* B, double* lambda, double* A_mode, void* stream)
+{
+    Error e = check_plan_call(plan, mode);
+    if (e.code) return report(e);
+    if (!lambda || !A_mode || !B) return fail(CPAPR_EINVAL, "lambda, A_mode or B is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    e = cpapr::launch_colsum(B, plan->dims[mode], plan->R, plan->partial, lambda, s);
+    if (e.code) return report(e);
+    float* a32 = plan->params.precision == CPAPR_MIXED ? plan->f32[mode] : nullptr;
+    return report(cpapr::launch_normalize(B, lambda, A_mode, a32, plan->dims[mode], plan->R, s));
+}
+
+int cpapr_plan_sync_f32(cpapr_plan* plan, const double* const* A, void* stream)
+{
+    if (!plan) return fail(CPAPR_EINVAL, "plan is NULL");
+    if (plan->params.precision != CPAPR_MIXED) return CPAPR_OK;
+    Error e = check_factors(plan, A, -1);
+    if (e.code) return report(e);
+    for (int m = 0; m < plan->N; ++m) {
+        e = cpapr::launch_to_f32(A[m], plan->f32[m], plan->dims[m] * (int64_t)plan->R, (hipStream_t)stream);
+        if (e.code) return report(e);
+    }
+    return CPAPR_OK;
+}
+
 int cpapr_loglik(cpapr_plan* plan, const double* lambda, const double* const* A, double eps, double* out,
                  void* stream)
 {

@@ -26,6 +26,7 @@ constexpr int kMaxClasses = 64;
 
 struct HostSlot {
     bool set = false;
+    int flags = 0;
     cpapr_plan* plan = nullptr;
     int mode = 0;
     const double* B = nullptr;
@@ -34,7 +35,8 @@ struct HostSlot {
 };
 
 struct Layout {
-    size_t slots, tile_map, class_off, class_ntiles, copies, ncopies, copy_total, total;
+    size_t slots, tile_map, class_off, class_ntiles, copies, ncopies, copy_total;
+    size_t mu, nmu, mu_total, viol, viol_out, updated, total;
 };
 
 Layout layout(int max_slots, int64_t max_tiles)
@@ -55,6 +57,18 @@ Layout layout(int max_slots, int64_t max_tiles)
     off += 256;
     L.copy_total = off;
     off += 256;
+    L.mu = off;
+    off += align256(sizeof(cpapr::BatchMu) * (size_t)max_slots);
+    L.nmu = off;
+    off += 256;
+    L.mu_total = off;
+    off += 256;
+    L.viol = off;
+    off += align256(8 * (size_t)cpapr::kMuSpread * max_slots);
+    L.viol_out = off;
+    off += align256(8 * (size_t)max_slots);
+    L.updated = off;
+    off += align256(4 * (size_t)max_slots);
     L.total = off;
     return L;
 }
@@ -79,6 +93,12 @@ struct cpapr_batch {
     BatchCopy* d_copies;
     int32_t* d_ncopies;
     int64_t* d_copy_total;
+    cpapr::BatchMu* d_mu;
+    int32_t* d_nmu;
+    int64_t* d_mu_total;
+    unsigned long long* d_viol;
+    double* d_viol_out;
+    int32_t* d_updated;
     std::vector<HostSlot> slots;
     bool committed = false;
     std::vector<int> classes;           // classes with work at the last commit
@@ -161,6 +181,12 @@ int cpapr_batch_create(int32_t max_slots, int64_t max_tiles, void* ws, size_t ws
         b->d_copies = (BatchCopy*)(b->ws + L.copies);
         b->d_ncopies = (int32_t*)(b->ws + L.ncopies);
         b->d_copy_total = (int64_t*)(b->ws + L.copy_total);
+        b->d_mu = (cpapr::BatchMu*)(b->ws + L.mu);
+        b->d_nmu = (int32_t*)(b->ws + L.nmu);
+        b->d_mu_total = (int64_t*)(b->ws + L.mu_total);
+        b->d_viol = (unsigned long long*)(b->ws + L.viol);
+        b->d_viol_out = (double*)(b->ws + L.viol_out);
+        b->d_updated = (int32_t*)(b->ws + L.updated);
         b->slots.resize(max_slots);
         *out = b;
         return CPAPR_OK;
@@ -178,7 +204,7 @@ int cpapr_batch_destroy(cpapr_batch* batch)
 }
 
 int cpapr_batch_set(cpapr_batch* batch, int32_t slot, cpapr_plan* plan, int32_t mode, const double* B,
-                    const double* const* A, double* Phi)
+                    const double* const* A, double* Phi, int32_t flags)
 {
     if (!batch || !plan) return fail(CPAPR_EINVAL, "batch or plan is NULL");
     if (slot < 0 || slot >= batch->max_slots) return fail(CPAPR_EINVAL, "slot out of range");
@@ -190,8 +216,10 @@ int cpapr_batch_set(cpapr_batch* batch, int32_t slot, cpapr_plan* plan, int32_t 
     const int rpl = cpapr::rank_block(plan->R, plan->group);
     if (cpapr::batch_class_of(plan->group, rpl, plan->N - 1, plan->params.precision == CPAPR_MIXED) < 0)
         return fail(CPAPR_EUNSUPPORTED, "no batched kernel for this plan's shape (lane group 4, 8 or 16; N <= 4)");
+    if (flags & ~CPAPR_BATCH_F32_CURRENT) return fail(CPAPR_EINVAL, "unknown flags");
     HostSlot& h = batch->slots[slot];
     h.set = true;
+    h.flags = flags;
     h.plan = plan;
     h.mode = mode;
     h.B = B;
@@ -244,9 +272,11 @@ int cpapr_batch_commit(cpapr_batch* batch, void* stream)
                 for (int m = 0; m < P->N; ++m) {
                     if (m == h.mode) continue;
                     if (mixed) {
-                        BatchCopy cp{h.A[m], P->f32[m], P->dims[m] * (int64_t)P->R, copy_total, 1, 0};
-                        copies.push_back(cp);
-                        copy_total += cp.n;
+                        if (!(h.flags & CPAPR_BATCH_F32_CURRENT)) {
+                            BatchCopy cp{h.A[m], P->f32[m], P->dims[m] * (int64_t)P->R, copy_total, 1, 0};
+                            copies.push_back(cp);
+                            copy_total += cp.n;
+                        }
                         fac[m] = P->f32[m];
                     } else {
                         fac[m] = h.A[m];
@@ -269,6 +299,24 @@ int cpapr_batch_commit(cpapr_batch* batch, void* stream)
             if (tiles > 0) classes.push_back(c);
         }
         const int32_t ncopies = (int32_t)copies.size();
+        std::vector<cpapr::BatchMu> mus;
+        int64_t mu_total = 0;
+        for (int i = 0; i < b->max_slots; ++i) {
+            const HostSlot& h = b->slots[i];
+            if (!h.set) continue;
+            const cpapr_plan* P = h.plan;
+            cpapr::BatchMu mu{const_cast<double*>(h.B), h.Phi, P->dims[h.mode] * (int64_t)P->R, mu_total,
+                              P->params.tol, i, 0};
+            mus.push_back(mu);
+            mu_total += mu.n;
+        }
+        const int32_t nmu = (int32_t)mus.size();
+        if (!mus.empty() && hipMemcpyAsync(b->d_mu, mus.data(), sizeof(cpapr::BatchMu) * mus.size(),
+                                           hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(CPAPR_EHIP, "upload of the MU list failed");
+        if (hipMemcpyAsync(b->d_nmu, &nmu, 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(b->d_mu_total, &mu_total, 8, hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(CPAPR_EHIP, "upload of MU list sizes failed");
         if (!hs.empty()) {
             if (hipMemcpyAsync(b->d_slots, hs.data(), sizeof(BatchSlot) * hs.size(), hipMemcpyHostToDevice, s) !=
                 hipSuccess)
@@ -293,6 +341,35 @@ int cpapr_batch_commit(cpapr_batch* batch, void* stream)
     } catch (...) {
         return fail(CPAPR_EINVAL, "unexpected exception");
     }
+}
+
+int cpapr_batch_mu(cpapr_batch* batch, void* stream)
+{
+    if (!batch) return fail(CPAPR_EINVAL, "batch is NULL");
+    if (!batch->committed) return fail(CPAPR_EINVAL, "batch not committed since the last change");
+    cpapr_batch* b = batch;
+    if (b->copy_grid <= 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return fail(CPAPR_EHIP, "device query failed");
+        b->copy_grid = 4 * std::max(1, cus);
+    }
+    return report(cpapr::launch_batch_mu(b->d_mu, b->d_nmu, b->d_mu_total, b->max_slots, b->d_viol, b->d_viol_out,
+                                         b->d_updated, b->copy_grid, (hipStream_t)stream));
+}
+
+int cpapr_batch_status(cpapr_batch* batch, double* viol, int32_t* updated, void* stream)
+{
+    if (!batch || !viol || !updated) return fail(CPAPR_EINVAL, "batch, viol or updated is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(viol, batch->d_viol_out, 8 * (size_t)batch->max_slots, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(updated, batch->d_updated, 4 * (size_t)batch->max_slots, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(CPAPR_EHIP, "reading the batch status failed");
+    return CPAPR_OK;
 }
 
 int cpapr_batch_run(cpapr_batch* batch, int32_t use_graph, void* stream)

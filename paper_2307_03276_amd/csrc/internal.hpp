@@ -78,6 +78,19 @@ struct alignas(16) BatchCopy {
     int32_t pad;
 };
 
+// One list entry of the batched KKT / MU update kernels (one per slot).
+struct alignas(16) BatchMu {
+    double* B;
+    const double* Phi;
+    int64_t n;      // elements (I_mode x R)
+    int64_t begin;  // offset in the concatenated element space
+    double tol;     // the slot plan's KKT tolerance
+    int32_t slot;
+    int32_t pad;
+};
+
+constexpr int kMuSpread = 8;  // per-slot KKT maxima are spread over this many cache lines
+
 }  // namespace cpapr
 
 struct cpapr_plan {
@@ -128,6 +141,10 @@ Error launch_phi_batch(int cls, const BatchSlot* slots, const int32_t* tile_map,
 Error launch_batch_elementwise(const BatchCopy* items, const int32_t* nitems_dev, const int64_t* total_dev, int grid,
                                hipStream_t s);
 PhiArgs phi_args(const cpapr_plan* P, int mode, const double* B, const void* const* fac, double eps, double* Phi);
+// viol: [kMuSpread * max_slots] u64 (slot s, spread j at j * max_slots + s); status
+// out: viol_out[max_slots] (double), updated[max_slots] (int).
+Error launch_batch_mu(const BatchMu* items, const int32_t* nitems_dev, const int64_t* total_dev, int max_slots,
+                      unsigned long long* viol, double* viol_out, int32_t* updated, int grid, hipStream_t s);
 
 // ---- elementwise and reduction kernels (mu.hip) ----
 Error launch_fill(double* p, int64_t n, double v, const int* done, hipStream_t s);

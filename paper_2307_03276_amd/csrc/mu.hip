@@ -224,7 +224,100 @@ __global__ __launch_bounds__(kBlock) void loglik_final_kernel(const double* __re
     st->ll = s - mass;
 }
 
+// Locate the first list item whose range contains element e0 (items sorted by begin).
+template <typename Item>
+__device__ __forceinline__ int first_item(const Item* items, int nitems, int64_t e0)
+{
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (items[mid].begin <= e0) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void batch_clear_kernel(unsigned long long* viol, int n)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) viol[i] = 0ull;
+}
+
+// Per slot: max over its entries of |min(B, 1 - Phi)|. Workgroup b takes a
+// contiguous range of the concatenated element space; its maxima go to one of
+// kMuSpread line-separated words of each slot it touches.
+__global__ __launch_bounds__(kBlock) void batch_kkt_kernel(const BatchMu* __restrict__ items,
+                                                           const int32_t* __restrict__ nitems_dev,
+                                                           const int64_t* __restrict__ total_dev, int max_slots,
+                                                           unsigned long long* viol)
+{
+    __shared__ double red[kBlock / 64];
+    const int nitems = *nitems_dev;
+    const int64_t total = *total_dev;
+    const int64_t per = ((total + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
+    const int64_t e0 = blockIdx.x * per, e1 = min(e0 + per, total);
+    if (e0 >= e1) return;
+    for (int it = first_item(items, nitems, e0); it < nitems && items[it].begin < e1; ++it) {
+        const BatchMu m = items[it];
+        const int64_t a0 = max(e0, m.begin) - m.begin, a1 = min(e1, m.begin + m.n) - m.begin;
+        double v = 0.0;
+        for (int64_t i = a0 + threadIdx.x; i < a1; i += kBlock) {
+            const double b = m.B[i], q = 1.0 - m.Phi[i];
+            v = fmax(v, fabs(b < q ? b : q));
+        }
+        v = wave_max(v);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double w = red[0];
+            for (int q = 1; q < kBlock / 64; ++q) w = fmax(w, red[q]);
+            const int j = blockIdx.x % kMuSpread;
+            atomicMax(&viol[(int64_t)j * max_slots + m.slot], (unsigned long long)__double_as_longlong(w));
+        }
+        __syncthreads();
+    }
+}
+
+// Per slot: B <- B .* Phi unless tol > 0 and its violation < tol. The workgroup
+// whose range holds a slot's first element reports its violation and decision.
+__global__ __launch_bounds__(kBlock) void batch_update_kernel(const BatchMu* __restrict__ items,
+                                                              const int32_t* __restrict__ nitems_dev,
+                                                              const int64_t* __restrict__ total_dev, int max_slots,
+                                                              const unsigned long long* __restrict__ viol,
+                                                              double* viol_out, int32_t* updated)
+{
+    const int nitems = *nitems_dev;
+    const int64_t total = *total_dev;
+    const int64_t per = ((total + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
+    const int64_t e0 = blockIdx.x * per, e1 = min(e0 + per, total);
+    if (e0 >= e1) return;
+    for (int it = first_item(items, nitems, e0); it < nitems && items[it].begin < e1; ++it) {
+        const BatchMu m = items[it];
+        double v = 0.0;
+        for (int j = 0; j < kMuSpread; ++j)
+            v = fmax(v, __longlong_as_double((long long)viol[(int64_t)j * max_slots + m.slot]));
+        const bool upd = !(m.tol > 0.0 && v < m.tol);
+        if (threadIdx.x == 0 && m.begin >= e0) {
+            viol_out[m.slot] = v;
+            updated[m.slot] = upd ? 1 : 0;
+        }
+        if (!upd) continue;
+        const int64_t a0 = max(e0, m.begin) - m.begin, a1 = min(e1, m.begin + m.n) - m.begin;
+        for (int64_t i = a0 + threadIdx.x; i < a1; i += kBlock) m.B[i] *= m.Phi[i];
+    }
+}
+
 }  // namespace
+
+Error launch_batch_mu(const BatchMu* items, const int32_t* nitems_dev, const int64_t* total_dev, int max_slots,
+                      unsigned long long* viol, double* viol_out, int32_t* updated, int grid, hipStream_t s)
+{
+    batch_clear_kernel<<<32, kBlock, 0, s>>>(viol, kMuSpread * max_slots);
+    CPAPR_LAUNCHED();
+    batch_kkt_kernel<<<grid, kBlock, 0, s>>>(items, nitems_dev, total_dev, max_slots, viol);
+    CPAPR_LAUNCHED();
+    batch_update_kernel<<<grid, kBlock, 0, s>>>(items, nitems_dev, total_dev, max_slots, viol, viol_out, updated);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
 
 Error launch_fill(double* p, int64_t n, double v, const int* done, hipStream_t s)
 {

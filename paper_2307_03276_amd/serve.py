@@ -1,0 +1,255 @@
+"""Continuous-batching CP-APR MU solver service on one GPU.
+
+Requests (a sparse count tensor, an initial model, a rank) arrive over time.
+A request is admitted when a batch slot is free and its device footprint fits
+the HBM budget (first come, first served); on admission its tensor is uploaded,
+its plan built (per-mode device sort) and its model placed on the device. Every
+tick runs one MU inner iteration (Algorithm 1) for *all* active requests
+together: one batched Phi launch over each request's current mode
+(cpapr_batch_run, optionally a replayed hipGraph), one batched KKT + MU update
+(cpapr_batch_mu) and one status read-back. The host then advances each
+request's (outer k, mode n, inner l) state exactly as Algorithm 1's loops do;
+mode transitions run the per-mode prologue / epilogue kernels
+(cpapr_mode_begin / cpapr_mode_end). A request retires when an outer sweep
+makes no update (tol > 0) or after k_max sweeps; its memory returns to the
+budget and queued requests are admitted.
+
+Each request's arithmetic is independent of the others in the batch (same
+kernels, same per-plan tiling), so its result is the same alone and in the mix
+up to the order of the few atomic additions at tile boundaries.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from collections import deque
+from typing import List, Optional
+
+import numpy as np
+
+from . import cpapr
+
+
+@dataclasses.dataclass
+class Request:
+    id: int
+    X: object  # synth.SparseTensor (host)
+    M: object  # synth.Model (host), initial guess
+    arrival: float = 0.0  # seconds from the start of the trace
+    # filled by the server
+    t_admit: Optional[float] = None
+    t_done: Optional[float] = None
+    result_lam: Optional[np.ndarray] = None
+    result_factors: Optional[List[np.ndarray]] = None
+    stats: dict = dataclasses.field(default_factory=dict)
+
+
+class _Active:
+    """Device state and loop counters of an admitted request."""
+
+    def __init__(self, req: Request, slot: int, plan, lam, A, B, phi, nbytes: int):
+        self.req, self.slot, self.plan = req, slot, plan
+        self.lam, self.A, self.B, self.phi = lam, A, B, phi
+        self.nbytes = nbytes
+        self.N = len(req.X.dims)
+        self.k, self.n, self.l = 1, 0, 0
+        self.any_update = False
+        self.updates = 0
+        self.last_viol = [0.0] * self.N
+        self.dirty = True  # slot operands changed since the last commit
+
+
+class Server:
+    def __init__(self, budget_bytes: float = 200e9, max_slots: int = 64, max_tiles: int = 1 << 22,
+                 kmax: int = 20, lmax: int = 10, tol: float = 1e-4, eps: float = 1e-10,
+                 precision: int = cpapr.CPAPR_MIXED, use_graph: bool = True, stream=None,
+                 compute_loglik: bool = True):
+        import torch
+        self.budget = float(budget_bytes)
+        self.used = 0.0
+        self.max_slots = max_slots
+        self.params = dict(kmax=kmax, lmax=lmax, tol=tol, eps=eps, precision=precision)
+        self.use_graph = use_graph
+        self.compute_loglik = compute_loglik
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.batch = cpapr.Batch(max_slots, max_tiles)
+        self.queue: deque = deque()
+        self.active: List[_Active] = []
+        self.free_slots = list(range(max_slots - 1, -1, -1))
+        self.done: List[Request] = []
+        self.ticks = 0
+        self.t0 = time.perf_counter()
+        self.peak_active = 0
+        self.peak_used = 0.0
+        self._need_commit = True
+
+    # ------------------------------------------------------------------ admission
+    def footprint(self, req: Request) -> int:
+        """Device bytes a request holds while active: plan workspace, factors,
+        B, the last Phi of every mode and lambda (its upload buffers are freed
+        once the plan is built)."""
+        X, R = req.X, req.M.rank
+        d = (cpapr.C.c_int64 * len(X.dims))(*X.dims)
+        coo = cpapr.cpapr_coo(len(X.dims), cpapr.C.cast(d, cpapr.C.POINTER(cpapr.C.c_int64)), X.nnz, None, None)
+        ws = cpapr.cpapr_plan_workspace_size(coo, R, cpapr.cpapr_params_default(**self.params))
+        mats = sum(X.dims) * R * 8
+        return int(ws + 2 * mats + max(X.dims) * R * 8 + R * 8)
+
+    def submit(self, req: Request):
+        req.stats["t_submit"] = time.perf_counter() - self.t0
+        self.queue.append(req)
+
+    def _admit(self):
+        import torch
+        while self.queue and self.free_slots:
+            req = self.queue[0]
+            need = self.footprint(req)
+            if need > self.budget:
+                self.queue.popleft()
+                req.stats["rejected"] = "larger than the HBM budget"
+                req.t_done = time.perf_counter() - self.t0
+                self.done.append(req)
+                continue
+            if self.used + need > self.budget:
+                break  # first come, first served: wait for memory
+            self.queue.popleft()
+            slot = self.free_slots.pop()
+            with torch.cuda.stream(self.stream):
+                idx = torch.from_numpy(req.X.idx).to("cuda", non_blocking=False)
+                vals = torch.from_numpy(req.X.vals).to("cuda", non_blocking=False)
+                plan = cpapr.Plan(req.X.dims, idx, vals, req.M.rank, stream=self.stream, **self.params)
+                del idx, vals
+                lam = torch.from_numpy(req.M.lam).to("cuda")
+                A = [torch.from_numpy(a).to("cuda") for a in req.M.factors]
+                B = torch.empty((max(req.X.dims), req.M.rank), dtype=torch.float64, device="cuda")
+                phi = [torch.zeros((d, req.M.rank), dtype=torch.float64, device="cuda") for d in req.X.dims]
+                cpapr.cpapr_plan_sync_f32(plan.handle, A, self.stream)
+            act = _Active(req, slot, plan, lam, A, B, phi, need)
+            self.used += need
+            self.peak_used = max(self.peak_used, self.used)
+            req.t_admit = time.perf_counter() - self.t0
+            self._mode_begin(act)
+            self.active.append(act)
+            self.peak_active = max(self.peak_active, len(self.active))
+
+    # ------------------------------------------------------------------ per request
+    def _mode_begin(self, a: _Active):
+        n = a.n
+        cpapr.cpapr_mode_begin(a.plan.handle, n, a.k, a.lam, a.A[n], a.phi[n] if a.k > 1 else None, a.B,
+                               self.stream)
+        a.dirty = True
+
+    def _retire(self, a: _Active):
+        import torch
+        req = a.req
+        if self.compute_loglik:
+            req.stats["loglik"] = a.plan.loglik(a.lam, a.A, stream=self.stream)
+        self.stream.synchronize()
+        req.result_lam = a.lam.cpu().numpy()
+        req.result_factors = [x.cpu().numpy() for x in a.A]
+        req.stats.update(outer_iters=a.k, inner_updates=a.updates,
+                         converged=bool(self.params["tol"] > 0 and not a.any_update),
+                         kkt=max(a.last_viol))
+        req.t_done = time.perf_counter() - self.t0
+        self.batch.clear(a.slot)
+        self._need_commit = True
+        self.free_slots.append(a.slot)
+        a.plan.close()
+        del a.A, a.B, a.phi, a.lam
+        self.used -= a.nbytes
+        self.done.append(req)
+
+    # ------------------------------------------------------------------ tick
+    def tick(self) -> bool:
+        """Admit what fits, run one inner iteration for every active request.
+        Returns False when nothing is active or queued."""
+        self._admit()
+        if not self.active:
+            return bool(self.queue)
+        flags = cpapr.CPAPR_BATCH_F32_CURRENT if self.params["precision"] == cpapr.CPAPR_MIXED else 0
+        changed = False
+        for a in self.active:
+            if a.dirty:
+                self.batch.set(a.slot, a.plan, a.n, a.B, a.A, a.phi[a.n], flags)
+                a.dirty = False
+                changed = True
+        if changed or self._need_commit:
+            self.batch.commit(self.stream)
+            self._need_commit = False
+        self.batch.run(use_graph=self.use_graph, stream=self.stream)
+        self.batch.mu(self.stream)
+        viol, upd = self.batch.status(self.stream)
+        self.ticks += 1
+        lmax, kmax, tol = self.params["lmax"], self.params["kmax"], self.params["tol"]
+        keep = []
+        for a in self.active:
+            a.l += 1
+            a.last_viol[a.n] = viol[a.slot]
+            if upd[a.slot]:
+                a.updates += 1
+                a.any_update = True
+            if upd[a.slot] and a.l < lmax:
+                keep.append(a)
+                continue
+            # mode finished: lambda and normalisation, then the next mode
+            cpapr.cpapr_mode_end(a.plan.handle, a.n, a.B, a.lam, a.A[a.n], self.stream)
+            a.n += 1
+            a.l = 0
+            if a.n == a.N:
+                a.n = 0
+                if (tol > 0 and not a.any_update) or a.k >= kmax:
+                    self._retire(a)
+                    continue
+                a.k += 1
+                a.any_update = False
+            self._mode_begin(a)
+            keep.append(a)
+        self.active = keep
+        return bool(self.active or self.queue)
+
+    # ------------------------------------------------------------------ driving a trace
+    def run_trace(self, requests: List[Request], time_limit: float = 600.0) -> List[Request]:
+        """Replay arrivals in wall-clock time (request.arrival seconds after
+        start) and serve until every request is done."""
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        self.t0 = time.perf_counter()
+        while pending or self.active or self.queue:
+            now = time.perf_counter() - self.t0
+            while pending and pending[0].arrival <= now:
+                self.submit(pending.popleft())
+            if not self.tick() and pending:
+                time.sleep(max(0.0, min(0.001, pending[0].arrival - (time.perf_counter() - self.t0))))
+            if time.perf_counter() - self.t0 > time_limit:
+                raise TimeoutError("serving trace did not finish in time")
+        return self.done
+
+
+def solve_one(req: Request, precision=cpapr.CPAPR_MIXED, kmax=20, lmax=10, tol=1e-4, eps=1e-10, stream=None):
+    """The plain path: one request on its own with cpapr_solve."""
+    import torch
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    with torch.cuda.stream(stream):
+        idx = torch.from_numpy(req.X.idx).to("cuda")
+        vals = torch.from_numpy(req.X.vals).to("cuda")
+        plan = cpapr.Plan(req.X.dims, idx, vals, req.M.rank, stream=stream, kmax=kmax, lmax=lmax, tol=tol, eps=eps,
+                          precision=precision)
+        del idx, vals
+        lam = torch.from_numpy(req.M.lam).to("cuda")
+        A = [torch.from_numpy(a).to("cuda") for a in req.M.factors]
+        st = plan.solve(lam, A, stream=stream)
+        plan.close()
+        return lam.cpu().numpy(), [a.cpu().numpy() for a in A], st
+
+
+def latency_summary(done: List[Request]) -> dict:
+    ok = [r for r in done if "rejected" not in r.stats]
+    if not ok:
+        return {}
+    ttc = np.array([r.t_done - r.arrival for r in ok])
+    tadm = np.array([r.t_done - r.t_admit for r in ok])
+    span = max(r.t_done for r in ok) - min(r.arrival for r in ok)
+    return {"completed": len(ok), "rejected": len(done) - len(ok),
+            "p50_from_arrival_s": float(np.percentile(ttc, 50)), "p99_from_arrival_s": float(np.percentile(ttc, 99)),
+            "p50_from_admission_s": float(np.percentile(tadm, 50)),
+            "p99_from_admission_s": float(np.percentile(tadm, 99)),
+            "solves_per_s": len(ok) / span if span > 0 else float("inf")}
