@@ -171,6 +171,74 @@ def batch_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def serve_workload(args):
+    """Poisson arrivals at 200 requests/s of CP-APR MU solves (3- or 4-way, dims
+    U[1e3, 1e5], nnz LogUniform[1e4, 2e7], Zipf(1.1), R in {10, 16, 32}, KKT
+    tolerance 1e-4, k_max 20, FP32-stored factors), admitted by a 200 GB HBM
+    budget; against the same trace served one request at a time."""
+    import numpy as np
+    import torch
+
+    from paper_2307_03276_amd import cpapr, serve, synth
+
+    prec = cpapr.CPAPR_MIXED if args.precision == "mixed" else cpapr.CPAPR_FP64
+    total = args.serve_count + args.serve_warmup
+    trace = synth.serving_trace(seed=0, count=total)
+    t_gen = time.perf_counter()
+    reqs = []
+    for r in trace:
+        X, M = synth.request_tensor(r)
+        reqs.append(serve.Request(id=r["id"], X=X, M=M, arrival=r["arrival"]))
+    t_gen = time.perf_counter() - t_gen
+    kw = dict(kmax=20, lmax=10, tol=1e-4, precision=prec)
+    warm, meas = reqs[:args.serve_warmup], reqs[args.serve_warmup:]
+    t_first = meas[0].arrival
+    for r in meas:
+        r.arrival -= t_first
+    for r in warm:
+        r.arrival = 0.0
+    serve.Server(budget_bytes=200e9, max_slots=64, **kw).run_trace(warm)
+    torch.cuda.synchronize()
+    srv = serve.Server(budget_bytes=200e9, max_slots=64, **kw)
+    done = srv.run_trace(meas)
+    summary = serve.latency_summary(done)
+    # the plain path on the same trace: one request at a time, in arrival order
+    clock = 0.0
+    ttc, busy = [], 0.0
+    stream = torch.cuda.Stream()
+    for r in sorted(meas, key=lambda q: q.arrival):
+        start = max(clock, r.arrival)
+        t0 = time.perf_counter()
+        serve.solve_one(serve.Request(id=r.id, X=r.X, M=r.M, arrival=r.arrival), stream=stream, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        busy += dt
+        clock = start + dt
+        ttc.append(clock - r.arrival)
+    ttc = np.array(ttc)
+    nnz = np.array([r.X.nnz for r in meas])
+    out = {
+        "metric": "served solves/s",
+        "value": summary["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": 1, "warmup": args.serve_warmup, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if prec == cpapr.CPAPR_MIXED else "f64", "data": "synthetic",
+        "config": {"workload": "Poisson 200 req/s CP-APR MU solves, 3/4-way, dims U[1e3,1e5], nnz LogUniform[1e4,2e7], "
+                               "Zipf(1.1), R in {10,16,32}, tol 1e-4, kmax 20, HBM budget 200 GB",
+                   "requests": len(meas), "warmup_requests": len(warm), "total_nnz": int(nnz.sum()),
+                   "mean_nnz": float(nnz.mean()), "arrival_span_s": float(max(r.arrival for r in meas))},
+        "served": dict(summary, peak_active=srv.peak_active, peak_hbm_bytes=srv.peak_used, ticks=srv.ticks,
+                       converged=int(sum(1 for r in done if r.stats.get("converged"))),
+                       mean_outer_iters=float(np.mean([r.stats["outer_iters"] for r in done]))),
+        "one_at_a_time": {"p50_from_arrival_s": float(np.percentile(ttc, 50)),
+                          "p99_from_arrival_s": float(np.percentile(ttc, 99)),
+                          "solves_per_s": len(meas) / clock, "busy_s": busy},
+        "generation_s": t_gen,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,9 +247,12 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--nnz", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["zipf3", "batch"], default="zipf3",
-                    help="zipf3: the 20M-nonzero CP-APR MU job (default); batch: 512 uneven tensors")
+    ap.add_argument("--workload", choices=["zipf3", "batch", "serve"], default="zipf3",
+                    help="zipf3: the 20M-nonzero CP-APR MU job (default); batch: 512 uneven tensors; "
+                         "serve: a Poisson stream of solve requests")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--serve-count", type=int, default=60)
+    ap.add_argument("--serve-warmup", type=int, default=6)
     ap.add_argument("--profile-phi", action="store_true",
                     help="counter-collection driver: two Phi launches per mode on the benchmark tensor, "
                          "then a 1 GiB device copy that calibrates the byte counters; prints no JSON")
@@ -198,6 +269,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "batch":
         batch_workload(args)
+        return
+    if args.workload == "serve":
+        if args.precision == "fp64" and "--precision" not in sys.argv:
+            args.precision = "mixed"  # the served configuration stores factors in FP32
+        serve_workload(args)
         return
     X, M, sched = synth.config_zipf3(nnz=args.nnz)
     N, R = X.nmodes, M.rank

@@ -185,11 +185,10 @@ int cpapr_mttkrp(cpapr_plan* plan, int32_t mode, const double* const* A, double*
  * A batch is a set of slots; each slot is one Phi(n) work item: a plan, a mode
  * and its operands (B, the factors, the Phi output). cpapr_batch_run computes
  * Phi for every set slot with one list-driven fill/conversion launch and one
- * persistent launch per shape class (lane group, rank block, number of other
- * modes, precision) present, every launch sized to the device and reading its
- * work list from device memory. With use_graph the sequence is captured once
- * into a hipGraph and replayed; the graph stays valid when slots change, as
- * long as no new shape class appears (then it is re-captured). Caller-provided
+ * launch per shape class (lane group, rank block, number of other modes,
+ * precision) present, all reading their work lists from device memory. With
+ * use_graph the sequence is captured once into a hipGraph and replayed until
+ * a commit changes what the graph baked in (see cpapr_batch_create2). Caller-provided
  * workspace; the library allocates no device memory. Slots of one batch must
  * write disjoint Phi buffers; a plan may appear in several slots. */
 typedef struct cpapr_batch cpapr_batch;
@@ -200,6 +199,17 @@ typedef struct cpapr_batch cpapr_batch;
 int cpapr_batch_workspace_size(int32_t max_slots, int64_t max_tiles, size_t* bytes);
 int64_t cpapr_batch_tiles(const cpapr_plan* plan);
 int cpapr_batch_create(int32_t max_slots, int64_t max_tiles, void* ws, size_t ws_bytes, cpapr_batch** out);
+/* As cpapr_batch_create, with flags. By default (flags 0, what
+ * cpapr_batch_create uses) each shape class is one launch with a workgroup per
+ * tile, so the hardware dispatcher balances the uneven tiles; a captured graph
+ * is re-captured whenever the tile counts change. CPAPR_BATCH_PERSISTENT runs
+ * each class as one persistent launch sized to the device that claims tiles
+ * dynamically and whose graph survives any commit with the same shape classes
+ * (on MI355X about 1.5x slower per nonzero: each tile's descriptor loads are
+ * serialised inside a workgroup instead of overlapped across workgroups). */
+#define CPAPR_BATCH_PERSISTENT 1
+int cpapr_batch_create2(int32_t max_slots, int64_t max_tiles, int32_t flags, void* ws, size_t ws_bytes,
+                        cpapr_batch** out);
 int cpapr_batch_destroy(cpapr_batch* batch);
 
 /* Set slot `slot` (host-side only). B device [I_mode x R]; A host array of the
@@ -220,14 +230,24 @@ int cpapr_batch_commit(cpapr_batch* batch, void* stream);
  * replay the captured hipGraph (capturing it first when needed). */
 int cpapr_batch_run(cpapr_batch* batch, int32_t use_graph, void* stream);
 
-/* One MU inner step for every set slot, after cpapr_batch_run: viol = max
- * |min(B, 1 - Phi)| per slot; B <- B .* Phi unless the slot plan's tol > 0 and
- * viol < tol (the inner-loop test of cpapr_mu_inner). Stream-ordered. */
+/* One MU inner step for every set slot whose inner loop has not stopped, after
+ * cpapr_batch_run: viol = max |min(B, 1 - Phi)| per slot; B <- B .* Phi
+ * unless the slot plan's tol > 0 and viol < tol, which stops the slot (the
+ * inner-loop test of cpapr_mu_inner). Stream-ordered. */
 int cpapr_batch_mu(cpapr_batch* batch, void* stream);
 
-/* Per-slot result of the last cpapr_batch_mu (host arrays of max_slots
- * entries; entries of unset slots are unspecified). Waits for `stream`. */
-int cpapr_batch_status(cpapr_batch* batch, double* viol, int32_t* updated, void* stream);
+/* The whole MU inner loop of Algorithm 1 for every set slot at once: lmax x
+ * {Phi, KKT, update}, where a slot that stops (viol < tol) does no further
+ * work and keeps its last Phi. Equivalent, per slot, to cpapr_mu_inner.
+ * use_graph != 0 replays a captured hipGraph of the whole sequence.
+ * Stream-ordered; read the outcome with cpapr_batch_status. */
+int cpapr_batch_inner(cpapr_batch* batch, int32_t lmax, int32_t use_graph, void* stream);
+
+/* Per-slot outcome since the last cpapr_batch_run / cpapr_batch_inner (host
+ * arrays of max_slots entries; entries of unset slots are unspecified): last
+ * KKT violation, MU updates made, and whether the slot's loop stopped on the
+ * KKT test. Waits for `stream`. */
+int cpapr_batch_status(cpapr_batch* batch, double* viol, int32_t* updates, int32_t* done, void* stream);
 
 /* The per-mode steps of Algorithm 1 around the inner loop, for callers that
  * interleave many solves (cpapr_solve runs the same steps):

@@ -82,10 +82,12 @@ def load():
         "cpapr_batch_workspace_size": (C.c_int, [i32, i64, P(C.c_size_t)]),
         "cpapr_batch_tiles": (i64, [vp]),
         "cpapr_batch_create": (C.c_int, [i32, i64, vp, C.c_size_t, P(vp)]),
+        "cpapr_batch_create2": (C.c_int, [i32, i64, i32, vp, C.c_size_t, P(vp)]),
         "cpapr_batch_destroy": (C.c_int, [vp]),
         "cpapr_batch_set": (C.c_int, [vp, i32, vp, i32, vp, P(vp), vp, i32]),
         "cpapr_batch_mu": (C.c_int, [vp, vp]),
-        "cpapr_batch_status": (C.c_int, [vp, P(dbl), P(i32), vp]),
+        "cpapr_batch_status": (C.c_int, [vp, P(dbl), P(i32), P(i32), vp]),
+        "cpapr_batch_inner": (C.c_int, [vp, i32, i32, vp]),
         "cpapr_mode_begin": (C.c_int, [vp, i32, i32, vp, vp, vp, vp, vp]),
         "cpapr_mode_end": (C.c_int, [vp, i32, vp, vp, vp, vp]),
         "cpapr_plan_sync_f32": (C.c_int, [vp, P(vp), vp]),
@@ -107,9 +109,9 @@ def load():
 
 EXPORTED = ("cpapr_params_default", "cpapr_plan_workspace_size", "cpapr_plan_create", "cpapr_plan_destroy",
             "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_phi", "cpapr_mu_inner", "cpapr_solve", "cpapr_loglik",
-            "cpapr_mttkrp", "cpapr_batch_workspace_size", "cpapr_batch_tiles", "cpapr_batch_create",
+            "cpapr_mttkrp", "cpapr_batch_workspace_size", "cpapr_batch_tiles", "cpapr_batch_create", "cpapr_batch_create2",
             "cpapr_batch_destroy", "cpapr_batch_set", "cpapr_batch_clear", "cpapr_batch_commit", "cpapr_batch_run",
-            "cpapr_batch_mu", "cpapr_batch_status", "cpapr_mode_begin", "cpapr_mode_end", "cpapr_plan_sync_f32",
+            "cpapr_batch_mu", "cpapr_batch_inner", "cpapr_batch_status", "cpapr_mode_begin", "cpapr_mode_end", "cpapr_plan_sync_f32",
             "cpapr_prof_enable", "cpapr_prof_disable", "cpapr_prof_read", "cpapr_last_error")
 
 
@@ -224,9 +226,13 @@ def cpapr_batch_tiles(plan_handle) -> int:
     return int(load().cpapr_batch_tiles(plan_handle))
 
 
-def cpapr_batch_create(max_slots, max_tiles, ws):
+CPAPR_BATCH_PERSISTENT = 1
+
+
+def cpapr_batch_create(max_slots, max_tiles, ws, flags=0):
     h = C.c_void_p()
-    _check(load().cpapr_batch_create(max_slots, max_tiles, ws.data_ptr(), ws.numel() * ws.element_size(), C.byref(h)))
+    _check(load().cpapr_batch_create2(max_slots, max_tiles, flags, ws.data_ptr(), ws.numel() * ws.element_size(),
+                                      C.byref(h)))
     return h
 
 
@@ -246,11 +252,16 @@ def cpapr_batch_mu(h, stream=None):
     return _check(load().cpapr_batch_mu(h, _stream(stream)))
 
 
+def cpapr_batch_inner(h, lmax, use_graph=False, stream=None):
+    return _check(load().cpapr_batch_inner(h, lmax, 1 if use_graph else 0, _stream(stream)))
+
+
 def cpapr_batch_status(h, max_slots, stream=None):
     viol = (C.c_double * max_slots)()
     upd = (C.c_int32 * max_slots)()
-    _check(load().cpapr_batch_status(h, viol, upd, _stream(stream)))
-    return list(viol), list(upd)
+    done = (C.c_int32 * max_slots)()
+    _check(load().cpapr_batch_status(h, viol, upd, done, _stream(stream)))
+    return list(viol), list(upd), list(done)
 
 
 def cpapr_mode_begin(h, mode, outer_iter, lam, A_mode, phi_prev, B, stream=None):
@@ -282,12 +293,13 @@ def cpapr_batch_run(h, use_graph=False, stream=None):
 class Batch:
     """Slots of Phi work items run in persistent launches (optionally as a hipGraph)."""
 
-    def __init__(self, max_slots: int, max_tiles: int, device="cuda"):
+    def __init__(self, max_slots: int, max_tiles: int, device="cuda", persistent: bool = False):
         import torch
         self.max_slots, self.max_tiles = int(max_slots), int(max_tiles)
         nbytes = cpapr_batch_workspace_size(self.max_slots, self.max_tiles)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.handle = cpapr_batch_create(self.max_slots, self.max_tiles, self.ws)
+        self.handle = cpapr_batch_create(self.max_slots, self.max_tiles, self.ws,
+                                         CPAPR_BATCH_PERSISTENT if persistent else 0)
         self._keep = {}
 
     def set(self, slot, plan, mode, B, A, Phi, flags=0):
@@ -306,6 +318,9 @@ class Batch:
 
     def mu(self, stream=None):
         cpapr_batch_mu(self.handle, stream)
+
+    def inner(self, lmax, use_graph=False, stream=None):
+        cpapr_batch_inner(self.handle, lmax, use_graph, stream)
 
     def status(self, stream=None):
         return cpapr_batch_status(self.handle, self.max_slots, stream)

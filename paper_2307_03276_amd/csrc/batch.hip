@@ -22,7 +22,7 @@ namespace {
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-constexpr int kMaxClasses = 64;
+constexpr int kMaxClasses = cpapr::kBatchClassesMax;
 
 struct HostSlot {
     bool set = false;
@@ -36,7 +36,7 @@ struct HostSlot {
 
 struct Layout {
     size_t slots, tile_map, class_off, class_ntiles, copies, ncopies, copy_total;
-    size_t mu, nmu, mu_total, viol, viol_out, updated, total;
+    size_t mu, nmu, mu_total, viol, st_done, st_updates, st_viol, counters, total;
 };
 
 Layout layout(int max_slots, int64_t max_tiles)
@@ -65,10 +65,14 @@ Layout layout(int max_slots, int64_t max_tiles)
     off += 256;
     L.viol = off;
     off += align256(8 * (size_t)cpapr::kMuSpread * max_slots);
-    L.viol_out = off;
-    off += align256(8 * (size_t)max_slots);
-    L.updated = off;
+    L.st_done = off;
     off += align256(4 * (size_t)max_slots);
+    L.st_updates = off;
+    off += align256(4 * (size_t)max_slots);
+    L.st_viol = off;
+    off += align256(8 * (size_t)max_slots);
+    L.counters = off;
+    off += align256(4 * (size_t)cpapr::kBatchCounters * cpapr::kCounterStride);
     L.total = off;
     return L;
 }
@@ -97,15 +101,21 @@ struct cpapr_batch {
     int32_t* d_nmu;
     int64_t* d_mu_total;
     unsigned long long* d_viol;
-    double* d_viol_out;
-    int32_t* d_updated;
+    unsigned int* d_counters;
+    cpapr::BatchState st;
     std::vector<HostSlot> slots;
     bool committed = false;
     std::vector<int> classes;           // classes with work at the last commit
+    std::vector<int64_t> class_tiles;   // their tile counts (grid launches)
+    bool persistent = true;
     int grid_cache[kMaxClasses] = {};   // persistent grid per class
     int copy_grid = 0;
-    hipGraphExec_t graph = nullptr;
-    std::vector<int> graph_classes;     // classes captured in `graph`
+    struct Graph {
+        hipGraphExec_t exec = nullptr;
+        std::vector<int> classes;  // classes captured
+        std::vector<int64_t> tiles;  // per-class tile counts captured (grid launches)
+        int lmax = 0;              // inner iterations captured (0: Phi only)
+    } graph_run, graph_inner;
 };
 
 namespace {
@@ -122,7 +132,7 @@ int report(const Error& e)
     return e.code;
 }
 
-Error enqueue(cpapr_batch* b, const std::vector<int>& classes, hipStream_t s)
+Error ensure_grids(cpapr_batch* b)
 {
     if (b->copy_grid <= 0) {
         int dev = 0, cus = 0;
@@ -130,14 +140,92 @@ Error enqueue(cpapr_batch* b, const std::vector<int>& classes, hipStream_t s)
         CPAPR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         b->copy_grid = 4 * std::max(1, cus);
     }
-    Error e = cpapr::launch_batch_elementwise(b->d_copies, b->d_ncopies, b->d_copy_total, b->copy_grid, s);
+    return {CPAPR_OK, ""};
+}
+
+// Phi for every slot whose done flag is clear: zero their Phi (and refresh FP32
+// factor copies), then one persistent launch per shape class.
+Error enqueue_phi(cpapr_batch* b, const std::vector<int>& classes, hipStream_t s)
+{
+    Error e = ensure_grids(b);
+    if (e.code) return e;
+    e = cpapr::launch_batch_elementwise(b->d_copies, b->d_ncopies, b->d_copy_total, b->st.done, b->d_counters,
+                                        b->copy_grid, s);
     if (e.code) return e;
     for (int c : classes) {
-        e = cpapr::launch_phi_batch(c, b->d_slots, b->d_tile_map, b->d_class_off, b->d_class_ntiles,
-                                    &b->grid_cache[c], s);
+        const int64_t grid_tiles = b->persistent ? 0 : b->class_tiles[c];
+        e = cpapr::launch_phi_batch(c, b->d_slots, b->d_tile_map, b->d_class_off, b->d_class_ntiles, b->st.done,
+                                    b->d_counters, &b->grid_cache[c], grid_tiles, s);
         if (e.code) return e;
     }
     return {CPAPR_OK, ""};
+}
+
+Error enqueue_mu(cpapr_batch* b, hipStream_t s)
+{
+    Error e = ensure_grids(b);
+    if (e.code) return e;
+    return cpapr::launch_batch_mu(b->d_mu, b->d_nmu, b->d_mu_total, b->max_slots, b->d_viol, b->st, b->copy_grid, s);
+}
+
+// lmax == 0: clear the per-slot state and compute Phi for every slot.
+// lmax > 0: clear it and run lmax x {Phi, KKT, MU update} with per-slot stops.
+Error enqueue_sequence(cpapr_batch* b, int lmax, hipStream_t s)
+{
+    Error e = cpapr::launch_batch_reset(b->st, b->max_slots, s);
+    if (e.code) return e;
+    if (lmax == 0) return enqueue_phi(b, b->classes, s);
+    for (int l = 0; l < lmax; ++l) {
+        e = enqueue_phi(b, b->classes, s);
+        if (e.code) return e;
+        e = enqueue_mu(b, s);
+        if (e.code) return e;
+    }
+    return {CPAPR_OK, ""};
+}
+
+// Run a sequence directly, or replay it from a graph captured for the current
+// set of shape classes (capturing, after one direct run, when needed).
+int run_sequence(cpapr_batch* b, cpapr_batch::Graph& g, int lmax, bool use_graph, hipStream_t s)
+{
+    if (!use_graph) return report(enqueue_sequence(b, lmax, s));
+    bool covered = g.exec != nullptr && g.lmax == lmax;
+    for (int c : b->classes)
+        if (std::find(g.classes.begin(), g.classes.end(), c) == g.classes.end()) covered = false;
+    if (!b->persistent && g.tiles != b->class_tiles) covered = false;  // grid sizes are baked into the graph
+    if (covered) {
+        if (hipGraphLaunch(g.exec, s) != hipSuccess) return fail(CPAPR_EHIP, "hipGraphLaunch failed");
+        return CPAPR_OK;
+    }
+    if (s == nullptr) return fail(CPAPR_EINVAL, "graph capture needs a non-null stream");
+    if (g.exec) {
+        hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+    }
+    // One direct run first: it computes this call's result and performs the
+    // occupancy queries and lazy kernel loading outside the capture.
+    Error e = enqueue_sequence(b, lmax, s);
+    if (e.code) return report(e);
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(CPAPR_EHIP, "hipStreamBeginCapture failed");
+    e = enqueue_sequence(b, lmax, s);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (e.code) {
+        if (graph) hipGraphDestroy(graph);
+        return report(e);
+    }
+    if (ec != hipSuccess || !graph) return fail(CPAPR_EHIP, "hipStreamEndCapture failed");
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        g.exec = nullptr;
+        return fail(CPAPR_EHIP, "hipGraphInstantiate failed");
+    }
+    g.classes = b->classes;
+    g.tiles = b->class_tiles;
+    g.lmax = lmax;
+    return CPAPR_OK;
 }
 
 }  // namespace
@@ -160,6 +248,12 @@ int64_t cpapr_batch_tiles(const cpapr_plan* plan)
 
 int cpapr_batch_create(int32_t max_slots, int64_t max_tiles, void* ws, size_t ws_bytes, cpapr_batch** out)
 {
+    return cpapr_batch_create2(max_slots, max_tiles, 0, ws, ws_bytes, out);
+}
+
+int cpapr_batch_create2(int32_t max_slots, int64_t max_tiles, int32_t flags, void* ws, size_t ws_bytes,
+                        cpapr_batch** out)
+{
     try {
         if (!out) return fail(CPAPR_EINVAL, "out is NULL");
         *out = nullptr;
@@ -170,6 +264,11 @@ int cpapr_batch_create(int32_t max_slots, int64_t max_tiles, void* ws, size_t ws
         if (ws_bytes < L.total) return fail(CPAPR_EWORKSPACE, "workspace too small");
         cpapr_batch* b = new (std::nothrow) cpapr_batch();
         if (!b) return fail(CPAPR_EINVAL, "out of host memory");
+        if (flags & ~CPAPR_BATCH_PERSISTENT) {
+            delete b;
+            return fail(CPAPR_EINVAL, "unknown batch flags");
+        }
+        b->persistent = (flags & CPAPR_BATCH_PERSISTENT) != 0;
         b->max_slots = max_slots;
         b->max_tiles = max_tiles;
         b->ws = (char*)ws;
@@ -185,8 +284,10 @@ int cpapr_batch_create(int32_t max_slots, int64_t max_tiles, void* ws, size_t ws
         b->d_nmu = (int32_t*)(b->ws + L.nmu);
         b->d_mu_total = (int64_t*)(b->ws + L.mu_total);
         b->d_viol = (unsigned long long*)(b->ws + L.viol);
-        b->d_viol_out = (double*)(b->ws + L.viol_out);
-        b->d_updated = (int32_t*)(b->ws + L.updated);
+        b->st.done = (int32_t*)(b->ws + L.st_done);
+        b->st.updates = (int32_t*)(b->ws + L.st_updates);
+        b->st.viol = (double*)(b->ws + L.st_viol);
+        b->d_counters = (unsigned int*)(b->ws + L.counters);
         b->slots.resize(max_slots);
         *out = b;
         return CPAPR_OK;
@@ -198,7 +299,8 @@ int cpapr_batch_create(int32_t max_slots, int64_t max_tiles, void* ws, size_t ws
 int cpapr_batch_destroy(cpapr_batch* batch)
 {
     if (!batch) return CPAPR_OK;
-    if (batch->graph) hipGraphExecDestroy(batch->graph);
+    if (batch->graph_run.exec) hipGraphExecDestroy(batch->graph_run.exec);
+    if (batch->graph_inner.exec) hipGraphExecDestroy(batch->graph_inner.exec);
     delete batch;
     return CPAPR_OK;
 }
@@ -273,7 +375,7 @@ int cpapr_batch_commit(cpapr_batch* batch, void* stream)
                     if (m == h.mode) continue;
                     if (mixed) {
                         if (!(h.flags & CPAPR_BATCH_F32_CURRENT)) {
-                            BatchCopy cp{h.A[m], P->f32[m], P->dims[m] * (int64_t)P->R, copy_total, 1, 0};
+                            BatchCopy cp{h.A[m], P->f32[m], P->dims[m] * (int64_t)P->R, copy_total, 1, -1};
                             copies.push_back(cp);
                             copy_total += cp.n;
                         }
@@ -282,12 +384,13 @@ int cpapr_batch_commit(cpapr_batch* batch, void* stream)
                         fac[m] = h.A[m];
                     }
                 }
-                BatchCopy z{nullptr, h.Phi, P->dims[h.mode] * (int64_t)P->R, copy_total, 0, 0};
+                BatchCopy z{nullptr, h.Phi, P->dims[h.mode] * (int64_t)P->R, copy_total, 0, i};
                 copies.push_back(z);
                 copy_total += z.n;
                 BatchSlot bs{};
                 bs.args = cpapr::phi_args(P, h.mode, h.B, fac, P->params.eps, h.Phi);
                 bs.tile_begin = tiles;
+                bs.slot = i;
                 const int64_t nt = plan_tiles(P);
                 const int32_t idx = (int32_t)hs.size();
                 hs.push_back(bs);
@@ -336,6 +439,7 @@ int cpapr_batch_commit(cpapr_batch* batch, void* stream)
             return fail(CPAPR_EHIP, "upload of list sizes failed");
         if (hipStreamSynchronize(s) != hipSuccess) return fail(CPAPR_EHIP, "stream synchronisation failed");
         b->classes = classes;
+        b->class_tiles.assign(cnt.begin(), cnt.end());
         b->committed = true;
         return CPAPR_OK;
     } catch (...) {
@@ -347,26 +451,17 @@ int cpapr_batch_mu(cpapr_batch* batch, void* stream)
 {
     if (!batch) return fail(CPAPR_EINVAL, "batch is NULL");
     if (!batch->committed) return fail(CPAPR_EINVAL, "batch not committed since the last change");
-    cpapr_batch* b = batch;
-    if (b->copy_grid <= 0) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            return fail(CPAPR_EHIP, "device query failed");
-        b->copy_grid = 4 * std::max(1, cus);
-    }
-    return report(cpapr::launch_batch_mu(b->d_mu, b->d_nmu, b->d_mu_total, b->max_slots, b->d_viol, b->d_viol_out,
-                                         b->d_updated, b->copy_grid, (hipStream_t)stream));
+    return report(enqueue_mu(batch, (hipStream_t)stream));
 }
 
-int cpapr_batch_status(cpapr_batch* batch, double* viol, int32_t* updated, void* stream)
+int cpapr_batch_status(cpapr_batch* batch, double* viol, int32_t* updates, int32_t* done, void* stream)
 {
-    if (!batch || !viol || !updated) return fail(CPAPR_EINVAL, "batch, viol or updated is NULL");
+    if (!batch || !viol || !updates || !done) return fail(CPAPR_EINVAL, "batch or an output array is NULL");
     hipStream_t s = (hipStream_t)stream;
-    if (hipMemcpyAsync(viol, batch->d_viol_out, 8 * (size_t)batch->max_slots, hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipMemcpyAsync(updated, batch->d_updated, 4 * (size_t)batch->max_slots, hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
+    const size_t n = (size_t)batch->max_slots;
+    if (hipMemcpyAsync(viol, batch->st.viol, 8 * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(updates, batch->st.updates, 4 * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(done, batch->st.done, 4 * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return fail(CPAPR_EHIP, "reading the batch status failed");
     return CPAPR_OK;
@@ -376,45 +471,20 @@ int cpapr_batch_run(cpapr_batch* batch, int32_t use_graph, void* stream)
 {
     try {
         if (!batch) return fail(CPAPR_EINVAL, "batch is NULL");
-        cpapr_batch* b = batch;
-        if (!b->committed) return fail(CPAPR_EINVAL, "batch not committed since the last change");
-        hipStream_t s = (hipStream_t)stream;
-        if (!use_graph) return report(enqueue(b, b->classes, s));
-        bool covered = b->graph != nullptr;
-        for (int c : b->classes)
-            if (std::find(b->graph_classes.begin(), b->graph_classes.end(), c) == b->graph_classes.end())
-                covered = false;
-        if (!covered) {
-            if (s == nullptr) return fail(CPAPR_EINVAL, "graph capture needs a non-null stream");
-            if (b->graph) {
-                hipGraphExecDestroy(b->graph);
-                b->graph = nullptr;
-            }
-            // First launches outside capture so that occupancy queries and lazy
-            // kernel loading happen before the graph is recorded.
-            Error e = enqueue(b, b->classes, s);
-            if (e.code) return report(e);
-            if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
-                return fail(CPAPR_EHIP, "hipStreamBeginCapture failed");
-            e = enqueue(b, b->classes, s);
-            hipGraph_t g = nullptr;
-            const hipError_t ec = hipStreamEndCapture(s, &g);
-            if (e.code) {
-                if (g) hipGraphDestroy(g);
-                return report(e);
-            }
-            if (ec != hipSuccess || !g) return fail(CPAPR_EHIP, "hipStreamEndCapture failed");
-            const hipError_t ei = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-            hipGraphDestroy(g);
-            if (ei != hipSuccess) {
-                b->graph = nullptr;
-                return fail(CPAPR_EHIP, "hipGraphInstantiate failed");
-            }
-            b->graph_classes = b->classes;
-            return CPAPR_OK;  // the direct launch above already computed this commit
-        }
-        if (hipGraphLaunch(b->graph, s) != hipSuccess) return fail(CPAPR_EHIP, "hipGraphLaunch failed");
-        return CPAPR_OK;
+        if (!batch->committed) return fail(CPAPR_EINVAL, "batch not committed since the last change");
+        return run_sequence(batch, batch->graph_run, 0, use_graph != 0, (hipStream_t)stream);
+    } catch (...) {
+        return fail(CPAPR_EINVAL, "unexpected exception");
+    }
+}
+
+int cpapr_batch_inner(cpapr_batch* batch, int32_t lmax, int32_t use_graph, void* stream)
+{
+    try {
+        if (!batch) return fail(CPAPR_EINVAL, "batch is NULL");
+        if (lmax < 1 || lmax > CPAPR_MAX_LMAX) return fail(CPAPR_EINVAL, "lmax must be in [1, 4096]");
+        if (!batch->committed) return fail(CPAPR_EINVAL, "batch not committed since the last change");
+        return run_sequence(batch, batch->graph_inner, lmax, use_graph != 0, (hipStream_t)stream);
     } catch (...) {
         return fail(CPAPR_EINVAL, "unexpected exception");
     }

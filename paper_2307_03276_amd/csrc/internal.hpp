@@ -66,6 +66,8 @@ struct PhiArgs {
 struct alignas(16) BatchSlot {
     PhiArgs args;
     int64_t tile_begin;
+    int32_t slot;  // caller's slot id (index of its done flag)
+    int32_t pad;
 };
 
 // One list entry of the batched fill / conversion kernel.
@@ -75,7 +77,7 @@ struct alignas(16) BatchCopy {
     int64_t n;
     int64_t begin;  // offset in the concatenated element space
     int32_t op;     // 0: zero FP64 dst; 1: dst (FP32) = src (FP64)
-    int32_t pad;
+    int32_t slot;   // op 0: skipped while this slot's done flag is set; -1: never skipped
 };
 
 // One list entry of the batched KKT / MU update kernels (one per slot).
@@ -90,6 +92,13 @@ struct alignas(16) BatchMu {
 };
 
 constexpr int kMuSpread = 8;  // per-slot KKT maxima are spread over this many cache lines
+
+// Dynamic tile claiming of the persistent batched Phi kernel.
+constexpr int kBatchSubs = 64;      // tile sub-ranges per shape class (8 per XCD)
+constexpr int kBatchClaim = 4;      // tiles claimed per atomic
+constexpr int kCounterStride = 32;  // u32 words between counters (one 128-byte line each)
+constexpr int kBatchClassesMax = 64;
+constexpr int kBatchCounters = kBatchClassesMax * kBatchSubs;
 
 }  // namespace cpapr
 
@@ -136,15 +145,26 @@ Error launch_mttkrp(const cpapr_plan* P, int mode, const double* const* A, doubl
 // ---- batched Phi (phi.hip; host side in batch.hip) ----
 int batch_class_count();
 int batch_class_of(int G, int RPL, int NM1, bool mixed);  // -1: no batched kernel for this shape
+// counters: [kBatchCounters * kCounterStride] u32 in device memory.
+// grid_tiles > 0: launch one workgroup per tile (that many) instead of the
+// persistent kernel.
 Error launch_phi_batch(int cls, const BatchSlot* slots, const int32_t* tile_map, const int64_t* class_off,
-                       const int64_t* class_ntiles, int* grid_cache, hipStream_t s);
-Error launch_batch_elementwise(const BatchCopy* items, const int32_t* nitems_dev, const int64_t* total_dev, int grid,
-                               hipStream_t s);
+                       const int64_t* class_ntiles, const int32_t* slot_done, unsigned int* counters,
+                       int* grid_cache, int64_t grid_tiles, hipStream_t s);
+Error launch_batch_elementwise(const BatchCopy* items, const int32_t* nitems_dev, const int64_t* total_dev,
+                               const int32_t* slot_done, unsigned int* counters, int grid, hipStream_t s);
 PhiArgs phi_args(const cpapr_plan* P, int mode, const double* B, const void* const* fac, double eps, double* Phi);
-// viol: [kMuSpread * max_slots] u64 (slot s, spread j at j * max_slots + s); status
-// out: viol_out[max_slots] (double), updated[max_slots] (int).
+// Per-slot state of the batched inner loop, all [max_slots]: done flag, MU
+// updates made, last KKT violation.
+struct BatchState {
+    int32_t* done;
+    int32_t* updates;
+    double* viol;
+};
+// viol_spread: [kMuSpread * max_slots] u64 (slot s, spread j at j * max_slots + s).
 Error launch_batch_mu(const BatchMu* items, const int32_t* nitems_dev, const int64_t* total_dev, int max_slots,
-                      unsigned long long* viol, double* viol_out, int32_t* updated, int grid, hipStream_t s);
+                      unsigned long long* viol_spread, BatchState st, int grid, hipStream_t s);
+Error launch_batch_reset(BatchState st, int max_slots, hipStream_t s);
 
 // ---- elementwise and reduction kernels (mu.hip) ----
 Error launch_fill(double* p, int64_t n, double v, const int* done, hipStream_t s);

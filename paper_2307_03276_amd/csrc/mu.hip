@@ -11,6 +11,8 @@
 //
 // All reductions are two-level with a fixed partition and a fixed order, so
 // their results are bitwise reproducible run to run.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace cpapr {
@@ -241,13 +243,22 @@ __global__ __launch_bounds__(kBlock) void batch_clear_kernel(unsigned long long*
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) viol[i] = 0ull;
 }
 
+__global__ __launch_bounds__(kBlock) void batch_reset_kernel(BatchState st, int n)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        st.done[i] = 0;
+        st.updates[i] = 0;
+        st.viol[i] = 0.0;
+    }
+}
+
 // Per slot: max over its entries of |min(B, 1 - Phi)|. Workgroup b takes a
 // contiguous range of the concatenated element space; its maxima go to one of
 // kMuSpread line-separated words of each slot it touches.
 __global__ __launch_bounds__(kBlock) void batch_kkt_kernel(const BatchMu* __restrict__ items,
                                                            const int32_t* __restrict__ nitems_dev,
                                                            const int64_t* __restrict__ total_dev, int max_slots,
-                                                           unsigned long long* viol)
+                                                           unsigned long long* viol, const int32_t* __restrict__ done)
 {
     __shared__ double red[kBlock / 64];
     const int nitems = *nitems_dev;
@@ -257,6 +268,7 @@ __global__ __launch_bounds__(kBlock) void batch_kkt_kernel(const BatchMu* __rest
     if (e0 >= e1) return;
     for (int it = first_item(items, nitems, e0); it < nitems && items[it].begin < e1; ++it) {
         const BatchMu m = items[it];
+        if (done[m.slot]) continue;  // block-uniform
         const int64_t a0 = max(e0, m.begin) - m.begin, a1 = min(e1, m.begin + m.n) - m.begin;
         double v = 0.0;
         for (int64_t i = a0 + threadIdx.x; i < a1; i += kBlock) {
@@ -276,13 +288,16 @@ __global__ __launch_bounds__(kBlock) void batch_kkt_kernel(const BatchMu* __rest
     }
 }
 
-// Per slot: B <- B .* Phi unless tol > 0 and its violation < tol. The workgroup
-// whose range holds a slot's first element reports its violation and decision.
+// Per slot: B <- B .* Phi unless tol > 0 and its violation < tol, which stops
+// the slot's inner loop (done flag). The workgroup whose range holds a slot's
+// first element records the violation, the decision and the update count.
+// Blocks of this launch that see a flag raised by it skip work they would have
+// skipped anyway (a raised flag means no update).
 __global__ __launch_bounds__(kBlock) void batch_update_kernel(const BatchMu* __restrict__ items,
                                                               const int32_t* __restrict__ nitems_dev,
                                                               const int64_t* __restrict__ total_dev, int max_slots,
                                                               const unsigned long long* __restrict__ viol,
-                                                              double* viol_out, int32_t* updated)
+                                                              BatchState st)
 {
     const int nitems = *nitems_dev;
     const int64_t total = *total_dev;
@@ -291,13 +306,17 @@ __global__ __launch_bounds__(kBlock) void batch_update_kernel(const BatchMu* __r
     if (e0 >= e1) return;
     for (int it = first_item(items, nitems, e0); it < nitems && items[it].begin < e1; ++it) {
         const BatchMu m = items[it];
+        if (st.done[m.slot]) continue;
         double v = 0.0;
         for (int j = 0; j < kMuSpread; ++j)
             v = fmax(v, __longlong_as_double((long long)viol[(int64_t)j * max_slots + m.slot]));
         const bool upd = !(m.tol > 0.0 && v < m.tol);
         if (threadIdx.x == 0 && m.begin >= e0) {
-            viol_out[m.slot] = v;
-            updated[m.slot] = upd ? 1 : 0;
+            st.viol[m.slot] = v;
+            if (upd)
+                st.updates[m.slot] += 1;
+            else
+                st.done[m.slot] = 1;
         }
         if (!upd) continue;
         const int64_t a0 = max(e0, m.begin) - m.begin, a1 = min(e1, m.begin + m.n) - m.begin;
@@ -308,13 +327,20 @@ __global__ __launch_bounds__(kBlock) void batch_update_kernel(const BatchMu* __r
 }  // namespace
 
 Error launch_batch_mu(const BatchMu* items, const int32_t* nitems_dev, const int64_t* total_dev, int max_slots,
-                      unsigned long long* viol, double* viol_out, int32_t* updated, int grid, hipStream_t s)
+                      unsigned long long* viol_spread, BatchState st, int grid, hipStream_t s)
 {
-    batch_clear_kernel<<<32, kBlock, 0, s>>>(viol, kMuSpread * max_slots);
+    batch_clear_kernel<<<32, kBlock, 0, s>>>(viol_spread, kMuSpread * max_slots);
     CPAPR_LAUNCHED();
-    batch_kkt_kernel<<<grid, kBlock, 0, s>>>(items, nitems_dev, total_dev, max_slots, viol);
+    batch_kkt_kernel<<<grid, kBlock, 0, s>>>(items, nitems_dev, total_dev, max_slots, viol_spread, st.done);
     CPAPR_LAUNCHED();
-    batch_update_kernel<<<grid, kBlock, 0, s>>>(items, nitems_dev, total_dev, max_slots, viol, viol_out, updated);
+    batch_update_kernel<<<grid, kBlock, 0, s>>>(items, nitems_dev, total_dev, max_slots, viol_spread, st);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+Error launch_batch_reset(BatchState st, int max_slots, hipStream_t s)
+{
+    batch_reset_kernel<<<std::max(1, std::min(64, (max_slots + kBlock - 1) / kBlock)), kBlock, 0, s>>>(st, max_slots);
     CPAPR_LAUNCHED();
     return {CPAPR_OK, ""};
 }

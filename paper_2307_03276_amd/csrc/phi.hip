@@ -417,28 +417,75 @@ __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
     phi_tile<G, RPL, NM1, MIXED, KIND>(a, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 
-// Persistent Phi over a batch of operand sets of one shape class: the grid is
-// sized to the device, the tile count and the tile -> slot map are read from
-// device memory (so a captured graph stays valid when the batch changes), and
-// each workgroup walks a contiguous, XCD-mapped range of tiles.
+// Persistent Phi over a batch of operand sets of one shape class. The grid is
+// sized to the device; the tile count and the tile -> slot map are read from
+// device memory (so a captured graph stays valid when the batch changes).
+// Tiles are handed out dynamically: the class's tile space is cut into
+// kBatchSubs contiguous sub-ranges (kBatchSubs / 8 per XCD, so neighbouring
+// tiles, which share B and Phi rows, stay in one L2), each with its own
+// counter on its own cache line; a workgroup claims kBatchClaim tiles at a
+// time from its home sub-range, then from the following ones. Tile costs vary
+// a lot (a tile inside one heavy row does one flush, a tile in a sparse tail
+// many), which is why a static split loses to dynamic claiming.
 template <int G, int RPL, int NM1, bool MIXED>
 __global__ __launch_bounds__(kBlock) void phi_batch_kernel(const BatchSlot* __restrict__ slots,
                                                            const int32_t* __restrict__ tile_map,
                                                            const int64_t* __restrict__ class_off,
-                                                           const int64_t* __restrict__ class_ntiles, int cls)
+                                                           const int64_t* __restrict__ class_ntiles,
+                                                           const int32_t* __restrict__ slot_done,
+                                                           unsigned int* __restrict__ counters, int cls)
 {
     __shared__ TileShared<G, RPL, NM1> sh;
+    __shared__ unsigned int claimed;
     const int64_t total = class_ntiles[cls];
     const int32_t* __restrict__ tile_slot = tile_map + class_off[cls];
-    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-    const int64_t pos = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t t0 = pos * per, t1 = min(t0 + per, total);
-    for (int64_t tt = t0; tt < t1; ++tt) {
-        const int si = tile_slot[tt];
-        const PhiArgs a = slots[si].args;
-        __syncthreads();  // LDS of the previous tile is no longer read
-        phi_tile<G, RPL, NM1, MIXED, kPhi>(a, tt - slots[si].tile_begin, sh);
+    unsigned int* ctr_base = counters + (int64_t)cls * kBatchSubs * kCounterStride;
+    const int b = blockIdx.x;
+    const int home = (b % kXcds) * (kBatchSubs / kXcds) + (b / kXcds) % (kBatchSubs / kXcds);
+    for (int k = 0; k < kBatchSubs; ++k) {
+        const int sub = (home + k) % kBatchSubs;
+        const int64_t lo = sub * total / kBatchSubs, hi = (sub + 1) * total / kBatchSubs;
+        const unsigned int len = (unsigned int)(hi - lo);
+        unsigned int* ctr = ctr_base + (int64_t)sub * kCounterStride;
+        while (true) {
+            if (threadIdx.x == 0) {
+                unsigned int c = len;
+                if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < len)
+                    c = atomicAdd(ctr, (unsigned int)kBatchClaim);
+                claimed = c;
+            }
+            __syncthreads();
+            const unsigned int c = claimed;
+            __syncthreads();
+            if (c >= len) break;
+            const int64_t t1 = min(lo + (int64_t)c + kBatchClaim, hi);
+            for (int64_t tt = lo + c; tt < t1; ++tt) {
+                const int si = tile_slot[tt];
+                if (slot_done[slots[si].slot]) continue;  // this slot's inner loop has stopped
+                const PhiArgs a = slots[si].args;
+                __syncthreads();  // LDS of the previous tile is no longer read
+                phi_tile<G, RPL, NM1, MIXED, kPhi>(a, tt - slots[si].tile_begin, sh);
+            }
+        }
     }
+}
+
+// Non-persistent variant: one workgroup per tile of the class (grid size from
+// the host's commit), tiles spread XCD-aware like the single-plan kernel; the
+// hardware dispatcher balances the uneven tiles and overlaps each tile's
+// prologue with other workgroups' work.
+template <int G, int RPL, int NM1, bool MIXED>
+__global__ __launch_bounds__(kBlock) void phi_batch_grid_kernel(const BatchSlot* __restrict__ slots,
+                                                                const int32_t* __restrict__ tile_map,
+                                                                const int64_t* __restrict__ class_off,
+                                                                const int32_t* __restrict__ slot_done, int cls)
+{
+    __shared__ TileShared<G, RPL, NM1> sh;
+    const int64_t tt = xcd_remap(blockIdx.x, gridDim.x);
+    const int si = tile_map[class_off[cls] + tt];
+    if (slot_done[slots[si].slot]) return;
+    const PhiArgs a = slots[si].args;
+    phi_tile<G, RPL, NM1, MIXED, kPhi>(a, tt - slots[si].tile_begin, sh);
 }
 
 // List-driven fills / conversions for a batch: op 0 zeroes dst (FP64), op 1
@@ -446,8 +493,13 @@ __global__ __launch_bounds__(kBlock) void phi_batch_kernel(const BatchSlot* __re
 // of the concatenated lists and walks the items it spans.
 __global__ __launch_bounds__(kBlock) void batch_elementwise_kernel(const BatchCopy* __restrict__ items,
                                                                    const int32_t* __restrict__ nitems_dev,
-                                                                   const int64_t* __restrict__ total_dev)
+                                                                   const int64_t* __restrict__ total_dev,
+                                                                   const int32_t* __restrict__ slot_done,
+                                                                   unsigned int* __restrict__ counters, int ncounters)
 {
+    // the tile counters of the Phi launches that follow start from zero
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < ncounters; i += gridDim.x * kBlock)
+        counters[(int64_t)i * kCounterStride] = 0u;
     const int nitems = *nitems_dev;
     const int64_t total = *total_dev;
     const int64_t per = ((total + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
@@ -461,6 +513,7 @@ __global__ __launch_bounds__(kBlock) void batch_elementwise_kernel(const BatchCo
     for (int it = lo; it < nitems && items[it].begin < e1; ++it) {
         const BatchCopy c = items[it];
         const int64_t a0 = max(e0, c.begin) - c.begin, a1 = min(e1, c.begin + c.n) - c.begin;
+        if (c.op == 0 && c.slot >= 0 && slot_done[c.slot]) continue;  // keep a stopped slot's last Phi
         if (c.op == 0) {
             double* d = (double*)c.dst;
             for (int64_t i = a0 + threadIdx.x; i < a1; i += kBlock) d[i] = 0.0;
@@ -713,8 +766,16 @@ namespace {
 
 template <int G, int RPL, int NM1, bool MIXED>
 Error batch_launch_t(const BatchSlot* slots, const int32_t* tile_map, const int64_t* class_off,
-                     const int64_t* class_ntiles, int cls, int* grid_cache, hipStream_t s)
+                     const int64_t* class_ntiles, const int32_t* slot_done, unsigned int* counters, int cls,
+                     int* grid_cache, int64_t grid_tiles, hipStream_t s)
 {
+    if (grid_tiles > 0) {
+        if (grid_tiles > 0x7fffffffLL) return {CPAPR_EUNSUPPORTED, "too many tiles in one class"};
+        phi_batch_grid_kernel<G, RPL, NM1, MIXED><<<(unsigned)grid_tiles, kBlock, 0, s>>>(slots, tile_map, class_off,
+                                                                                         slot_done, cls);
+        CPAPR_LAUNCHED();
+        return {CPAPR_OK, ""};
+    }
     if (*grid_cache <= 0) {
         int per_cu = 0, dev = 0, cus = 0;
         CPAPR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, phi_batch_kernel<G, RPL, NM1, MIXED>,
@@ -723,7 +784,8 @@ Error batch_launch_t(const BatchSlot* slots, const int32_t* tile_map, const int6
         CPAPR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         *grid_cache = std::max(1, per_cu) * std::max(1, cus);
     }
-    phi_batch_kernel<G, RPL, NM1, MIXED><<<*grid_cache, kBlock, 0, s>>>(slots, tile_map, class_off, class_ntiles, cls);
+    phi_batch_kernel<G, RPL, NM1, MIXED><<<*grid_cache, kBlock, 0, s>>>(slots, tile_map, class_off, class_ntiles,
+                                                                        slot_done, counters, cls);
     CPAPR_LAUNCHED();
     return {CPAPR_OK, ""};
 }
@@ -755,13 +817,15 @@ int batch_class_of(int G, int RPL, int NM1, bool mixed)
 }
 
 Error launch_phi_batch(int cls, const BatchSlot* slots, const int32_t* tile_map, const int64_t* class_off,
-                       const int64_t* class_ntiles, int* grid_cache, hipStream_t s)
+                       const int64_t* class_ntiles, const int32_t* slot_done, unsigned int* counters,
+                       int* grid_cache, int64_t grid_tiles, hipStream_t s)
 {
     if (cls < 0 || cls >= batch_class_count()) return {CPAPR_EINVAL, "bad batch class"};
     const BatchShape& b = kBatchShapes[cls];
 #define CPAPR_BL(GG, RR, NN, MM)                                                                     \
     if (b.G == GG && b.RPL == RR && b.NM1 == NN && b.mixed == MM)                                    \
-        return batch_launch_t<GG, RR, NN, MM>(slots, tile_map, class_off, class_ntiles, cls, grid_cache, s);
+        return batch_launch_t<GG, RR, NN, MM>(slots, tile_map, class_off, class_ntiles, slot_done, counters, cls,   \
+                                              grid_cache, grid_tiles, s);
 #define CPAPR_BL6(GG, RR)                                                                            \
     CPAPR_BL(GG, RR, 1, false) CPAPR_BL(GG, RR, 2, false) CPAPR_BL(GG, RR, 3, false)                 \
     CPAPR_BL(GG, RR, 1, true) CPAPR_BL(GG, RR, 2, true) CPAPR_BL(GG, RR, 3, true)
@@ -771,10 +835,11 @@ Error launch_phi_batch(int cls, const BatchSlot* slots, const int32_t* tile_map,
     return {CPAPR_EUNSUPPORTED, "no batched Phi kernel for this shape"};
 }
 
-Error launch_batch_elementwise(const BatchCopy* items, const int32_t* nitems_dev, const int64_t* total_dev, int grid,
-                               hipStream_t s)
+Error launch_batch_elementwise(const BatchCopy* items, const int32_t* nitems_dev, const int64_t* total_dev,
+                               const int32_t* slot_done, unsigned int* counters, int grid, hipStream_t s)
 {
-    batch_elementwise_kernel<<<grid, kBlock, 0, s>>>(items, nitems_dev, total_dev);
+    batch_elementwise_kernel<<<grid, kBlock, 0, s>>>(items, nitems_dev, total_dev, slot_done, counters,
+                                                     kBatchCounters);
     CPAPR_LAUNCHED();
     return {CPAPR_OK, ""};
 }

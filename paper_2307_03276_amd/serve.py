@@ -4,11 +4,12 @@ Requests (a sparse count tensor, an initial model, a rank) arrive over time.
 A request is admitted when a batch slot is free and its device footprint fits
 the HBM budget (first come, first served); on admission its tensor is uploaded,
 its plan built (per-mode device sort) and its model placed on the device. Every
-tick runs one MU inner iteration (Algorithm 1) for *all* active requests
-together: one batched Phi launch over each request's current mode
-(cpapr_batch_run, optionally a replayed hipGraph), one batched KKT + MU update
-(cpapr_batch_mu) and one status read-back. The host then advances each
-request's (outer k, mode n, inner l) state exactly as Algorithm 1's loops do;
+tick runs the MU inner loop (Algorithm 1) of the current mode for *all* active requests
+together: the whole inner loop of each request's current mode runs as one
+device sequence (cpapr_batch_inner: l_max x {batched Phi, batched KKT + MU
+update}, a request whose KKT test stops it doing no further work; optionally a
+replayed hipGraph), followed by one status read-back. The host then advances
+each request's (outer k, mode n) state exactly as Algorithm 1's loops do;
 mode transitions run the per-mode prologue / epilogue kernels
 (cpapr_mode_begin / cpapr_mode_end). A request retires when an outer sweep
 makes no update (tol > 0) or after k_max sweeps; its memory returns to the
@@ -52,7 +53,7 @@ class _Active:
         self.lam, self.A, self.B, self.phi = lam, A, B, phi
         self.nbytes = nbytes
         self.N = len(req.X.dims)
-        self.k, self.n, self.l = 1, 0, 0
+        self.k, self.n = 1, 0
         self.any_update = False
         self.updates = 0
         self.last_viol = [0.0] * self.N
@@ -161,8 +162,10 @@ class Server:
 
     # ------------------------------------------------------------------ tick
     def tick(self) -> bool:
-        """Admit what fits, run one inner iteration for every active request.
-        Returns False when nothing is active or queued."""
+        """Admit what fits, then run the inner loop of every active request's
+        current mode together (one device sequence, stops decided on the
+        device) and advance each request to its next mode. Returns False when
+        nothing is active or queued."""
         self._admit()
         if not self.active:
             return bool(self.queue)
@@ -176,25 +179,20 @@ class Server:
         if changed or self._need_commit:
             self.batch.commit(self.stream)
             self._need_commit = False
-        self.batch.run(use_graph=self.use_graph, stream=self.stream)
-        self.batch.mu(self.stream)
-        viol, upd = self.batch.status(self.stream)
-        self.ticks += 1
         lmax, kmax, tol = self.params["lmax"], self.params["kmax"], self.params["tol"]
+        # the whole inner loop of every active request's current mode, stops on the device
+        self.batch.inner(lmax, use_graph=self.use_graph, stream=self.stream)
+        viol, updates, done = self.batch.status(self.stream)
+        self.ticks += 1
         keep = []
         for a in self.active:
-            a.l += 1
             a.last_viol[a.n] = viol[a.slot]
-            if upd[a.slot]:
-                a.updates += 1
+            a.updates += updates[a.slot]
+            if updates[a.slot] > 0:
                 a.any_update = True
-            if upd[a.slot] and a.l < lmax:
-                keep.append(a)
-                continue
             # mode finished: lambda and normalisation, then the next mode
             cpapr.cpapr_mode_end(a.plan.handle, a.n, a.B, a.lam, a.A[a.n], self.stream)
             a.n += 1
-            a.l = 0
             if a.n == a.N:
                 a.n = 0
                 if (tol > 0 and not a.any_update) or a.k >= kmax:

@@ -31,7 +31,7 @@ def _case(i, rng):
     return X, M
 
 
-def _build(cases, precision=cpapr.CPAPR_FP64, seed=0):
+def _build(cases, precision=cpapr.CPAPR_FP64, seed=0, persistent=False):
     import torch
     rng = np.random.default_rng(seed)
     items = []
@@ -43,17 +43,18 @@ def _build(cases, precision=cpapr.CPAPR_FP64, seed=0):
         Phi = torch.full((X.dims[n], M.rank), np.nan, dtype=torch.float64, device="cuda")
         items.append(dict(X=X, M=M, P=P, n=n, A=A, Bh=Bh, B=dev(Bh), Phi=Phi))
     tiles = sum(it["P"].tiles() for it in items)
-    batch = cpapr.Batch(len(items) + 3, tiles + 16)
+    batch = cpapr.Batch(len(items) + 3, tiles + 16, persistent=persistent)
     for s, it in enumerate(items):
         batch.set(s, it["P"], it["n"], it["B"], it["A"], it["Phi"])
     return items, batch
 
 
-def test_batch_matches_oracle_and_single_plan():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_matches_oracle_and_single_plan(persistent):
     import torch
     rng = np.random.default_rng(1)
     cases = [_case(i, rng) for i in range(40)]
-    items, batch = _build(cases)
+    items, batch = _build(cases, persistent=persistent)
     batch.commit()
     batch.run(use_graph=False)
     torch.cuda.synchronize()
@@ -66,13 +67,14 @@ def test_batch_matches_oracle_and_single_plan():
     batch.close()
 
 
-def test_batch_graph_replays_and_slot_changes():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_graph_replays_and_slot_changes(persistent):
     import torch
     rng = np.random.default_rng(2)
     cases = [_case(100 + i, rng) for i in range(24)]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        items, batch = _build(cases, seed=3)
+        items, batch = _build(cases, seed=3, persistent=persistent)
         batch.commit()
         batch.run(use_graph=False)
         torch.cuda.synchronize()
@@ -150,3 +152,39 @@ def test_batch_errors():
     with pytest.raises(cpapr.CpaprError) as ei:
         small.commit()
     assert ei.value.code == -4
+
+
+def test_batch_inner_loop_equals_mu_inner_per_slot():
+    """The batched inner loop with per-slot KKT stops gives, slot by slot, what
+    cpapr_mu_inner gives for that plan alone (B, last Phi, updates)."""
+    import torch
+    rng = np.random.default_rng(9)
+    cases = [_case(300 + i, rng) for i in range(12)]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        items = []
+        for X, M in cases:
+            n = int(rng.integers(0, X.nmodes))
+            Bh = M.factors[n] * M.lam
+            _, _, hist, _ = oracle.mu_inner(X, n, Bh, M.factors, lmax=12)
+            tol = float(hist[int(rng.integers(2, 10))]) * 1.0001  # each slot stops at its own iteration
+            P = cpapr.Plan.from_tensor(X, M.rank, lmax=12, tol=tol)
+            A = [dev(a) for a in M.factors]
+            Phi = torch.zeros((X.dims[n], M.rank), dtype=torch.float64, device="cuda")
+            items.append(dict(X=X, M=M, P=P, n=n, A=A, Bh=Bh, B=dev(Bh), Phi=Phi, tol=tol))
+        b = cpapr.Batch(len(items), sum(it["P"].tiles() for it in items) + 1)
+        for s, it in enumerate(items):
+            b.set(s, it["P"], it["n"], it["B"], it["A"], it["Phi"])
+        b.commit()
+        for use_graph in (False, True, True):
+            for it in items:
+                it["B"].copy_(dev(it["Bh"]))
+            b.inner(12, use_graph=use_graph)
+            viol, upd, done = b.status()
+            for s, it in enumerate(items):
+                Bo, Po, hist, nup = oracle.mu_inner(it["X"], it["n"], it["Bh"], it["M"].factors, lmax=12,
+                                                    tau=it["tol"])
+                assert upd[s] == nup and done[s] == (1 if nup < 12 else 0)
+                assert_parity(host(it["B"]), Bo, 1e-12, f"B slot {s}")
+                assert_parity(host(it["Phi"]), Po, 1e-12, f"Phi slot {s}")
+        b.close()
