@@ -102,6 +102,8 @@ typedef struct cpapr_stats {
     int64_t inner_iters;  /* MU updates performed, summed over modes */
     double kkt_violation; /* largest last-seen max|min(B, 1-Phi)| over modes of the final sweep */
     double loglik;        /* Poisson log-likelihood of the result (solve only) */
+    int64_t phi_evals;    /* Phi computations performed (an inner loop stopped by the KKT test
+                             computes one Phi more than it updates) */
 } cpapr_stats;
 
 typedef struct cpapr_plan cpapr_plan;

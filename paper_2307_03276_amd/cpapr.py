@@ -48,7 +48,7 @@ class cpapr_params(C.Structure):
 
 class cpapr_stats(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("converged", C.c_int32), ("inner_iters", C.c_int64),
-                ("kkt_violation", C.c_double), ("loglik", C.c_double)]
+                ("kkt_violation", C.c_double), ("loglik", C.c_double), ("phi_evals", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

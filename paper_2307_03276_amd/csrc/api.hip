@@ -188,7 +188,7 @@ Error enqueue_inner(cpapr_plan* P, int mode, double* B, const void* const* fac, 
 struct HostState {
     double last_viol[CPAPR_MAX_MODES];
     int done, updates, sweep_updates;
-    long long total_updates;
+    long long total_updates, phi_evals;
     double ll;
 };
 
@@ -198,6 +198,7 @@ Error read_state(const cpapr_plan* P, HostState* h, hipStream_t s)
     CPAPR_HIP(hipMemcpyAsync(h->last_viol, d->last_viol, sizeof(h->last_viol), hipMemcpyDeviceToHost, s));
     CPAPR_HIP(hipMemcpyAsync(&h->done, &d->done, sizeof(int) * 3, hipMemcpyDeviceToHost, s));
     CPAPR_HIP(hipMemcpyAsync(&h->total_updates, &d->total_updates, sizeof(long long), hipMemcpyDeviceToHost, s));
+    CPAPR_HIP(hipMemcpyAsync(&h->phi_evals, &d->phi_evals, sizeof(long long), hipMemcpyDeviceToHost, s));
     CPAPR_HIP(hipMemcpyAsync(&h->ll, &d->ll, sizeof(double), hipMemcpyDeviceToHost, s));
     CPAPR_HIP(hipStreamSynchronize(s));
     return {CPAPR_OK, ""};
@@ -400,6 +401,7 @@ int cpapr_mu_inner(cpapr_plan* plan, int32_t mode, double* B, const double* cons
             out->inner_iters = h.updates;
             out->kkt_violation = h.last_viol[mode];
             out->loglik = NAN;
+            out->phi_evals = h.phi_evals;
         }
         return CPAPR_OK;
     } catch (...) {
@@ -473,6 +475,7 @@ int cpapr_solve(cpapr_plan* plan, double* lambda, double* const* A, cpapr_stats*
             for (int n = 0; n < N; ++n) kkt = std::max(kkt, h.last_viol[n]);
             out->kkt_violation = kkt;
             out->loglik = h.ll;
+            out->phi_evals = h.phi_evals;
         }
         return CPAPR_OK;
     } catch (...) {

@@ -33,6 +33,7 @@ struct DevState {
     int sweep_updates;                                      // MU updates in the current outer sweep
     int pad;
     long long total_updates;                                // MU updates since the last reset
+    long long phi_evals;                                    // Phi computations since the last reset
     double ll;                                              // log-likelihood result
 };
 

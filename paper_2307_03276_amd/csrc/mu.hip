@@ -51,6 +51,7 @@ __global__ __launch_bounds__(kBlock) void reset_state_kernel(DevState* st, int n
         if (new_sweep) st->sweep_updates = 0;
         if (all) {
             st->total_updates = 0;
+            st->phi_evals = 0;
             for (int m = 0; m < CPAPR_MAX_MODES; ++m) st->last_viol[m] = 0.0;
         }
     }
@@ -78,6 +79,7 @@ __global__ __launch_bounds__(kBlock) void kkt_kernel(const double* __restrict__ 
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
+        if (blockIdx.x == 0) st->phi_evals += 1;  // this iteration's Phi was computed
         double m = red[0];
         for (int w = 1; w < kBlock / 64; ++w) m = fmax(m, red[w]);
         const int slot = blockIdx.x % kViolSlots;

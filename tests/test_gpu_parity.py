@@ -187,7 +187,7 @@ def test_mu_inner_fixed_schedule():
         B = dev(Bh)
         phi_last, st = P.mu_inner(n, B, A)
         Bo, Po, hist, nup = oracle.mu_inner(X, n, Bh, M.factors, lmax=10)
-        assert st["inner_iters"] == nup == 10
+        assert st["inner_iters"] == nup == 10 and st["phi_evals"] == 10
         assert_parity(host(B), Bo, TOL64, f"B mode {n}")
         assert_parity(host(phi_last), Po, TOL64, f"Phi mode {n}")
         assert abs(st["kkt_violation"] - hist[-1]) <= 1e-12 * max(1.0, hist[-1])
@@ -206,6 +206,7 @@ def test_mu_inner_kkt_stop():
     B = dev(Bh)
     phi_last, st = P.mu_inner(n, B, [dev(a) for a in M.factors])
     assert st["inner_iters"] == nup_o
+    assert st["phi_evals"] == nup_o + 1  # the Phi that triggered the stop is computed too
     assert_parity(host(B), Bo, TOL64, "B")
     assert_parity(host(phi_last), Po, TOL64, "Phi_last")
     P.close()
@@ -221,6 +222,8 @@ def _solve_case(X, M, kmax, lmax, tau, tol, elementwise=True, **kw):
     out, ost = oracle.solve(X, M, kmax=kmax, lmax=lmax, tau=tau)
     assert st["outer_iters"] == ost["outer_iters"]
     assert st["inner_iters"] == ost["inner_updates"]
+    # one Phi per update, plus one per inner loop that stopped on the KKT test
+    assert st["inner_iters"] <= st["phi_evals"] <= st["inner_iters"] + st["outer_iters"] * X.nmodes
     assert bool(st["converged"]) == ost["converged"]
     assert_parity(host(lam), out.lam, tol, "lambda")
     for n in range(X.nmodes):
