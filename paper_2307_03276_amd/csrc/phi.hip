@@ -152,6 +152,28 @@ struct Acc<true> {
     __device__ double value() const { return (double)hi + (double)lo; }
 };
 
+// q = x / m for normal, finite m > 0 (m is clamped to eps > 0 before): the
+// hardware reciprocal estimate, one Newton step r <- r + r(1 - m r), then one
+// residual correction q <- q + r(x - m q) with the residual formed exactly by
+// an FMA. The result is within an ulp of the rounded quotient; the IEEE
+// division sequence's scaling for denormal and huge operands is not needed in
+// this range.
+__device__ __forceinline__ double div_pos(double x, double m)
+{
+    double r = __builtin_amdgcn_rcp(m);
+    r = __builtin_fma(r, __builtin_fma(-m, r, 1.0), r);
+    const double q = x * r;
+    return __builtin_fma(r, __builtin_fma(-m, q, x), q);
+}
+
+__device__ __forceinline__ float div_pos(float x, float m)
+{
+    float r = __builtin_amdgcn_rcpf(m);
+    r = __builtin_fmaf(r, __builtin_fmaf(-m, r, 1.f), r);
+    const float q = x * r;
+    return __builtin_fmaf(r, __builtin_fmaf(-m, q, x), q);
+}
+
 // What the segmented kernel computes per nonzero and where it goes.
 constexpr int kPhi = 0;     // s_k = x_k / max(m_k, eps); Phi[i_n] += s_k pi_k
 constexpr int kMttkrp = 1;  // s_k = x_k;                  M[i_n]  += s_k pi_k
@@ -170,7 +192,7 @@ __device__ __forceinline__ T nonzero_scale(const T (&b)[RPL], const T (&pi)[RPL]
         for (int c = 0; c < RPL; ++c) d = __builtin_fma(b[c], pi[c], d);
         d = group_sum<G>(d);
         if constexpr (KIND == kLoglik) return x * log(d > eps ? d : eps);
-        return x / (d > eps ? d : eps);
+        return div_pos(x, d > eps ? d : eps);
     } else {
         float hi = 0.f, lo = 0.f;
 #pragma unroll
@@ -178,7 +200,7 @@ __device__ __forceinline__ T nonzero_scale(const T (&b)[RPL], const T (&pi)[RPL]
         group_sum_pair<G>(hi, lo);
         const float m = hi + lo;
         const float e = (float)eps;
-        return (float)x / (m > e ? m : e);
+        return div_pos((float)x, m > e ? m : e);
     }
 }
 
