@@ -122,7 +122,7 @@ Layout layout(int N, int64_t nnz, const int64_t* dims, int R, bool mixed)
     s += align256((size_t)N * R * 8);
     L.state = off + s;
     s += align256(sizeof(cpapr::DevState));
-    s = std::max(s, (size_t)cpapr::sort_scratch_bytes(nnz));
+    s = std::max(s, (size_t)cpapr::sort_scratch_bytes(nnz, N));
     L.total = off + s;
     return L;
 }

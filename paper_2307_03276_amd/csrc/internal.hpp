@@ -127,7 +127,7 @@ namespace cpapr {
 constexpr int kPartials = 512;   // blocks of the two-level deterministic column sums
 
 // ---- plan construction (sort.hip) ----
-int64_t sort_scratch_bytes(int64_t nnz);
+int64_t sort_scratch_bytes(int64_t nnz, int N);
 // Validates coordinates/values, then builds the sorted copies of every mode.
 Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t s);
 

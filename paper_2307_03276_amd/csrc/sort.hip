@@ -34,19 +34,38 @@ struct DimsArg {
     int64_t d[CPAPR_MAX_MODES];
 };
 
+// Nonzero record: the N coordinates (int32 words 0..N-1) and the value (the
+// last two words) of one nonzero in 32 bytes (N <= 6) or 64 bytes (N = 7, 8).
+// The per-mode gathers through a sort permutation then touch one record per
+// nonzero instead of N + 1 separate arrays.
+inline int record_words(int N) { return N <= 6 ? 8 : 16; }
+
+// Validates the input and packs it into records in the same pass.
 // flags bit 0: coordinate out of range; bit 1: value not finite or <= 0.
-__global__ __launch_bounds__(kBlock) void validate_kernel(const int32_t* __restrict__ idx,
-                                                          const double* __restrict__ vals, int64_t nnz,
-                                                          int N, DimsArg dims, int* flags)
+template <int RSW>
+__global__ __launch_bounds__(kBlock) void validate_pack_kernel(const int32_t* __restrict__ idx,
+                                                               const double* __restrict__ vals, int64_t nnz,
+                                                               int N, DimsArg dims, int* flags,
+                                                               uint4* __restrict__ rec)
 {
     int bad = 0;
     for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kBlock) {
-        for (int m = 0; m < N; ++m) {
-            int32_t c = idx[(int64_t)m * nnz + k];
-            if (c < 0 || (int64_t)c >= dims.d[m]) bad |= 1;
+        int32_t w[RSW];
+#pragma unroll
+        for (int m = 0; m < RSW - 2; ++m) {
+            w[m] = 0;
+            if (m < N) {
+                const int32_t c = idx[(int64_t)m * nnz + k];
+                if (c < 0 || (int64_t)c >= dims.d[m]) bad |= 1;
+                w[m] = c;
+            }
         }
-        double v = vals[k];
+        const double v = vals[k];
         if (!(v > 0.0) || !(v <= 1.7976931348623157e308)) bad |= 2;
+        __builtin_memcpy(&w[RSW - 2], &v, sizeof(double));
+        uint4* r = rec + k * (RSW / 4);
+#pragma unroll
+        for (int i = 0; i < RSW / 4; ++i) r[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
     }
     if (bad) atomicOr(flags, bad);
 }
@@ -204,24 +223,42 @@ __global__ __launch_bounds__(kBlock) void permute_keys_kernel(const int32_t* __r
     }
 }
 
-// Copy sorted keys to the row array and gather values and the other modes'
-// factor row offsets (coordinate x R) through the permutation (perm == nullptr:
-// identity).
-__global__ __launch_bounds__(kBlock) void gather_sorted_kernel(
-    const int32_t* __restrict__ idx, const double* __restrict__ vals, int64_t nnz, int N, int mode,
-    const int32_t* __restrict__ perm, int R, int32_t* __restrict__ rows, uint32_t* __restrict__ cofs,
-    double* __restrict__ svals)
+// Write the sorted copy of one mode: row, value and the other modes' factor
+// row offsets (coordinate x R), read from the records through the permutation
+// (perm == nullptr: identity).
+template <int RSW>
+__global__ __launch_bounds__(kBlock) void gather_sorted_kernel(const uint4* __restrict__ rec, int64_t nnz, int N,
+                                                               int mode, const int32_t* __restrict__ perm, int R,
+                                                               int32_t* __restrict__ rows,
+                                                               uint32_t* __restrict__ cofs,
+                                                               double* __restrict__ svals)
 {
     for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * kBlock) {
         int64_t k = perm ? perm[p] : p;
         if (k < 0 || k >= nnz) k = p;  // a permutation never leaves [0, nnz); keeps reads in bounds
-        rows[p] = idx[(int64_t)mode * nnz + k];
-        svals[p] = vals[k];
+        int32_t w[RSW];
+        const uint4* r = rec + k * (RSW / 4);
+#pragma unroll
+        for (int i = 0; i < RSW / 4; ++i) {
+            const uint4 q = r[i];
+            w[4 * i] = (int32_t)q.x;
+            w[4 * i + 1] = (int32_t)q.y;
+            w[4 * i + 2] = (int32_t)q.z;
+            w[4 * i + 3] = (int32_t)q.w;
+        }
+        double v;
+        __builtin_memcpy(&v, &w[RSW - 2], sizeof(double));
+        svals[p] = v;
         int j = 0;
-        for (int m = 0; m < N; ++m) {
-            if (m == mode) continue;
-            cofs[(int64_t)j * nnz + p] = (uint32_t)idx[(int64_t)m * nnz + k] * (uint32_t)R;
-            ++j;
+#pragma unroll
+        for (int m = 0; m < RSW - 2; ++m) {
+            if (m >= N) break;
+            if (m == mode) {
+                rows[p] = w[m];
+            } else {
+                cofs[(int64_t)j * nnz + p] = (uint32_t)w[m] * (uint32_t)R;
+                ++j;
+            }
         }
     }
 }
@@ -282,11 +319,12 @@ Error exclusive_scan(int* a, int64_t n, int* sums, hipStream_t s)
 
 }  // namespace
 
-int64_t sort_scratch_bytes(int64_t nnz)
+int64_t sort_scratch_bytes(int64_t nnz, int N)
 {
     const int64_t ntiles = cdiv(nnz > 0 ? nnz : 1, kSortTile);
     const int64_t ncounts = ntiles * kRadix;
     size_t b = 0;
+    b += align256((size_t)nnz * 4 * record_words(N));       // nonzero records
     b += 4 * align256((size_t)nnz * 4);                     // keys/payload ping-pong
     b += align256((size_t)ncounts * 4);                     // histogram table
     b += align256((size_t)cdiv(ncounts, kScanChunk) * 4 + 4);  // scan chunk sums
@@ -307,6 +345,8 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
         q += align256(bytes);
         return r;
     };
+    const int rsw = record_words(N);
+    uint4* rec = (uint4*)take((size_t)nnz * 4 * rsw);
     int32_t* ka = (int32_t*)take((size_t)nnz * 4);
     int32_t* kb = (int32_t*)take((size_t)nnz * 4);
     int32_t* pa = (int32_t*)take((size_t)nnz * 4);
@@ -322,7 +362,10 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
     if (nnz > 0) {
         DimsArg d{};
         for (int m = 0; m < N; ++m) d.d[m] = P->dims[m];
-        validate_kernel<<<grid_for(nnz), kBlock, 0, s>>>(X->idx, X->vals, nnz, N, d, flags);
+        if (rsw == 8)
+            validate_pack_kernel<8><<<grid_for(nnz), kBlock, 0, s>>>(X->idx, X->vals, nnz, N, d, flags, rec);
+        else
+            validate_pack_kernel<16><<<grid_for(nnz), kBlock, 0, s>>>(X->idx, X->vals, nnz, N, d, flags, rec);
         CPAPR_LAUNCHED();
     }
     int hflags = 0;
@@ -386,8 +429,12 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
             Error e = passes(P->dims[n]);
             if (e.code) return e;
         }
-        gather_sorted_kernel<<<grid_for(nnz), kBlock, 0, s>>>(X->idx, X->vals, nnz, N, n, pin, P->R, pm.rows, pm.cofs,
-                                                              pm.vals);
+        if (rsw == 8)
+            gather_sorted_kernel<8><<<grid_for(nnz), kBlock, 0, s>>>(rec, nnz, N, n, pin, P->R, pm.rows, pm.cofs,
+                                                                     pm.vals);
+        else
+            gather_sorted_kernel<16><<<grid_for(nnz), kBlock, 0, s>>>(rec, nnz, N, n, pin, P->R, pm.rows, pm.cofs,
+                                                                      pm.vals);
         CPAPR_LAUNCHED();
         const int gseg = std::min(grid_for(nnz), kSegPartials);
         count_segments_kernel<<<gseg, kBlock, 0, s>>>(pm.rows, nnz, segpart);
