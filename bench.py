@@ -176,7 +176,9 @@ def batch_workload(args):
                           "launches_per_step": 3 * len(items)},
         "speedup_vs_one_at_a_time": ms_single / ms_batched,
         "max_rel_err_vs_oracle_sampled": worst,
-        "autotuner": {k: {"group": v["group"], "chunk": v["chunk"], "ms": v["ms"]} for k, v in choices.items()},
+        "autotuner": {k: {"group": v["group"], "chunk": v["chunk"], "ms": v["ms"],
+                          "model": v.get("model"), "model_vs_tuned": v.get("model_vs_tuned")}
+                      for k, v in choices.items()},
     }
     print(json.dumps(out), flush=True)
 

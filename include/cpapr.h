@@ -91,7 +91,7 @@ typedef struct cpapr_params {
     int32_t precision; /* CPAPR_FP64 or CPAPR_MIXED */
     int32_t variant;   /* CPAPR_VARIANT_* */
     int32_t group;     /* lanes per nonzero (0 = by rank; else 4, 8, 16, 32 or 64) */
-    int32_t chunk;     /* nonzeros per lane group per tile (0 = default) */
+    int32_t chunk;     /* nonzeros per lane group per tile (0 = launch-policy model) */
     int32_t sort;      /* CPAPR_SORT_*: order of the nonzeros inside each row of a mode */
 } cpapr_params;
 
@@ -128,10 +128,17 @@ int cpapr_plan_destroy(cpapr_plan* plan);
 
 /* Change the Phi launch shape of an existing plan (lanes per nonzero `group`:
  * 0 = by rank, else 4, 8, 16, 32 or 64; nonzeros per lane group per tile
- * `chunk`: 0 = default, else 1..65536). Host-only; used by the autotuner to
+ * `chunk`: 0 = launch-policy model, else 1..65536). Host-only; used by the autotuner to
  * time shapes without re-sorting. Returns CPAPR_EUNSUPPORTED for shapes with
  * no kernel at this rank and mode count. */
 int cpapr_plan_set_shape(cpapr_plan* plan, int32_t group, int32_t chunk);
+
+/* The Phi launch shape a plan uses: lanes per nonzero and nonzeros per lane
+ * group per tile. With group 0 (params or cpapr_plan_set_shape) the group
+ * follows the rank; with chunk 0 the chunk comes from a launch-policy model
+ * (512-nonzero tiles in FP64, 1024 with FP32-stored factors; the kind of
+ * heuristic the paper names as future work in Section 4). Host-only. */
+int cpapr_plan_shape(const cpapr_plan* plan, int32_t* group, int32_t* chunk);
 
 /* Number of nonempty rows (segments) of mode `mode` (host query). */
 int64_t cpapr_plan_segments(const cpapr_plan* plan, int32_t mode);

@@ -74,6 +74,7 @@ def load():
         "cpapr_plan_destroy": (C.c_int, [vp]),
         "cpapr_plan_segments": (i64, [vp, i32]),
         "cpapr_plan_set_shape": (C.c_int, [vp, i32, i32]),
+        "cpapr_plan_shape": (C.c_int, [vp, P(i32), P(i32)]),
         "cpapr_phi": (C.c_int, [vp, i32, vp, P(vp), dbl, vp, vp]),
         "cpapr_mu_inner": (C.c_int, [vp, i32, vp, P(vp), vp, P(cpapr_stats), vp]),
         "cpapr_solve": (C.c_int, [vp, vp, P(vp), P(cpapr_stats), vp]),
@@ -108,7 +109,7 @@ def load():
 
 
 EXPORTED = ("cpapr_params_default", "cpapr_plan_workspace_size", "cpapr_plan_create", "cpapr_plan_destroy",
-            "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_phi", "cpapr_mu_inner", "cpapr_solve", "cpapr_loglik",
+            "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_plan_shape", "cpapr_phi", "cpapr_mu_inner", "cpapr_solve", "cpapr_loglik",
             "cpapr_mttkrp", "cpapr_batch_workspace_size", "cpapr_batch_tiles", "cpapr_batch_create", "cpapr_batch_create2",
             "cpapr_batch_destroy", "cpapr_batch_set", "cpapr_batch_clear", "cpapr_batch_commit", "cpapr_batch_run",
             "cpapr_batch_mu", "cpapr_batch_inner", "cpapr_batch_status", "cpapr_mode_begin", "cpapr_mode_end", "cpapr_plan_sync_f32",
@@ -183,6 +184,12 @@ def cpapr_plan_destroy(h):
 
 def cpapr_plan_set_shape(h, group: int, chunk: int):
     return _check(load().cpapr_plan_set_shape(h, group, chunk))
+
+
+def cpapr_plan_shape(h):
+    g, c = C.c_int32(0), C.c_int32(0)
+    _check(load().cpapr_plan_shape(h, C.byref(g), C.byref(c)))
+    return g.value, c.value
 
 
 def cpapr_plan_segments(h, mode: int) -> int:
@@ -380,6 +387,10 @@ class Plan:
     def set_shape(self, group, chunk):
         cpapr_plan_set_shape(self.handle, group, chunk)
         self.params.group, self.params.chunk = group, chunk
+
+    def shape(self):
+        """(lanes per nonzero, nonzeros per lane group per tile) of the Phi launch."""
+        return cpapr_plan_shape(self.handle)
 
     def tiles(self):
         return cpapr_batch_tiles(self.handle)

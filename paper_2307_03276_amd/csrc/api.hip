@@ -290,7 +290,7 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
         P->ws = w;
         P->ws_bytes = ws_bytes;
         P->group = cpapr::resolve_group(R, p->group, X->nmodes - 1);
-        P->chunk = cpapr::resolve_chunk(P->group, p->chunk);
+        P->chunk = cpapr::resolve_chunk(P->group, p->chunk);  // replaced by the model below if 0
         for (int n = 0; n < P->N; ++n) {
             P->mode[n].rows = (int32_t*)(w + L.mode_rows[n]);
             P->mode[n].cofs = (uint32_t*)(w + L.mode_cidx[n]);
@@ -310,6 +310,7 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
             delete P;
             return report(e);
         }
+        if (p->chunk == 0) P->chunk = cpapr::model_chunk(P, P->group);
         e = cpapr::launch_reset_state(P->state, true, true, s);
         if (e.code) {
             delete P;
@@ -342,7 +343,15 @@ int cpapr_plan_set_shape(cpapr_plan* plan, int32_t group, int32_t chunk)
     if (e.code) return report(e);
     plan->params = p;
     plan->group = cpapr::resolve_group(plan->R, group, plan->N - 1);
-    plan->chunk = cpapr::resolve_chunk(plan->group, chunk);
+    plan->chunk = chunk > 0 ? chunk : cpapr::model_chunk(plan, plan->group);
+    return CPAPR_OK;
+}
+
+int cpapr_plan_shape(const cpapr_plan* plan, int32_t* group, int32_t* chunk)
+{
+    if (!plan) return fail(CPAPR_EINVAL, "plan is NULL");
+    if (group) *group = plan->group;
+    if (chunk) *chunk = plan->chunk;
     return CPAPR_OK;
 }
 

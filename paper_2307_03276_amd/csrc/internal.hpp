@@ -137,6 +137,7 @@ bool phi_shape_supported(int group, int rpl, int nmodes_other);
 // Resolve the lane-group size for rank R (the `group` parameter, 0 = automatic).
 int resolve_group(int R, int requested, int nm1);
 int resolve_chunk(int group, int requested);
+int model_chunk(const cpapr_plan* P, int group);  // default chunk once segments are known
 // Rank columns per lane (1, 2 or 4) for rank R on `group` lanes; -1 if R > 4 * group.
 int rank_block(int R, int group);
 Error launch_phi(const cpapr_plan* P, int mode, const double* B, const void* const* fac, bool mixed,

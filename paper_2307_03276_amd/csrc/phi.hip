@@ -751,6 +751,19 @@ int resolve_chunk(int group, int requested)
     return 512 / (kBlock / group);
 }
 
+// Launch-policy model for the nonzeros per lane group per tile, in place of a
+// measured search (the paper leaves such a heuristic as future work, Section 4).
+// Fitted to chunk sweeps at the default lane groups on single Zipf tensors and
+// on batches of small uniform ones: 512-nonzero tiles are best or within a few
+// percent of best for FP64 at every rank measured; with FP32-stored factors,
+// whose per-nonzero work is larger, 1024-nonzero tiles are (fewer tile merges
+// and boundary atomics per nonzero). Row length had no consistent effect.
+int model_chunk(const cpapr_plan* P, int group)
+{
+    const int tile = P->params.precision == CPAPR_MIXED ? 1024 : 512;
+    return std::max(1, tile / (kBlock / group));
+}
+
 Error launch_phi(const cpapr_plan* P, int mode, const double* B, const void* const* fac, bool mixed,
                  double eps, double* Phi, const int* done, hipStream_t s)
 {

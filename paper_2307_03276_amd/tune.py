@@ -108,22 +108,32 @@ class Autotuner:
         self.save()
         return choices
 
+    def _time_batch(self, its: Sequence[dict]) -> float:
+        tiles = sum(it["P"].tiles() for it in its)
+        b = cpapr.Batch(len(its), tiles + 1)
+        for s, it in enumerate(its):
+            b.set(s, it["P"], it["n"], it["B"], it["A"], it["Phi"])
+        b.commit()
+        ms = _time(lambda: b.run(use_graph=False), self.reps)
+        b.close()
+        return ms
+
     def _search(self, its: Sequence[dict], nm: int, R: int) -> dict:
         results = []
         for G, chunk in shape_candidates(R, nm):
             for it in its:
                 it["P"].set_shape(G, chunk)
-            tiles = sum(it["P"].tiles() for it in its)
-            b = cpapr.Batch(len(its), tiles + 1)
-            for s, it in enumerate(its):
-                b.set(s, it["P"], it["n"], it["B"], it["A"], it["Phi"])
-            b.commit()
-            ms = _time(lambda: b.run(use_graph=False), self.reps)
-            b.close()
-            results.append((ms, G, chunk))
+            results.append((self._time_batch(its), G, chunk))
         results.sort()
         ms, G, chunk = results[0]
+        # the library's launch-policy model (group by rank, chunk from precision,
+        # rank and row length, per plan), timed on the same slots
+        for it in its:
+            it["P"].set_shape(0, 0)
+        model = sorted({it["P"].shape() for it in its})
+        model_ms = self._time_batch(its)
         return {"group": G, "chunk": chunk, "ms": ms,
+                "model": [list(m) for m in model], "model_ms": model_ms, "model_vs_tuned": model_ms / ms,
                 "candidates": [{"group": g, "chunk": c, "ms": round(t, 4)} for t, g, c in results]}
 
     def tune_sort(self, make_plan, modes: Iterable[int], operands) -> int:

@@ -117,3 +117,5 @@ def test_calls_reject_null_plan(lib):
     assert lib.cpapr_loglik(None, None, arr, 1e-10, None, None) == -1
     assert lib.cpapr_mttkrp(None, 0, arr, None, None) == -1
     assert lib.cpapr_plan_segments(None, 0) == -1
+    g = C.c_int32(0)
+    assert lib.cpapr_plan_shape(None, C.byref(g), C.byref(g)) == -1

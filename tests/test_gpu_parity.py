@@ -178,6 +178,25 @@ def test_invalid_inputs_are_rejected():
 
 # ---------------------------------------------------------------- MU inner loop, solve, loglik
 
+def test_launch_policy_model_shapes():
+    """Default launch shape: lanes by rank, chunk from the policy model (512-
+    nonzero tiles in FP64, 1024 with FP32-stored factors); explicit shapes are
+    kept, and the model returns when the chunk is reset."""
+    X, M, _ = synth.config_small()
+    P = cpapr.Plan.from_tensor(X, 10)
+    assert P.shape() == (8, 16)
+    P.set_shape(16, 40)
+    assert P.shape() == (16, 40)
+    P.set_shape(0, 0)
+    assert P.shape() == (8, 16)
+    P.set_shape(16, 0)
+    assert P.shape() == (16, 32)
+    P.close()
+    Pm = cpapr.Plan.from_tensor(X, 10, precision=cpapr.CPAPR_MIXED)
+    assert Pm.shape() == (8, 32)
+    Pm.close()
+
+
 def test_mu_inner_fixed_schedule():
     X, M, _ = synth.config_small()
     P = cpapr.Plan.from_tensor(X, 10, lmax=10, tol=0.0)
