@@ -167,3 +167,50 @@ def mttkrp(X, mode, factors):
     rc = lib.oracle_mttkrp(*keep[3], C.c_int(mode), C.c_int(R), ptrs, _ptr(out))
     _check(rc, "mttkrp")
     return out
+
+
+def pqnr_inner(X, mode, B, factors, lmax, tau=0.0, eps=1e-10, rows=None):
+    """PQNR row solves of one mode (projected quasi-Newton per row of B; the
+    paper names the variant in its Background). Rows are independent, so
+    ``rows`` restricts the work exactly for any tau. Returns (B, stats) with
+    stats: n_updates (most steps of any row), row_steps (sum over rows),
+    last_viol (largest last KKT violation over rows), steps (per row)."""
+    lib = _load()
+    keep = _tensor_args(X)
+    R = B.shape[1]
+    Bw = np.array(B, dtype=np.float64, copy=True, order="C")
+    arrs, ptrs = _fac_array(factors)
+    In = X.dims[mode]
+    mask = None
+    if rows is not None:
+        mask = np.zeros(In, dtype=np.uint8)
+        mask[np.asarray(rows)] = 1
+    nup = C.c_int(0)
+    total = C.c_int64(0)
+    last = C.c_double(0)
+    steps = np.zeros(In, dtype=np.int32)
+    rc = lib.oracle_pqnr_inner_rows(*keep[3], C.c_int(mode), C.c_int(R), _ptr(Bw), ptrs, C.c_int(lmax),
+                                    C.c_double(tau), C.c_double(eps),
+                                    _ptr(mask, C.c_uint8) if mask is not None else None,
+                                    C.byref(nup), C.byref(total), C.byref(last), _ptr(steps, C.c_int32))
+    _check(rc, "pqnr_inner")
+    return Bw, dict(n_updates=int(nup.value), row_steps=int(total.value), last_viol=last.value, steps=steps)
+
+
+def pqnr_solve(X, model, kmax, lmax, tau=0.0, eps=1e-10):
+    """CP-APR with PQNR row solves in place of the MU inner loop (no S shift).
+    Returns (model, stats dict); the input model is not modified."""
+    lib = _load()
+    keep = _tensor_args(X)
+    lam = np.array(model.lam, dtype=np.float64, copy=True)
+    arrs, ptrs = _fac_array([a.copy() for a in model.factors])
+    outer = C.c_int(0)
+    steps = C.c_int64(0)
+    conv = C.c_int(0)
+    kkt = C.c_double(0)
+    rc = lib.oracle_pqnr_solve(*keep[3], C.c_int(model.rank), _ptr(lam), ptrs, C.c_int(kmax), C.c_int(lmax),
+                               C.c_double(tau), C.c_double(eps), C.byref(outer), C.byref(steps), C.byref(conv),
+                               C.byref(kkt))
+    _check(rc, "pqnr_solve")
+    return _Kruskal(lam, arrs), dict(outer_iters=outer.value, row_steps=steps.value,
+                                  converged=bool(conv.value), kkt=kkt.value)

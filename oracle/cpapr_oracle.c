@@ -300,3 +300,311 @@ int oracle_mttkrp(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* i
     free(t);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * PQNR: projected quasi-Newton for the row subproblems.
+ *
+ * The paper names this CP-APR variant (Background: each row of a mode's
+ * factor is its own subproblem and converges independently) but prints no
+ * algorithm; the readings below follow the row-subproblem formulation of the
+ * method it cites, written from that formulation:
+ *
+ *   f_i(b) = sum_r b_r - sum_{k in row i} x_k log(max(b . pi_k, eps)),  b >= 0,
+ *
+ * the negative Poisson log-likelihood of row i of B = A(n) Lambda with the
+ * other factors' columns summing to one (so the linear term is sum_r b_r).
+ * Its gradient is g = 1 - phi_i with phi_i row i of Phi(n) (Algorithm 2), so
+ * KKT is min(b, g) = 0, the same test as the MU loop.
+ *
+ * One iteration of one row, given b >= 0:
+ *   1. phi = sum_k x_k/max(m_k, eps) pi_k, g = 1 - phi, viol = max|min(b, g)|;
+ *      stop the row when tau > 0 and viol < tau.
+ *   2. After a step: s = last step, y = g - g_prev; keep (s, y) (at most
+ *      PQNR_MEM pairs, oldest dropped) when s.y > PQNR_CURV |s| |y|.
+ *   3. Bound set: b_r == 0 and g_r > 0; the others are free.
+ *   4. Direction: without pairs the scaled gradient -b .* g (the MU step);
+ *      with pairs the L-BFGS two-loop recursion over the free set (pairs with
+ *      free-set curvature <= 0 skipped, initial scaling s.y / y.y of the newest
+ *      usable pair), zero on bound entries; if g.d >= 0, or no pair is usable,
+ *      the scaled gradient.
+ *   5. Projected backtracking: for alpha = 1, 1/2, ... (PQNR_TRIALS trials)
+ *      delta = max(b + alpha d, 0) - b; accept the first with g.delta < 0 and
+ *      f(b + delta) - f(b) <= PQNR_SIGMA g.delta, where the decrease is
+ *      formed term by term (sum_r delta_r - sum_k x_k log1p(delta.pi_k / m_k),
+ *      with the clamped logs where m or m + delta.pi reaches eps) instead of
+ *      as a difference of two large sums. With no acceptable trial the MU step
+ *      b .* phi is taken (it never increases f).
+ *   6. b <- b + delta; the iteration counts as an update.
+ * ------------------------------------------------------------------------ */
+#define PQNR_MEM 3
+#define PQNR_CURV 1e-10
+#define PQNR_SIGMA 1e-4
+#define PQNR_TRIALS 10
+
+typedef struct {
+    int R, count, head; /* ring of pairs: newest at head - 1 */
+    double s[PQNR_MEM][256], y[PQNR_MEM][256];
+} pqnr_pairs;
+
+static double dot_masked(int R, const double* a, const double* b, const uint8_t* free_set)
+{
+    double t = 0.0;
+    for (int r = 0; r < R; ++r)
+        if (!free_set || free_set[r]) t += a[r] * b[r];
+    return t;
+}
+
+/* one row of one mode: nz[] are the row's nonzero ids, pis[j*R..] their pi */
+static void pqnr_row(int R, int64_t nrow, const double* xs, const double* pis, double* b,
+                     int lmax, double tau, double eps, int* steps_out, double* viol_out)
+{
+    pqnr_pairs P;
+    P.R = R;
+    P.count = 0;
+    P.head = 0;
+    double phi[256], comp[256], g[256], gprev[256], d[256], q[256], delta[256], slast[256];
+    double a[PQNR_MEM];
+    uint8_t fr[256];
+    int steps = 0;
+    double viol = 0.0;
+    for (int l = 0; l < lmax; ++l) {
+        /* 1. gradient from Phi's row */
+        for (int r = 0; r < R; ++r) phi[r] = comp[r] = 0.0;
+        for (int64_t j = 0; j < nrow; ++j) {
+            const double* pi = pis + j * R;
+            double m = 0.0;
+            for (int r = 0; r < R; ++r) m += b[r] * pi[r];
+            const double sc = xs[j] / (m > eps ? m : eps);
+            for (int r = 0; r < R; ++r) neumaier_add(&phi[r], &comp[r], sc * pi[r]);
+        }
+        viol = 0.0;
+        for (int r = 0; r < R; ++r) {
+            phi[r] += comp[r];
+            g[r] = 1.0 - phi[r];
+            const double t = fabs(b[r] < g[r] ? b[r] : g[r]);
+            if (t > viol) viol = t;
+        }
+        if (tau > 0.0 && viol < tau) break;
+        /* 2. curvature pair from the previous step */
+        if (l > 0) {
+            double y[256];
+            for (int r = 0; r < R; ++r) y[r] = g[r] - gprev[r];
+            const double sy = dot_masked(R, slast, y, NULL);
+            const double ss = dot_masked(R, slast, slast, NULL), yy = dot_masked(R, y, y, NULL);
+            if (sy > PQNR_CURV * sqrt(ss * yy)) {
+                for (int r = 0; r < R; ++r) {
+                    P.s[P.head][r] = slast[r];
+                    P.y[P.head][r] = y[r];
+                }
+                P.head = (P.head + 1) % PQNR_MEM;
+                if (P.count < PQNR_MEM) ++P.count;
+            }
+        }
+        /* 3. free set */
+        for (int r = 0; r < R; ++r) fr[r] = !(b[r] == 0.0 && g[r] > 0.0);
+        /* 4. direction */
+        int use_mu = 1;
+        if (P.count > 0) {
+            for (int r = 0; r < R; ++r) q[r] = fr[r] ? g[r] : 0.0;
+            double gamma = 0.0;
+            int usable = 0;
+            for (int c = 0; c < P.count; ++c) { /* newest to oldest */
+                const int j = (P.head - 1 - c + 2 * PQNR_MEM) % PQNR_MEM;
+                const double sy = dot_masked(R, P.s[j], P.y[j], fr);
+                a[c] = 0.0;
+                if (sy <= 0.0) continue;
+                if (!usable) {
+                    const double yy = dot_masked(R, P.y[j], P.y[j], fr);
+                    gamma = yy > 0.0 ? sy / yy : 0.0;
+                }
+                usable = 1;
+                a[c] = dot_masked(R, P.s[j], q, fr) / sy;
+                for (int r = 0; r < R; ++r)
+                    if (fr[r]) q[r] -= a[c] * P.y[j][r];
+            }
+            if (usable && gamma > 0.0) {
+                for (int r = 0; r < R; ++r) q[r] *= gamma;
+                for (int c = P.count - 1; c >= 0; --c) { /* oldest to newest */
+                    const int j = (P.head - 1 - c + 2 * PQNR_MEM) % PQNR_MEM;
+                    const double sy = dot_masked(R, P.s[j], P.y[j], fr);
+                    if (sy <= 0.0) continue;
+                    const double beta = dot_masked(R, P.y[j], q, fr) / sy;
+                    for (int r = 0; r < R; ++r)
+                        if (fr[r]) q[r] += (a[c] - beta) * P.s[j][r];
+                }
+                double gd = 0.0;
+                for (int r = 0; r < R; ++r) {
+                    d[r] = fr[r] ? -q[r] : 0.0;
+                    gd += g[r] * d[r];
+                }
+                use_mu = !(gd < 0.0);
+            }
+        }
+        if (use_mu)
+            for (int r = 0; r < R; ++r) d[r] = -b[r] * g[r];
+        /* 5. projected backtracking line search */
+        int accepted = 0;
+        double alpha = 1.0;
+        for (int t = 0; t < PQNR_TRIALS && !accepted; ++t, alpha *= 0.5) {
+            double gdel = 0.0, lin = 0.0;
+            for (int r = 0; r < R; ++r) {
+                const double nb = b[r] + alpha * d[r];
+                delta[r] = (nb > 0.0 ? nb : 0.0) - b[r];
+                gdel += g[r] * delta[r];
+                lin += delta[r];
+            }
+            if (!(gdel < 0.0)) continue;
+            double ls = 0.0, lc = 0.0;
+            for (int64_t j = 0; j < nrow; ++j) {
+                const double* pi = pis + j * R;
+                double m = 0.0, dm = 0.0;
+                for (int r = 0; r < R; ++r) {
+                    m += b[r] * pi[r];
+                    dm += delta[r] * pi[r];
+                }
+                const double m1 = m + dm;
+                double term;
+                if (m > eps && m1 > eps)
+                    term = log1p(dm / m);
+                else
+                    term = log(m1 > eps ? m1 : eps) - log(m > eps ? m : eps);
+                neumaier_add(&ls, &lc, xs[j] * term);
+            }
+            const double df = lin - (ls + lc);
+            if (df <= PQNR_SIGMA * gdel) accepted = 1;
+        }
+        if (!accepted)
+            for (int r = 0; r < R; ++r) delta[r] = b[r] * phi[r] - b[r];
+        /* 6. step */
+        for (int r = 0; r < R; ++r) {
+            b[r] += delta[r];
+            slast[r] = delta[r];
+            gprev[r] = g[r];
+        }
+        ++steps;
+    }
+    *steps_out = steps;
+    *viol_out = viol;
+}
+
+/* PQNR inner iterations of one mode, row by row (rows are independent).
+ * B in/out (I_n x R). Outputs: the largest number of steps any row took
+ * (n_updates), the sum of steps over rows (row_steps), the largest last
+ * violation over rows (last_viol) and per-row steps (row_steps_out, may be
+ * NULL). With row_mask only those rows are solved. R <= 256. */
+int oracle_pqnr_inner_rows(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                           const double* vals, int mode, int R, double* B,
+                           const double* const* A, int lmax, double tau, double eps,
+                           const uint8_t* row_mask, int* n_updates, int64_t* row_steps,
+                           double* last_viol, int* row_steps_out)
+{
+    if (check_args(nmodes, dims, nnz, idx, vals, R) || mode < 0 || mode >= nmodes || lmax < 1 ||
+        R > 256 || !B)
+        return -1;
+    const int64_t In = dims[mode];
+    /* rows' nonzero lists by counting sort (input order inside a row) */
+    int64_t* start = (int64_t*)calloc((size_t)In + 1, sizeof(int64_t));
+    int64_t* order = (int64_t*)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int64_t));
+    if (!start || !order) { free(start); free(order); return -2; }
+    for (int64_t k = 0; k < nnz; ++k) ++start[idx[(int64_t)mode * nnz + k] + 1];
+    for (int64_t i = 0; i < In; ++i) start[i + 1] += start[i];
+    {
+        int64_t* fill = (int64_t*)malloc((size_t)In * sizeof(int64_t));
+        if (!fill) { free(start); free(order); return -2; }
+        for (int64_t i = 0; i < In; ++i) fill[i] = start[i];
+        for (int64_t k = 0; k < nnz; ++k) order[fill[idx[(int64_t)mode * nnz + k]]++] = k;
+        free(fill);
+    }
+    int64_t maxrow = 0;
+    for (int64_t i = 0; i < In; ++i)
+        if (start[i + 1] - start[i] > maxrow) maxrow = start[i + 1] - start[i];
+    double* xs = (double*)malloc((size_t)(maxrow > 0 ? maxrow : 1) * sizeof(double));
+    double* pis = (double*)malloc((size_t)(maxrow > 0 ? maxrow : 1) * R * sizeof(double));
+    if (!xs || !pis) { free(start); free(order); free(xs); free(pis); return -2; }
+    int maxsteps = 0;
+    int64_t total = 0;
+    double vmax = 0.0;
+    for (int64_t i = 0; i < In; ++i) {
+        if (row_mask && !row_mask[i]) continue;
+        const int64_t nrow = start[i + 1] - start[i];
+        for (int64_t j = 0; j < nrow; ++j) {
+            const int64_t k = order[start[i] + j];
+            xs[j] = vals[k];
+            double* pi = pis + j * R;
+            for (int r = 0; r < R; ++r) pi[r] = 1.0;
+            for (int m = 0; m < nmodes; ++m) {
+                if (m == mode) continue;
+                const double* row = A[m] + (int64_t)idx[(int64_t)m * nnz + k] * R;
+                for (int r = 0; r < R; ++r) pi[r] *= row[r];
+            }
+        }
+        int st = 0;
+        double v = 0.0;
+        pqnr_row(R, nrow, xs, pis, B + i * R, lmax, tau, eps, &st, &v);
+        if (row_steps_out) row_steps_out[i] = st;
+        if (st > maxsteps) maxsteps = st;
+        total += st;
+        if (v > vmax) vmax = v;
+    }
+    if (n_updates) *n_updates = maxsteps;
+    if (row_steps) *row_steps = total;
+    if (last_viol) *last_viol = vmax;
+    free(start); free(order); free(xs); free(pis);
+    return 0;
+}
+
+/* CP-APR with PQNR row solves: the outer loop of Algorithm 1 with the MU inner
+ * loop replaced by the row solves and no S shift (a projected method moves
+ * entries off zero itself). lam and A[m] in/out. */
+int oracle_pqnr_solve(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                      const double* vals, int R, double* lam, double* const* A, int kmax, int lmax,
+                      double tau, double eps, int* outer_iters, int64_t* row_steps, int* converged,
+                      double* kkt)
+{
+    if (check_args(nmodes, dims, nnz, idx, vals, R) || kmax < 1 || lmax < 1 || !lam || !A || R > 256)
+        return -1;
+    int64_t maxI = 0;
+    for (int m = 0; m < nmodes; ++m) if (dims[m] > maxI) maxI = dims[m];
+    double* B = (double*)malloc((size_t)maxI * R * sizeof(double));
+    if (!B) return -2;
+    int k, conv = 0, rc = 0;
+    int64_t total = 0;
+    double kkt_sweep = 0.0;
+    for (k = 1; k <= kmax; ++k) {
+        int any_update = 0;
+        kkt_sweep = 0.0;
+        for (int n = 0; n < nmodes; ++n) {
+            const int64_t In = dims[n];
+            double* An = A[n];
+            for (int64_t i = 0; i < In; ++i)
+                for (int r = 0; r < R; ++r) B[i * R + r] = An[i * R + r] * lam[r];
+            int upd = 0;
+            int64_t st = 0;
+            double v = 0.0;
+            rc = oracle_pqnr_inner_rows(nmodes, dims, nnz, idx, vals, n, R, B,
+                                        (const double* const*)A, lmax, tau, eps, NULL, &upd, &st,
+                                        &v, NULL);
+            if (rc) goto done;
+            if (upd > 0) any_update = 1;
+            total += st;
+            if (v > kkt_sweep) kkt_sweep = v;
+            for (int r = 0; r < R; ++r) {
+                double s = 0.0, c = 0.0;
+                for (int64_t i = 0; i < In; ++i) neumaier_add(&s, &c, B[i * R + r]);
+                lam[r] = s + c;
+            }
+            for (int64_t i = 0; i < In; ++i)
+                for (int r = 0; r < R; ++r)
+                    An[i * R + r] = lam[r] > 0.0 ? B[i * R + r] / lam[r] : 0.0;
+        }
+        if (tau > 0.0 && !any_update) { conv = 1; break; }
+    }
+    if (k > kmax) k = kmax;
+done:
+    if (outer_iters) *outer_iters = k;
+    if (row_steps) *row_steps = total;
+    if (converged) *converged = conv;
+    if (kkt) *kkt = kkt_sweep;
+    free(B);
+    return rc;
+}

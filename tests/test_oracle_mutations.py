@@ -38,6 +38,16 @@ MUTATIONS = [
      ["test_loglik_matches_dense"]),
     ("mttkrp-no-value", "neumaier_add(&M[i * R + r], &comp[i * R + r], vals[k] * t[r]);",
      "neumaier_add(&M[i * R + r], &comp[i * R + r], t[r]);", ["test_mttkrp_matches_dense"]),
+    ("pqnr-y-sign", "y[r] = g[r] - gprev[r];", "y[r] = gprev[r] - g[r];",
+     ["pqnr:test_pqnr_converges_faster_than_mu"]),
+    ("pqnr-armijo-sign", "if (df <= PQNR_SIGMA * gdel) accepted = 1;", "if (df >= PQNR_SIGMA * gdel) accepted = 1;",
+     ["pqnr:test_pqnr_objective_decreases_every_step", "pqnr:test_pqnr_matches_independent_lbfgsb"]),
+    ("pqnr-no-projection", "delta[r] = (nb > 0.0 ? nb : 0.0) - b[r];", "delta[r] = nb - b[r];",
+     ["pqnr:test_pqnr_kkt_at_convergence", "pqnr:test_pqnr_matches_independent_lbfgsb"]),
+    ("pqnr-decrease-drops-m", "term = log1p(dm / m);", "term = log1p(dm);",
+     ["pqnr:test_pqnr_objective_decreases_every_step", "pqnr:test_pqnr_converges_faster_than_mu"]),
+    ("pqnr-two-loop-sign", "if (fr[r]) q[r] += (a[c] - beta) * P.s[j][r];", "if (fr[r]) q[r] -= (a[c] - beta) * P.s[j][r];",
+     ["pqnr:test_pqnr_converges_faster_than_mu", "pqnr:test_pqnr_matches_independent_lbfgsb"]),
 ]
 
 PARAMS = {
@@ -47,6 +57,10 @@ PARAMS = {
 
 
 def _run_pin(name):
+    if name.startswith("pqnr:"):
+        from tests import test_oracle_pqnr as pq
+        getattr(pq, name[5:])(oracle)
+        return
     fn = getattr(pins, name)
     cases = PARAMS.get(name, [()])
     for args in cases:
