@@ -333,13 +333,13 @@ int oracle_mttkrp(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* i
  *      formed term by term (sum_r delta_r - sum_k x_k log1p(delta.pi_k / m_k),
  *      with the clamped logs where m or m + delta.pi reaches eps) instead of
  *      as a difference of two large sums. With no acceptable trial the MU step
- *      b .* phi is taken (it never increases f).
+ *      b .* phi = b + (-b .* g) is taken (it never increases f).
  *   6. b <- b + delta; the iteration counts as an update.
  * ------------------------------------------------------------------------ */
 #define PQNR_MEM 3
 #define PQNR_CURV 1e-10
 #define PQNR_SIGMA 1e-4
-#define PQNR_TRIALS 10
+#define PQNR_TRIALS 4
 
 typedef struct {
     int R, count, head; /* ring of pairs: newest at head - 1 */
@@ -473,8 +473,8 @@ static void pqnr_row(int R, int64_t nrow, const double* xs, const double* pis, d
             const double df = lin - (ls + lc);
             if (df <= PQNR_SIGMA * gdel) accepted = 1;
         }
-        if (!accepted)
-            for (int r = 0; r < R; ++r) delta[r] = b[r] * phi[r] - b[r];
+        if (!accepted) /* the MU step b .* phi, written as b + (-b .* g) */
+            for (int r = 0; r < R; ++r) delta[r] = -b[r] * g[r];
         /* 6. step */
         for (int r = 0; r < R; ++r) {
             b[r] += delta[r];
