@@ -71,6 +71,16 @@ enum { CPAPR_VARIANT_AUTO = 0, CPAPR_VARIANT_SEGMENTED = 1, CPAPR_VARIANT_ATOMIC
  * order. */
 enum { CPAPR_SORT_ROW = 0, CPAPR_SORT_ROW_COL = 1 };
 
+/* Inner solver of each mode. MU: the multiplicative update of Algorithm 1.
+ * PQNR: projected quasi-Newton solves of the row subproblems (the variant the
+ * paper names in its Background): each row b of B = A(n) Lambda minimises
+ * sum(b) - sum_k x_k log(max(b . pi_k, eps)) over b >= 0 by L-BFGS steps (3
+ * pairs) over the variables not held at zero, with a projected backtracking
+ * line search (sufficient decrease 1e-4, 4 trials, then the MU step); rows
+ * stop independently when max|min(b, 1 - phi)| < tol. No S shift is applied.
+ * PQNR runs in FP64 only (precision CPAPR_FP64) and needs R <= 256. */
+enum { CPAPR_METHOD_MU = 0, CPAPR_METHOD_PQNR = 1 };
+
 /* Sparse count tensor in coordinate format (the paper's I[n][j], X[j]). */
 typedef struct cpapr_coo {
     int32_t nmodes;      /* N */
@@ -93,6 +103,7 @@ typedef struct cpapr_params {
     int32_t group;     /* lanes per nonzero (0 = by rank; else 4, 8, 16, 32 or 64) */
     int32_t chunk;     /* nonzeros per lane group per tile (0 = launch-policy model) */
     int32_t sort;      /* CPAPR_SORT_*: order of the nonzeros inside each row of a mode */
+    int32_t method;    /* CPAPR_METHOD_*: inner solver of cpapr_solve */
 } cpapr_params;
 
 /* Result summary of cpapr_mu_inner / cpapr_solve (host). */
@@ -104,12 +115,15 @@ typedef struct cpapr_stats {
     double loglik;        /* Poisson log-likelihood of the result (solve only) */
     int64_t phi_evals;    /* Phi computations performed (an inner loop stopped by the KKT test
                              computes one Phi more than it updates) */
+    int64_t row_steps;    /* PQNR: steps taken, summed over rows and modes (MU: 0) */
+    int64_t trial_evals;  /* PQNR: line-search passes over the nonzeros (MU: 0) */
 } cpapr_stats;
 
 typedef struct cpapr_plan cpapr_plan;
 
 /* Fill *p with the defaults: kmax 10, lmax 10, tol 1e-4, eps 1e-10,
- * kappa 0.01, kappa_tol 1e-10, FP64, AUTO, group 0, chunk 0, sort ROW_COL. */
+ * kappa 0.01, kappa_tol 1e-10, FP64, AUTO, group 0, chunk 0, sort ROW_COL,
+ * method MU. */
 void cpapr_params_default(cpapr_params* p);
 
 /* Bytes of device workspace a plan for X at rank R and parameters p needs
@@ -165,6 +179,20 @@ int cpapr_phi(cpapr_plan* plan, int32_t mode, const double* B, const double* con
  * The loop's stop decision stays on the device; waits for the stream once. */
 int cpapr_mu_inner(cpapr_plan* plan, int32_t mode, double* B, const double* const* A,
                    double* Phi_last, cpapr_stats* out, void* stream);
+
+/* PQNR row solves of one mode (see CPAPR_METHOD_PQNR): up to params.lmax
+ * iterations for every row of B (device, I_mode x R, in/out, the row
+ * subproblems' starting point, e.g. A(mode) Lambda) with the other factors A
+ * (device, columns summing to one). Every iteration is one Phi pass for the
+ * gradients and up to 4 line-search passes over the nonzeros, all ordered on
+ * `stream` with stops decided on the device. out (host, may be NULL):
+ * inner_iters = most steps taken by a row, row_steps = steps summed over rows,
+ * kkt_violation = largest last violation over rows, converged = every row met
+ * tol, phi_evals / trial_evals = passes run. The plan must have been created
+ * with method CPAPR_METHOD_PQNR (its workspace holds the row state);
+ * otherwise CPAPR_EINVAL. */
+int cpapr_pqnr_inner(cpapr_plan* plan, int32_t mode, double* B, const double* const* A, cpapr_stats* out,
+                     void* stream);
 
 /* Full CP-APR MU (Algorithm 1) with the plan's parameters.
  *   lambda device [R], in/out.  A host array of N device pointers, in/out.

@@ -26,6 +26,8 @@ CPAPR_VARIANT_SEGMENTED = 1
 CPAPR_VARIANT_ATOMIC = 2
 CPAPR_SORT_ROW = 0
 CPAPR_SORT_ROW_COL = 1
+CPAPR_METHOD_MU = 0
+CPAPR_METHOD_PQNR = 1
 MAX_MODES = 8
 
 
@@ -43,12 +45,14 @@ class cpapr_coo(C.Structure):
 class cpapr_params(C.Structure):
     _fields_ = [("kmax", C.c_int32), ("lmax", C.c_int32), ("tol", C.c_double), ("eps", C.c_double),
                 ("kappa", C.c_double), ("kappa_tol", C.c_double), ("precision", C.c_int32),
-                ("variant", C.c_int32), ("group", C.c_int32), ("chunk", C.c_int32), ("sort", C.c_int32)]
+                ("variant", C.c_int32), ("group", C.c_int32), ("chunk", C.c_int32), ("sort", C.c_int32),
+                ("method", C.c_int32)]
 
 
 class cpapr_stats(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("converged", C.c_int32), ("inner_iters", C.c_int64),
-                ("kkt_violation", C.c_double), ("loglik", C.c_double), ("phi_evals", C.c_int64)]
+                ("kkt_violation", C.c_double), ("loglik", C.c_double), ("phi_evals", C.c_int64),
+                ("row_steps", C.c_int64), ("trial_evals", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -77,6 +81,7 @@ def load():
         "cpapr_plan_shape": (C.c_int, [vp, P(i32), P(i32)]),
         "cpapr_phi": (C.c_int, [vp, i32, vp, P(vp), dbl, vp, vp]),
         "cpapr_mu_inner": (C.c_int, [vp, i32, vp, P(vp), vp, P(cpapr_stats), vp]),
+        "cpapr_pqnr_inner": (C.c_int, [vp, i32, vp, P(vp), P(cpapr_stats), vp]),
         "cpapr_solve": (C.c_int, [vp, vp, P(vp), P(cpapr_stats), vp]),
         "cpapr_loglik": (C.c_int, [vp, vp, P(vp), dbl, P(dbl), vp]),
         "cpapr_mttkrp": (C.c_int, [vp, i32, P(vp), vp, vp]),
@@ -109,7 +114,7 @@ def load():
 
 
 EXPORTED = ("cpapr_params_default", "cpapr_plan_workspace_size", "cpapr_plan_create", "cpapr_plan_destroy",
-            "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_plan_shape", "cpapr_phi", "cpapr_mu_inner", "cpapr_solve", "cpapr_loglik",
+            "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_plan_shape", "cpapr_phi", "cpapr_mu_inner", "cpapr_pqnr_inner", "cpapr_solve", "cpapr_loglik",
             "cpapr_mttkrp", "cpapr_batch_workspace_size", "cpapr_batch_tiles", "cpapr_batch_create", "cpapr_batch_create2",
             "cpapr_batch_destroy", "cpapr_batch_set", "cpapr_batch_clear", "cpapr_batch_commit", "cpapr_batch_run",
             "cpapr_batch_mu", "cpapr_batch_inner", "cpapr_batch_status", "cpapr_mode_begin", "cpapr_mode_end", "cpapr_plan_sync_f32",
@@ -204,6 +209,12 @@ def cpapr_mu_inner(h, mode, B, A, Phi_last, stream=None) -> dict:
     st = cpapr_stats()
     _check(load().cpapr_mu_inner(h, mode, B.data_ptr(), _ptr_array(A), Phi_last.data_ptr(), C.byref(st),
                                  _stream(stream)))
+    return st.as_dict()
+
+
+def cpapr_pqnr_inner(h, mode, B, A, stream=None) -> dict:
+    st = cpapr_stats()
+    _check(load().cpapr_pqnr_inner(h, mode, B.data_ptr(), _ptr_array(A), C.byref(st), _stream(stream)))
     return st.as_dict()
 
 
@@ -411,6 +422,10 @@ class Plan:
             phi_last = torch.empty((self.dims[mode], self.R), dtype=torch.float64, device=B.device)
         st = cpapr_mu_inner(self.handle, mode, B, A, phi_last, stream)
         return phi_last, st
+
+    def pqnr_inner(self, mode, B, A, stream=None):
+        """PQNR row solves of one mode (plan created with method=CPAPR_METHOD_PQNR); B in/out."""
+        return cpapr_pqnr_inner(self.handle, mode, B, A, stream)
 
     def solve(self, lam, A, stream=None):
         return cpapr_solve(self.handle, lam, A, stream)

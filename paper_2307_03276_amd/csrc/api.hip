@@ -73,6 +73,9 @@ Error check_params(const cpapr_params* p, int32_t R, int nmodes)
         return {CPAPR_EUNSUPPORTED, "no Phi kernel for this lane group and rank block at this mode count"};
     if (p->chunk < 0 || p->chunk > 65536) return {CPAPR_EINVAL, "chunk must be in [0, 65536]"};
     if (p->sort != CPAPR_SORT_ROW && p->sort != CPAPR_SORT_ROW_COL) return {CPAPR_EINVAL, "unknown sort"};
+    if (p->method != CPAPR_METHOD_MU && p->method != CPAPR_METHOD_PQNR) return {CPAPR_EINVAL, "unknown method"};
+    if (p->method == CPAPR_METHOD_PQNR && p->precision != CPAPR_FP64)
+        return {CPAPR_EUNSUPPORTED, "PQNR runs in FP64 only"};
     return {CPAPR_OK, ""};
 }
 
@@ -84,11 +87,11 @@ struct Layout {
     size_t mode_rows[CPAPR_MAX_MODES], mode_cidx[CPAPR_MAX_MODES], mode_vals[CPAPR_MAX_MODES];
     size_t f32[CPAPR_MAX_MODES];
     size_t region2;
-    size_t B, phi_prev[CPAPR_MAX_MODES], partial, llpart, colsums, state;
+    size_t B, phi_prev[CPAPR_MAX_MODES], partial, llpart, colsums, state, pqnr;
     size_t total;
 };
 
-Layout layout(int N, int64_t nnz, const int64_t* dims, int R, bool mixed)
+Layout layout(int N, int64_t nnz, const int64_t* dims, int R, bool mixed, bool pqnr)
 {
     Layout L{};
     size_t off = 0;
@@ -122,6 +125,8 @@ Layout layout(int N, int64_t nnz, const int64_t* dims, int R, bool mixed)
     s += align256((size_t)N * R * 8);
     L.state = off + s;
     s += align256(sizeof(cpapr::DevState));
+    L.pqnr = off + s;
+    if (pqnr) s += cpapr::pqnr_bytes(maxI, R);
     s = std::max(s, (size_t)cpapr::sort_scratch_bytes(nnz, N));
     L.total = off + s;
     return L;
@@ -188,7 +193,7 @@ Error enqueue_inner(cpapr_plan* P, int mode, double* B, const void* const* fac, 
 struct HostState {
     double last_viol[CPAPR_MAX_MODES];
     int done, updates, sweep_updates;
-    long long total_updates, phi_evals;
+    long long total_updates, phi_evals, row_steps, trial_evals;
     double ll;
 };
 
@@ -199,6 +204,8 @@ Error read_state(const cpapr_plan* P, HostState* h, hipStream_t s)
     CPAPR_HIP(hipMemcpyAsync(&h->done, &d->done, sizeof(int) * 3, hipMemcpyDeviceToHost, s));
     CPAPR_HIP(hipMemcpyAsync(&h->total_updates, &d->total_updates, sizeof(long long), hipMemcpyDeviceToHost, s));
     CPAPR_HIP(hipMemcpyAsync(&h->phi_evals, &d->phi_evals, sizeof(long long), hipMemcpyDeviceToHost, s));
+    CPAPR_HIP(hipMemcpyAsync(&h->row_steps, &d->row_steps, sizeof(long long), hipMemcpyDeviceToHost, s));
+    CPAPR_HIP(hipMemcpyAsync(&h->trial_evals, &d->trial_evals, sizeof(long long), hipMemcpyDeviceToHost, s));
     CPAPR_HIP(hipMemcpyAsync(&h->ll, &d->ll, sizeof(double), hipMemcpyDeviceToHost, s));
     CPAPR_HIP(hipStreamSynchronize(s));
     return {CPAPR_OK, ""};
@@ -244,6 +251,7 @@ void cpapr_params_default(cpapr_params* p)
     p->group = 0;
     p->chunk = 0;
     p->sort = CPAPR_SORT_ROW_COL;
+    p->method = CPAPR_METHOD_MU;
 }
 
 const char* cpapr_last_error(void) { return g_error.c_str(); }
@@ -256,7 +264,8 @@ int cpapr_plan_workspace_size(const cpapr_coo* X, int32_t R, const cpapr_params*
         e = check_params(p, R, X->nmodes);
         if (e.code) return report(e);
         if (!bytes) return fail(CPAPR_EINVAL, "bytes is NULL");
-        *bytes = layout(X->nmodes, X->nnz, X->dims, R, p->precision == CPAPR_MIXED).total;
+        *bytes = layout(X->nmodes, X->nnz, X->dims, R, p->precision == CPAPR_MIXED,
+                        p->method == CPAPR_METHOD_PQNR).total;
         return CPAPR_OK;
     } catch (...) {
         return fail(CPAPR_EINVAL, "unexpected exception");
@@ -274,7 +283,7 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
         e = check_params(p, R, X->nmodes);
         if (e.code) return report(e);
         const bool mixed = p->precision == CPAPR_MIXED;
-        const Layout L = layout(X->nmodes, X->nnz, X->dims, R, mixed);
+        const Layout L = layout(X->nmodes, X->nnz, X->dims, R, mixed, p->method == CPAPR_METHOD_PQNR);
         if (!ws) return fail(CPAPR_EWORKSPACE, "workspace is NULL");
         if (((uintptr_t)ws & 255) != 0) return fail(CPAPR_EWORKSPACE, "workspace must be 256-byte aligned");
         if (ws_bytes < L.total) return fail(CPAPR_EWORKSPACE, "workspace too small");
@@ -303,6 +312,11 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
         P->llpart = (double*)(w + L.llpart);
         P->colsums = (double*)(w + L.colsums);
         P->state = (cpapr::DevState*)(w + L.state);
+        if (p->method == CPAPR_METHOD_PQNR) {
+            int64_t maxI = 0;
+            for (int m = 0; m < P->N; ++m) maxI = std::max(maxI, P->dims[m]);
+            cpapr::pqnr_bind(&P->pq, w + L.pqnr, maxI, R);
+        }
 
         hipStream_t s = (hipStream_t)stream;
         e = cpapr::build_sorted(P, X, w + L.region2, s);
@@ -411,6 +425,45 @@ int cpapr_mu_inner(cpapr_plan* plan, int32_t mode, double* B, const double* cons
             out->kkt_violation = h.last_viol[mode];
             out->loglik = NAN;
             out->phi_evals = h.phi_evals;
+            out->row_steps = 0;
+            out->trial_evals = 0;
+        }
+        return CPAPR_OK;
+    } catch (...) {
+        return fail(CPAPR_EINVAL, "unexpected exception");
+    }
+}
+
+int cpapr_pqnr_inner(cpapr_plan* plan, int32_t mode, double* B, const double* const* A, cpapr_stats* out,
+                     void* stream)
+{
+    try {
+        Error e = check_plan_call(plan, mode);
+        if (e.code) return report(e);
+        if (plan->params.method != CPAPR_METHOD_PQNR) return fail(CPAPR_EINVAL, "the plan was not created for PQNR");
+        e = check_factors(plan, A, mode);
+        if (e.code) return report(e);
+        if (!B) return fail(CPAPR_EINVAL, "B is NULL");
+        hipStream_t s = (hipStream_t)stream;
+        const void* fac[CPAPR_MAX_MODES];
+        e = phi_factors(plan, mode, A, fac, s);
+        if (e.code) return report(e);
+        e = cpapr::launch_reset_state(plan->state, true, true, s);
+        if (e.code) return report(e);
+        e = cpapr::enqueue_pqnr_inner(plan, mode, B, fac, plan->phi_prev[mode], s);
+        if (e.code) return report(e);
+        HostState h{};
+        e = read_state(plan, &h, s);
+        if (e.code) return report(e);
+        if (out) {
+            out->outer_iters = 0;
+            out->converged = h.done;
+            out->inner_iters = h.updates;
+            out->kkt_violation = h.last_viol[mode];
+            out->loglik = NAN;
+            out->phi_evals = h.phi_evals;
+            out->row_steps = h.row_steps;
+            out->trial_evals = h.trial_evals;
         }
         return CPAPR_OK;
     } catch (...) {
@@ -448,10 +501,12 @@ int cpapr_solve(cpapr_plan* plan, double* lambda, double* const* A, cpapr_stats*
                 const int64_t In = P->dims[n];
                 e = cpapr::launch_reset_state(P->state, n == 0, false, s);
                 if (e.code) return report(e);
+                const bool pqnr = P->params.method == CPAPR_METHOD_PQNR;
                 e = cpapr::launch_shift_scale(A[n], P->phi_prev[n], lambda, P->B, In, R, P->params.kappa,
-                                              P->params.kappa_tol, k > 1, s);
+                                              P->params.kappa_tol, k > 1 && !pqnr, s);
                 if (e.code) return report(e);
-                e = enqueue_inner(P, n, P->B, fac, P->phi_prev[n], s);
+                e = pqnr ? cpapr::enqueue_pqnr_inner(P, n, P->B, fac, P->phi_prev[n], s)
+                         : enqueue_inner(P, n, P->B, fac, P->phi_prev[n], s);
                 if (e.code) return report(e);
                 e = cpapr::launch_colsum(P->B, In, R, P->partial, lambda, s);
                 if (e.code) return report(e);
@@ -485,6 +540,8 @@ int cpapr_solve(cpapr_plan* plan, double* lambda, double* const* A, cpapr_stats*
             out->kkt_violation = kkt;
             out->loglik = h.ll;
             out->phi_evals = h.phi_evals;
+            out->row_steps = h.row_steps;
+            out->trial_evals = h.trial_evals;
         }
         return CPAPR_OK;
     } catch (...) {

@@ -35,6 +35,35 @@ struct DevState {
     long long total_updates;                                // MU updates since the last reset
     long long phi_evals;                                    // Phi computations since the last reset
     double ll;                                              // log-likelihood result
+    long long row_steps;                                    // PQNR: steps summed over rows since the last reset
+    long long trial_evals;                                  // PQNR: line-search passes since the last reset
+    int pq_all_done;                                        // PQNR: no row of the current mode is active
+    int pq_idle;                                            // PQNR: no row is in a line search
+};
+
+// PQNR (projected quasi-Newton row solves): constants shared by every kernel.
+constexpr int kPqnrMem = 3;          // curvature pairs kept per row
+constexpr int kPqnrTrials = 4;       // backtracking trials before the MU step
+constexpr double kPqnrSigma = 1e-4;  // sufficient-decrease constant
+constexpr double kPqnrCurv = 1e-10;  // pair kept when s.y > kPqnrCurv |s| |y|
+
+// PQNR state of the mode being solved (rows x R matrices, per-row scalars).
+struct PqnrState {
+    double* G;      // gradient 1 - Phi at the current b
+    double* Gp;     // gradient before the last step
+    double* Dd;     // search direction
+    double* Dt;     // trial step (after a step: the step taken)
+    double* S;      // kPqnrMem x (rows x R) steps of the kept pairs
+    double* Y;      // kPqnrMem x (rows x R) gradient changes of the kept pairs
+    double* alpha;  // per row: current trial length
+    double* gdel;   // per row: g . trial step
+    double* viol;   // per row: last KKT violation
+    int32_t* status;  // per row: 0 active, 1 in a line search, 3 converged
+    int32_t* trials;  // per row: rejected trials in this line search
+    int32_t* steps;   // per row: steps taken
+    int32_t* npairs;  // per row: kept pairs
+    int32_t* head;    // per row: ring position of the next pair
+    int64_t stride;   // rows of every matrix (largest mode)
 };
 
 struct PlanMode {
@@ -55,6 +84,7 @@ struct PhiArgs {
     const double* B;
     double* Phi;
     const int* done;
+    const double* D;  // trial step matrix (line-search pass only)
     int64_t nnz;
     int R;
     int NM1;
@@ -120,6 +150,7 @@ struct cpapr_plan {
     char* ws;
     size_t ws_bytes;
     int group, chunk;                 // resolved launch shape of the Phi kernel
+    cpapr::PqnrState pq;              // PQNR row-solve state (method CPAPR_METHOD_PQNR only)
 };
 
 namespace cpapr {
@@ -170,6 +201,18 @@ Error launch_batch_reset(BatchState st, int max_slots, hipStream_t s);
 
 // ---- elementwise and reduction kernels (mu.hip) ----
 Error launch_fill(double* p, int64_t n, double v, const int* done, hipStream_t s);
+// Per-row sums of x_k log(max(m_k + dm_k, eps) / max(m_k, eps)) with m = B pi, dm = D pi
+// into column 0 of `out` (the other columns get 0); skipped when *skip != 0.
+Error launch_delta(const cpapr_plan* P, int mode, const double* B, const double* D, const void* const* fac,
+                   double eps, double* out, const int* skip, hipStream_t s);
+
+// ---- PQNR row solves (pqnr.hip) ----
+size_t pqnr_bytes(int64_t maxI, int R);
+void pqnr_bind(PqnrState* q, char* base, int64_t maxI, int R);
+// One PQNR inner loop (lmax iterations) for the rows of `mode`; B in/out. Uses
+// `phi` (I_mode x R) as the Phi / line-search buffer. Leaves per-mode stats in
+// the device state (updates = most steps of a row, row_steps, last_viol[mode]).
+Error enqueue_pqnr_inner(cpapr_plan* P, int mode, double* B, const void* const* fac, double* phi, hipStream_t s);
 Error launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 Error launch_reset_state(DevState* st, bool new_sweep, bool all, hipStream_t s);
 Error launch_kkt(const double* B, const double* Phi, int64_t n, DevState* st, int l, hipStream_t s);

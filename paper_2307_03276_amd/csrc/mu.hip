@@ -52,6 +52,8 @@ __global__ __launch_bounds__(kBlock) void reset_state_kernel(DevState* st, int n
         if (all) {
             st->total_updates = 0;
             st->phi_evals = 0;
+            st->row_steps = 0;
+            st->trial_evals = 0;
             for (int m = 0; m < CPAPR_MAX_MODES; ++m) st->last_viol[m] = 0.0;
         }
     }

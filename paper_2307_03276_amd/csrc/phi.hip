@@ -178,6 +178,28 @@ __device__ __forceinline__ float div_pos(float x, float m)
 constexpr int kPhi = 0;     // s_k = x_k / max(m_k, eps); Phi[i_n] += s_k pi_k
 constexpr int kMttkrp = 1;  // s_k = x_k;                  M[i_n]  += s_k pi_k
 constexpr int kLoglik = 2;  // x_k log(max(m_k, eps)) summed per tile (no scatter)
+constexpr int kDelta = 3;   // x_k log(max(m_k + dm_k, eps) / max(m_k, eps)) summed per row (column 0)
+
+// The change of the likelihood term of one nonzero along a trial step d of its
+// row, m = b . pi and dm = d . pi: log1p(dm / m) when neither end is clamped
+// (accurate for small steps, unlike a difference of two logarithms), else the
+// difference of the clamped logarithms.
+template <int G, int RPL>
+__device__ __forceinline__ double delta_term(const double (&b)[RPL], const double (&d)[RPL],
+                                             const double (&pi)[RPL], double x, double eps)
+{
+    double m = 0.0, dm = 0.0;
+#pragma unroll
+    for (int c = 0; c < RPL; ++c) {
+        m = __builtin_fma(b[c], pi[c], m);
+        dm = __builtin_fma(d[c], pi[c], dm);
+    }
+    m = group_sum<G>(m);
+    dm = group_sum<G>(dm);
+    const double m1 = m + dm;
+    const double t = (m > eps && m1 > eps) ? log1p(div_pos(dm, m)) : log(m1 > eps ? m1 : eps) - log(m > eps ? m : eps);
+    return x * t;
+}
 
 // One nonzero's dot product and scale: s_k for Phi, x_k for MTTKRP, the
 // likelihood term for Loglik.
@@ -279,10 +301,12 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
     double ll = 0.0;  // likelihood terms of this lane group (Loglik)
     Acc<MIXED> acc[RPL];
     T b[RPL];
+    double dv[RPL];  // the row's trial step (line-search pass)
 #pragma unroll
     for (int c = 0; c < RPL; ++c) {
         acc[c].zero();
         b[c] = (T)0;
+        dv[c] = 0.0;
     }
 
     // Flush kinds: 0 = head partial (LDS), 1 = tail partial (LDS), 2 = owned row (store).
@@ -374,13 +398,24 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
 #pragma unroll
                             for (int c = 0; c < RPL; ++c) b[c] = own[c] ? (T)brow[c] : (T)0;
                         }
-                    }
-                    const T s = nonzero_scale<G, RPL, MIXED, KIND, T>(b, pi, xu[u], a.eps);
-                    if constexpr (KIND == kLoglik) {
-                        ll += s;
-                    } else {
+                        if constexpr (KIND == kDelta) {
+                            const double* drow = a.D + (int64_t)row * R + colbase;
 #pragma unroll
-                        for (int c = 0; c < RPL; ++c) acc[c].add(s, pi[c]);
+                            for (int c = 0; c < RPL; ++c) dv[c] = own[c] ? drow[c] : 0.0;
+                        }
+                    }
+                    if constexpr (KIND == kDelta) {
+                        static_assert(!MIXED, "the line-search pass is FP64");
+                        const double t = delta_term<G, RPL>(b, dv, pi, xu[u], a.eps);
+                        if (lane == 0) acc[0].v += t;
+                    } else {
+                        const T s = nonzero_scale<G, RPL, MIXED, KIND, T>(b, pi, xu[u], a.eps);
+                        if constexpr (KIND == kLoglik) {
+                            ll += s;
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < RPL; ++c) acc[c].add(s, pi[c]);
+                        }
                     }
                 }
             }
@@ -781,6 +816,16 @@ Error launch_phi(const cpapr_plan* P, int mode, const double* B, const void* con
     Error e = mixed ? dispatch_seg<true, kPhi>(G, RPL, a, s) : dispatch_seg<false, kPhi>(G, RPL, a, s);
     prof_end(s);
     return e;
+}
+
+Error launch_delta(const cpapr_plan* P, int mode, const double* B, const double* D, const void* const* fac,
+                   double eps, double* out, const int* skip, hipStream_t s)
+{
+    const int G = P->group;
+    const int RPL = rank_block(P->R, G);
+    PhiArgs a = make_args(P, mode, B, fac, eps, out, skip);
+    a.D = D;
+    return dispatch_seg<false, kDelta>(G, RPL, a, s);
 }
 
 Error launch_mttkrp(const cpapr_plan* P, int mode, const double* const* A, double* M, hipStream_t s)

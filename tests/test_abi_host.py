@@ -38,7 +38,7 @@ def test_params_default(lib):
     p = cpapr.cpapr_params_default()
     assert (p.kmax, p.lmax, p.tol, p.eps, p.kappa, p.kappa_tol) == (10, 10, 1e-4, 1e-10, 0.01, 1e-10)
     assert p.precision == cpapr.CPAPR_FP64 and p.variant == 0 and p.group == 0 and p.chunk == 0
-    assert p.sort == cpapr.CPAPR_SORT_ROW_COL
+    assert p.sort == cpapr.CPAPR_SORT_ROW_COL and p.method == cpapr.CPAPR_METHOD_MU
 
 
 def _coo(dims, nnz):
@@ -83,6 +83,7 @@ def test_workspace_size_grows_with_problem(lib):
     ([4, 5, 6], 10, 40, "group", 8, -6),                  # R > 4 * group
     ([4, 5, 6], 10, 4, "variant", 9, -1),
     ([4, 5, 6], 10, 4, "sort", 5, -1),
+    ([4, 5, 6], 10, 4, "method", 7, -1),
     ([4, 5, 6, 7, 8], 10, 32, "group", 16, 0),           # N = 5: 16 lanes x 2 ranks is built
     ([4, 5, 6, 7, 8], 10, 64, "group", 16, -6),          # N = 5: 16 lanes x 4 ranks is not
 ])
@@ -94,6 +95,19 @@ def test_workspace_size_rejects(lib, dims, nnz, R, field, val, code):
     assert rc == code
     if code:
         assert cpapr.cpapr_last_error()
+
+
+def test_pqnr_params(lib):
+    """PQNR needs FP64; its plans carry the row-solve state in the workspace."""
+    coo = _coo([100, 80, 60], 10_000)
+    mu = cpapr.cpapr_params_default()
+    pq = cpapr.cpapr_params_default(method=cpapr.CPAPR_METHOD_PQNR)
+    rc, a = _size(coo, 16, mu)
+    rc2, b = _size(coo, 16, pq)
+    assert rc == 0 and rc2 == 0 and b >= a
+    pm = cpapr.cpapr_params_default(method=cpapr.CPAPR_METHOD_PQNR, precision=cpapr.CPAPR_MIXED)
+    rc, _ = _size(coo, 16, pm)
+    assert rc == -6
 
 
 def test_plan_create_host_checks(lib):
@@ -113,6 +127,7 @@ def test_calls_reject_null_plan(lib):
     arr = (C.c_void_p * 3)()
     assert lib.cpapr_phi(None, 0, None, arr, 1e-10, None, None) == -1
     assert lib.cpapr_mu_inner(None, 0, None, arr, None, None, None) == -1
+    assert lib.cpapr_pqnr_inner(None, 0, None, arr, None, None) == -1
     assert lib.cpapr_solve(None, None, arr, None, None) == -1
     assert lib.cpapr_loglik(None, None, arr, 1e-10, None, None) == -1
     assert lib.cpapr_mttkrp(None, 0, arr, None, None) == -1

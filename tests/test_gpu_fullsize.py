@@ -68,3 +68,24 @@ def test_mu_inner_fullsize_sampled_rows(big):
     assert_parity(host(B)[rows], Bo[rows], 1e-12, "B rows")
     assert_parity(host(phi_last)[rows], Po[rows], 1e-12, "Phi rows")
     P.close()
+
+
+def test_pqnr_inner_fullsize_sampled_rows(big):
+    """PQNR row solves of mode 0 at full size; rows are independent, so the
+    oracle solves the sampled rows alone (heavy rows of 2.6M nonzeros among
+    them) with the same tolerance and iteration limit."""
+    X, M, sched = big
+    P = cpapr.Plan.from_tensor(X, M.rank, method=cpapr.CPAPR_METHOD_PQNR, lmax=8, tol=1e-6)
+    A = [dev(a) for a in M.factors]
+    rng = np.random.default_rng(2)
+    n = 0
+    Bh = M.factors[n] * M.lam
+    B = dev(Bh)
+    st = P.pqnr_inner(n, B, A)
+    rows, _ = _sample_rows(X, n, rng, k_random=10)
+    Bo, ost = oracle.pqnr_inner(X, n, Bh, M.factors, lmax=8, tau=1e-6, rows=rows)
+    got = host(B)
+    for i in rows:
+        assert_parity(got[i:i + 1], Bo[i:i + 1], 1e-10, f"PQNR row {i}", elementwise=False)
+    assert st["inner_iters"] >= ost["n_updates"]
+    P.close()

@@ -1,0 +1,133 @@
+"""PQNR row solves on the GPU against the oracle's PQNR (same row rules).
+
+Rows are independent and every decision (KKT stop, pair kept, bound set,
+descent test, sufficient decrease) is taken from quantities both sides form
+to within rounding, so the iterations run in lockstep: step counts per mode
+match exactly and the iterates agree to the parity tolerance on short
+schedules. Over long schedules tiny differences pass through the quasi-Newton
+recursion, so converged runs are compared at the tolerance the convergence
+test leaves (both sides end within tol of KKT at the same unique row optimum)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_03276_amd import cpapr, synth
+from tests.gpu_util import assert_parity, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+    assert torch.cuda.is_available()
+    oracle.build(force=False)
+    cpapr.load()
+
+
+def _plan(X, R, **kw):
+    return cpapr.Plan.from_tensor(X, R, method=cpapr.CPAPR_METHOD_PQNR, **kw)
+
+
+@pytest.mark.parametrize("lmax", [1, 3, 6])
+def test_pqnr_short_schedule_lockstep(lmax):
+    X, M, _ = synth.config_small()
+    P = _plan(X, 10, lmax=lmax, tol=0.0)  # fixed schedule: every row steps lmax times
+    A = [dev(a) for a in M.factors]
+    for n in range(3):
+        Bh = M.factors[n] * M.lam
+        B = dev(Bh)
+        st = P.pqnr_inner(n, B, A)
+        Bo, ost = oracle.pqnr_inner(X, n, Bh, M.factors, lmax=lmax, tau=0.0)
+        assert st["inner_iters"] == ost["n_updates"] == lmax
+        assert st["row_steps"] == ost["row_steps"]
+        # normwise: a projected step can leave an entry at a tiny value formed by
+        # cancellation (b + (max(b + alpha d, 0) - b)), whose relative error says nothing
+        got = host(B)
+        assert_parity(got, Bo, 1e-12, f"B after {lmax} PQNR steps, mode {n}", elementwise=False)
+        assert np.max(np.abs(got - Bo)) <= 1e-12 * np.max(np.abs(Bo))
+    P.close()
+
+
+@pytest.mark.parametrize("dims,R,nnz", [((100, 80, 60), 10, 10_000), ((40, 30, 20, 10), 4, 3000),
+                                        ((60, 50, 40), 32, 8000), ((30, 25, 20), 70, 4000)])
+def test_pqnr_converged_rows_match_oracle(dims, R, nnz):
+    X = synth.random_tensor(11, dims, nnz, zipf=(1.1,) + (None,) * (len(dims) - 1))
+    M = synth.random_model(11, dims, R)
+    tau = 1e-9
+    P = _plan(X, R, lmax=200, tol=tau)
+    A = [dev(a) for a in M.factors]
+    for n in range(len(dims)):
+        Bh = M.factors[n] * M.lam
+        B = dev(Bh)
+        st = P.pqnr_inner(n, B, A)
+        Bo, ost = oracle.pqnr_inner(X, n, Bh, M.factors, lmax=200, tau=tau)
+        assert st["kkt_violation"] < tau and ost["last_viol"] < tau
+        assert abs(st["row_steps"] - ost["row_steps"]) <= max(2, ost["row_steps"] // 200)
+        # both within tau of KKT at the same row optimum
+        assert_parity(host(B), Bo, 1e-6, f"converged B mode {n}", elementwise=False)
+    P.close()
+
+
+def test_pqnr_rank_one_and_empty_rows():
+    """R = 1: one step reaches the row totals exactly (the MU step is the row
+    optimum); rows without nonzeros go to zero and stop."""
+    X = synth.random_tensor(5, (50, 40, 30), 300)
+    M = synth.random_model(5, X.dims, 1)
+    P = _plan(X, 1, lmax=5, tol=1e-12)
+    A = [dev(a) for a in M.factors]
+    for n in range(3):
+        B = dev(M.factors[n] * M.lam)
+        st = P.pqnr_inner(n, B, A)
+        marg = np.bincount(X.idx[n], weights=X.vals, minlength=X.dims[n])
+        np.testing.assert_allclose(host(B)[:, 0], marg, rtol=1e-13, atol=0)
+        assert st["inner_iters"] == 1 and st["converged"] == 1
+    P.close()
+
+
+def test_pqnr_solve_matches_oracle():
+    X, M, _ = synth.config_small()
+    P = _plan(X, 10, kmax=3, lmax=8, tol=0.0)
+    lam = dev(M.lam)
+    A = [dev(a) for a in M.factors]
+    st = P.solve(lam, A)
+    out, ost = oracle.pqnr_solve(X, M, kmax=3, lmax=8, tau=0.0)
+    assert st["outer_iters"] == ost["outer_iters"] == 3
+    assert st["row_steps"] == ost["row_steps"]
+    assert_parity(host(lam), out.lam, 1e-10, "lambda")
+    for n in range(3):
+        assert_parity(host(A[n]), out.factors[n], 1e-10, f"A{n}", elementwise=False)
+    assert st["phi_evals"] == 3 * 3 * 8
+    P.close()
+
+
+def test_pqnr_solve_reaches_lower_kkt_than_mu():
+    """Same outer sweeps and inner limit: the PQNR solve ends far closer to a
+    KKT point than MU and at a higher likelihood (the oracle shows the same:
+    KKT 3.4e-4 vs 0.17 after 20 sweeps on this configuration)."""
+    X, M, _ = synth.config_small()
+    kw = dict(kmax=20, lmax=10, tol=1e-4)
+    Pq = _plan(X, 10, **kw)
+    lam_q, A_q = dev(M.lam), [dev(a) for a in M.factors]
+    sq = Pq.solve(lam_q, A_q)
+    Pm = cpapr.Plan.from_tensor(X, 10, **kw)
+    lam_m, A_m = dev(M.lam), [dev(a) for a in M.factors]
+    sm = Pm.solve(lam_m, A_m)
+    assert sq["kkt_violation"] < 0.1 * sm["kkt_violation"], (sq["kkt_violation"], sm["kkt_violation"])
+    assert sq["loglik"] >= sm["loglik"]
+    out, ost = oracle.pqnr_solve(X, M, **{"kmax": 20, "lmax": 10, "tau": 1e-4})
+    assert abs(sq["loglik"] - oracle.loglik(X, out)) <= 1e-6 * abs(sq["loglik"])
+    Pq.close()
+    Pm.close()
+
+
+def test_pqnr_rejects_mu_plan_and_mixed():
+    X, M, _ = synth.config_small()
+    P = cpapr.Plan.from_tensor(X, 10)
+    with pytest.raises(cpapr.CpaprError) as ei:
+        P.pqnr_inner(0, dev(M.factors[0] * M.lam), [dev(a) for a in M.factors])
+    assert ei.value.code == -1
+    P.close()
+    with pytest.raises(cpapr.CpaprError) as ei:
+        _plan(X, 10, precision=cpapr.CPAPR_MIXED)
+    assert ei.value.code == -6
