@@ -76,9 +76,11 @@ enum { CPAPR_SORT_ROW = 0, CPAPR_SORT_ROW_COL = 1 };
  * paper names in its Background): each row b of B = A(n) Lambda minimises
  * sum(b) - sum_k x_k log(max(b . pi_k, eps)) over b >= 0 by L-BFGS steps (3
  * pairs) over the variables not held at zero, with a projected backtracking
- * line search (sufficient decrease 1e-4, 4 trials, then the MU step); rows
- * stop independently when max|min(b, 1 - phi)| < tol. No S shift is applied.
- * PQNR runs in FP64 only (precision CPAPR_FP64) and needs R <= 256. */
+ * line search (sufficient decrease 1e-4, trials that bring a model value to
+ * the floor eps rejected, 4 trials, then the MU step); rows stop independently
+ * when max|min(b, 1 - phi)| < tol. The outer loop, S shift included, is
+ * Algorithm 1's. PQNR runs in FP64 only (precision CPAPR_FP64) and needs
+ * R <= 256. */
 enum { CPAPR_METHOD_MU = 0, CPAPR_METHOD_PQNR = 1 };
 
 /* Sparse count tensor in coordinate format (the paper's I[n][j], X[j]). */

@@ -189,17 +189,21 @@ def pqnr_inner(X, mode, B, factors, lmax, tau=0.0, eps=1e-10, rows=None):
     total = C.c_int64(0)
     last = C.c_double(0)
     steps = np.zeros(In, dtype=np.int32)
+    phi_last = np.full((In, R), np.nan) if rows is not None else np.zeros((In, R))
     rc = lib.oracle_pqnr_inner_rows(*keep[3], C.c_int(mode), C.c_int(R), _ptr(Bw), ptrs, C.c_int(lmax),
                                     C.c_double(tau), C.c_double(eps),
                                     _ptr(mask, C.c_uint8) if mask is not None else None,
-                                    C.byref(nup), C.byref(total), C.byref(last), _ptr(steps, C.c_int32))
+                                    C.byref(nup), C.byref(total), C.byref(last), _ptr(steps, C.c_int32),
+                                    _ptr(phi_last))
     _check(rc, "pqnr_inner")
-    return Bw, dict(n_updates=int(nup.value), row_steps=int(total.value), last_viol=last.value, steps=steps)
+    return Bw, dict(n_updates=int(nup.value), row_steps=int(total.value), last_viol=last.value, steps=steps,
+                    phi_last=phi_last)
 
 
-def pqnr_solve(X, model, kmax, lmax, tau=0.0, eps=1e-10):
-    """CP-APR with PQNR row solves in place of the MU inner loop (no S shift).
-    Returns (model, stats dict); the input model is not modified."""
+def pqnr_solve(X, model, kmax, lmax, tau=0.0, eps=1e-10, kappa=0.01, kappa_tol=1e-10):
+    """CP-APR with PQNR row solves in place of the MU inner loop (Algorithm 1's
+    outer loop, S shift included). Returns (model, stats dict); the input model
+    is not modified."""
     lib = _load()
     keep = _tensor_args(X)
     lam = np.array(model.lam, dtype=np.float64, copy=True)
@@ -209,8 +213,8 @@ def pqnr_solve(X, model, kmax, lmax, tau=0.0, eps=1e-10):
     conv = C.c_int(0)
     kkt = C.c_double(0)
     rc = lib.oracle_pqnr_solve(*keep[3], C.c_int(model.rank), _ptr(lam), ptrs, C.c_int(kmax), C.c_int(lmax),
-                               C.c_double(tau), C.c_double(eps), C.byref(outer), C.byref(steps), C.byref(conv),
-                               C.byref(kkt))
+                               C.c_double(tau), C.c_double(eps), C.c_double(kappa), C.c_double(kappa_tol),
+                               C.byref(outer), C.byref(steps), C.byref(conv), C.byref(kkt))
     _check(rc, "pqnr_solve")
     return _Kruskal(lam, arrs), dict(outer_iters=outer.value, row_steps=steps.value,
                                   converged=bool(conv.value), kkt=kkt.value)

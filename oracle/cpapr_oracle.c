@@ -330,11 +330,18 @@ int oracle_mttkrp(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* i
  *   5. Projected backtracking: for alpha = 1, 1/2, ... (PQNR_TRIALS trials)
  *      delta = max(b + alpha d, 0) - b; accept the first with g.delta < 0 and
  *      f(b + delta) - f(b) <= PQNR_SIGMA g.delta, where the decrease is
- *      formed term by term (sum_r delta_r - sum_k x_k log1p(delta.pi_k / m_k),
- *      with the clamped logs where m or m + delta.pi reaches eps) instead of
- *      as a difference of two large sums. With no acceptable trial the MU step
- *      b .* phi = b + (-b .* g) is taken (it never increases f).
+ *      formed term by term (sum_r delta_r - sum_k x_k log1p(delta.pi_k / m_k))
+ *      instead of as a difference of two large sums. The objective is the
+ *      negative log-likelihood, finite only while every model value of the
+ *      row is positive: a trial that brings some m_k (above eps now) down to
+ *      eps or below is rejected (the floor only guards a point that is
+ *      already there, for which the clamped logarithms are used). With no
+ *      acceptable trial the MU step b .* phi = b + (-b .* g) is taken (it
+ *      never increases f and keeps every m_k positive).
  *   6. b <- b + delta; the iteration counts as an update.
+ * The outer loop is Algorithm 1's, S shift included: a row entry held at
+ * zero whose gradient is negative (Phi > 1) is an inadmissible zero for any
+ * inner solver, and the shift lifts it before B is formed.
  * ------------------------------------------------------------------------ */
 #define PQNR_MEM 3
 #define PQNR_CURV 1e-10
@@ -356,7 +363,7 @@ static double dot_masked(int R, const double* a, const double* b, const uint8_t*
 
 /* one row of one mode: nz[] are the row's nonzero ids, pis[j*R..] their pi */
 static void pqnr_row(int R, int64_t nrow, const double* xs, const double* pis, double* b,
-                     int lmax, double tau, double eps, int* steps_out, double* viol_out)
+                     int lmax, double tau, double eps, int* steps_out, double* viol_out, double* phi_out)
 {
     pqnr_pairs P;
     P.R = R;
@@ -455,6 +462,7 @@ static void pqnr_row(int R, int64_t nrow, const double* xs, const double* pis, d
             }
             if (!(gdel < 0.0)) continue;
             double ls = 0.0, lc = 0.0;
+            int outside = 0;
             for (int64_t j = 0; j < nrow; ++j) {
                 const double* pi = pis + j * R;
                 double m = 0.0, dm = 0.0;
@@ -464,12 +472,17 @@ static void pqnr_row(int R, int64_t nrow, const double* xs, const double* pis, d
                 }
                 const double m1 = m + dm;
                 double term;
-                if (m > eps && m1 > eps)
+                if (m > eps && m1 > eps) {
                     term = log1p(dm / m);
-                else
-                    term = log(m1 > eps ? m1 : eps) - log(m > eps ? m : eps);
+                } else if (m > eps) {
+                    outside = 1; /* the trial leaves the domain of f */
+                    break;
+                } else {
+                    term = log(m1 > eps ? m1 : eps) - log(eps);
+                }
                 neumaier_add(&ls, &lc, xs[j] * term);
             }
+            if (outside) continue;
             const double df = lin - (ls + lc);
             if (df <= PQNR_SIGMA * gdel) accepted = 1;
         }
@@ -485,6 +498,8 @@ static void pqnr_row(int R, int64_t nrow, const double* xs, const double* pis, d
     }
     *steps_out = steps;
     *viol_out = viol;
+    if (phi_out)
+        for (int r = 0; r < R; ++r) phi_out[r] = phi[r]; /* the last Phi row computed */
 }
 
 /* PQNR inner iterations of one mode, row by row (rows are independent).
@@ -496,7 +511,7 @@ int oracle_pqnr_inner_rows(int nmodes, const int64_t* dims, int64_t nnz, const i
                            const double* vals, int mode, int R, double* B,
                            const double* const* A, int lmax, double tau, double eps,
                            const uint8_t* row_mask, int* n_updates, int64_t* row_steps,
-                           double* last_viol, int* row_steps_out)
+                           double* last_viol, int* row_steps_out, double* Phi_last)
 {
     if (check_args(nmodes, dims, nnz, idx, vals, R) || mode < 0 || mode >= nmodes || lmax < 1 ||
         R > 256 || !B)
@@ -540,7 +555,7 @@ int oracle_pqnr_inner_rows(int nmodes, const int64_t* dims, int64_t nnz, const i
         }
         int st = 0;
         double v = 0.0;
-        pqnr_row(R, nrow, xs, pis, B + i * R, lmax, tau, eps, &st, &v);
+        pqnr_row(R, nrow, xs, pis, B + i * R, lmax, tau, eps, &st, &v, Phi_last ? Phi_last + i * R : NULL);
         if (row_steps_out) row_steps_out[i] = st;
         if (st > maxsteps) maxsteps = st;
         total += st;
@@ -553,20 +568,29 @@ int oracle_pqnr_inner_rows(int nmodes, const int64_t* dims, int64_t nnz, const i
     return 0;
 }
 
-/* CP-APR with PQNR row solves: the outer loop of Algorithm 1 with the MU inner
- * loop replaced by the row solves and no S shift (a projected method moves
- * entries off zero itself). lam and A[m] in/out. */
+/* CP-APR with PQNR row solves: the outer loop of Algorithm 1 (S shift
+ * included, from the last Phi of each mode) with the MU inner loop replaced by
+ * the row solves. lam and A[m] in/out. */
 int oracle_pqnr_solve(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
                       const double* vals, int R, double* lam, double* const* A, int kmax, int lmax,
-                      double tau, double eps, int* outer_iters, int64_t* row_steps, int* converged,
-                      double* kkt)
+                      double tau, double eps, double kappa, double kappa_tol, int* outer_iters,
+                      int64_t* row_steps, int* converged, double* kkt)
 {
     if (check_args(nmodes, dims, nnz, idx, vals, R) || kmax < 1 || lmax < 1 || !lam || !A || R > 256)
         return -1;
     int64_t maxI = 0;
     for (int m = 0; m < nmodes; ++m) if (dims[m] > maxI) maxI = dims[m];
     double* B = (double*)malloc((size_t)maxI * R * sizeof(double));
-    if (!B) return -2;
+    double** phi_prev = (double**)calloc((size_t)(unsigned)nmodes, sizeof(double*));
+    if (!B || !phi_prev) { free(B); free(phi_prev); return -2; }
+    for (int m = 0; m < nmodes; ++m) {
+        phi_prev[m] = (double*)calloc((size_t)dims[m] * R, sizeof(double));
+        if (!phi_prev[m]) {
+            for (int q = 0; q < m; ++q) free(phi_prev[q]);
+            free(phi_prev); free(B);
+            return -2;
+        }
+    }
     int k, conv = 0, rc = 0;
     int64_t total = 0;
     double kkt_sweep = 0.0;
@@ -576,6 +600,9 @@ int oracle_pqnr_solve(int nmodes, const int64_t* dims, int64_t nnz, const int32_
         for (int n = 0; n < nmodes; ++n) {
             const int64_t In = dims[n];
             double* An = A[n];
+            if (k > 1) /* S, as in Algorithm 1 */
+                for (int64_t e = 0; e < In * R; ++e)
+                    if (An[e] < kappa_tol && phi_prev[n][e] > 1.0) An[e] += kappa;
             for (int64_t i = 0; i < In; ++i)
                 for (int r = 0; r < R; ++r) B[i * R + r] = An[i * R + r] * lam[r];
             int upd = 0;
@@ -583,7 +610,7 @@ int oracle_pqnr_solve(int nmodes, const int64_t* dims, int64_t nnz, const int32_
             double v = 0.0;
             rc = oracle_pqnr_inner_rows(nmodes, dims, nnz, idx, vals, n, R, B,
                                         (const double* const*)A, lmax, tau, eps, NULL, &upd, &st,
-                                        &v, NULL);
+                                        &v, NULL, phi_prev[n]);
             if (rc) goto done;
             if (upd > 0) any_update = 1;
             total += st;
@@ -605,6 +632,8 @@ done:
     if (row_steps) *row_steps = total;
     if (converged) *converged = conv;
     if (kkt) *kkt = kkt_sweep;
+    for (int m = 0; m < nmodes; ++m) free(phi_prev[m]);
+    free(phi_prev);
     free(B);
     return rc;
 }

@@ -503,7 +503,7 @@ int cpapr_solve(cpapr_plan* plan, double* lambda, double* const* A, cpapr_stats*
                 if (e.code) return report(e);
                 const bool pqnr = P->params.method == CPAPR_METHOD_PQNR;
                 e = cpapr::launch_shift_scale(A[n], P->phi_prev[n], lambda, P->B, In, R, P->params.kappa,
-                                              P->params.kappa_tol, k > 1 && !pqnr, s);
+                                              P->params.kappa_tol, k > 1, s);
                 if (e.code) return report(e);
                 e = pqnr ? cpapr::enqueue_pqnr_inner(P, n, P->B, fac, P->phi_prev[n], s)
                          : enqueue_inner(P, n, P->B, fac, P->phi_prev[n], s);

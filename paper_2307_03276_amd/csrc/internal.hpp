@@ -53,6 +53,7 @@ struct PqnrState {
     double* Gp;     // gradient before the last step
     double* Dd;     // search direction
     double* Dt;     // trial step (after a step: the step taken)
+    double* T;      // line-search sums (column 0 of each row)
     double* S;      // kPqnrMem x (rows x R) steps of the kept pairs
     double* Y;      // kPqnrMem x (rows x R) gradient changes of the kept pairs
     double* alpha;  // per row: current trial length
@@ -84,7 +85,8 @@ struct PhiArgs {
     const double* B;
     double* Phi;
     const int* done;
-    const double* D;  // trial step matrix (line-search pass only)
+    const double* D;       // trial step matrix (line-search pass only)
+    const int32_t* live;   // line-search pass: rows with live[row] == 1 are evaluated, the others skipped
     int64_t nnz;
     int R;
     int NM1;
@@ -201,17 +203,19 @@ Error launch_batch_reset(BatchState st, int max_slots, hipStream_t s);
 
 // ---- elementwise and reduction kernels (mu.hip) ----
 Error launch_fill(double* p, int64_t n, double v, const int* done, hipStream_t s);
-// Per-row sums of x_k log(max(m_k + dm_k, eps) / max(m_k, eps)) with m = B pi, dm = D pi
-// into column 0 of `out` (the other columns get 0); skipped when *skip != 0.
-Error launch_delta(const cpapr_plan* P, int mode, const double* B, const double* D, const void* const* fac,
-                   double eps, double* out, const int* skip, hipStream_t s);
+// Per-row sums of the likelihood-term changes along the trial steps D (m = B pi,
+// dm = D pi; see delta_term) into column 0 of `out` (the other columns get 0),
+// for rows with live[row] == 1 only; skipped when *skip != 0.
+Error launch_delta(const cpapr_plan* P, int mode, const double* B, const double* D, const int32_t* live,
+                   const void* const* fac, double eps, double* out, const int* skip, hipStream_t s);
 
 // ---- PQNR row solves (pqnr.hip) ----
 size_t pqnr_bytes(int64_t maxI, int R);
 void pqnr_bind(PqnrState* q, char* base, int64_t maxI, int R);
-// One PQNR inner loop (lmax iterations) for the rows of `mode`; B in/out. Uses
-// `phi` (I_mode x R) as the Phi / line-search buffer. Leaves per-mode stats in
-// the device state (updates = most steps of a row, row_steps, last_viol[mode]).
+// One PQNR inner loop (lmax iterations) for the rows of `mode`; B in/out.
+// `phi` (I_mode x R) receives every Phi pass, so it ends with the last Phi
+// computed. Leaves per-mode stats in the device state (updates = most steps of
+// a row, row_steps, last_viol[mode]).
 Error enqueue_pqnr_inner(cpapr_plan* P, int mode, double* B, const void* const* fac, double* phi, hipStream_t s);
 Error launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 Error launch_reset_state(DevState* st, bool new_sweep, bool all, hipStream_t s);

@@ -181,9 +181,11 @@ constexpr int kLoglik = 2;  // x_k log(max(m_k, eps)) summed per tile (no scatte
 constexpr int kDelta = 3;   // x_k log(max(m_k + dm_k, eps) / max(m_k, eps)) summed per row (column 0)
 
 // The change of the likelihood term of one nonzero along a trial step d of its
-// row, m = b . pi and dm = d . pi: log1p(dm / m) when neither end is clamped
-// (accurate for small steps, unlike a difference of two logarithms), else the
-// difference of the clamped logarithms.
+// row, m = b . pi and dm = d . pi: log1p(dm / m) when neither end is at the
+// floor (accurate for small steps, unlike a difference of two logarithms);
+// -infinity when the step brings m from above eps down to eps or below (the
+// trial leaves the domain of the row objective and must be rejected); from a
+// point already at the floor, the difference of the clamped logarithms.
 template <int G, int RPL>
 __device__ __forceinline__ double delta_term(const double (&b)[RPL], const double (&d)[RPL],
                                              const double (&pi)[RPL], double x, double eps)
@@ -197,7 +199,11 @@ __device__ __forceinline__ double delta_term(const double (&b)[RPL], const doubl
     m = group_sum<G>(m);
     dm = group_sum<G>(dm);
     const double m1 = m + dm;
-    const double t = (m > eps && m1 > eps) ? log1p(div_pos(dm, m)) : log(m1 > eps ? m1 : eps) - log(m > eps ? m : eps);
+    double t;
+    if (m > eps)
+        t = m1 > eps ? log1p(div_pos(dm, m)) : -__builtin_inf();
+    else
+        t = log(m1 > eps ? m1 : eps) - log(eps);
     return x * t;
 }
 
@@ -339,6 +345,10 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
             const int64_t p = base + k * G + lane;
             if (p < p1) {
                 pre[k].row = a.rows[p];
+                // line-search pass: a row not in a line search is staged as ~row
+                // (negative), so the skip costs no load in the gather loop
+                if constexpr (KIND == kDelta)
+                    if (a.live[pre[k].row] != 1) pre[k].row = ~pre[k].row;
 #pragma unroll
                 for (int m = 0; m < NM1; ++m) pre[k].c[m] = a.cofs[(int64_t)m * nnz + p];
                 pre[k].x = a.vals[p];
@@ -361,17 +371,22 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
             int rowu[U];
             double xu[U];
             T fu[U][NM1][RPL];
+            bool liveu[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (q0 + u < cnt) {
                     const Staged<NM1> e = my[q0 + u];
-                    rowu[u] = e.row;
+                    // line-search pass: rows not in a line search contribute nothing
+                    liveu[u] = KIND != kDelta || e.row >= 0;
+                    rowu[u] = liveu[u] ? e.row : ~e.row;
                     xu[u] = e.x;
+                    if (liveu[u]) {
 #pragma unroll
-                    for (int m = 0; m < NM1; ++m) {
-                        const T* f = fac[m] + (uint64_t)e.c[m] + colbase;
+                        for (int m = 0; m < NM1; ++m) {
+                            const T* f = fac[m] + (uint64_t)e.c[m] + colbase;
 #pragma unroll
-                        for (int c = 0; c < RPL; ++c) fu[u][m][c] = f[c];
+                            for (int c = 0; c < RPL; ++c) fu[u][m][c] = f[c];
+                        }
                     }
                 }
             }
@@ -399,15 +414,19 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
                             for (int c = 0; c < RPL; ++c) b[c] = own[c] ? (T)brow[c] : (T)0;
                         }
                         if constexpr (KIND == kDelta) {
-                            const double* drow = a.D + (int64_t)row * R + colbase;
+                            if (liveu[u]) {
+                                const double* drow = a.D + (int64_t)row * R + colbase;
 #pragma unroll
-                            for (int c = 0; c < RPL; ++c) dv[c] = own[c] ? drow[c] : 0.0;
+                                for (int c = 0; c < RPL; ++c) dv[c] = own[c] ? drow[c] : 0.0;
+                            }
                         }
                     }
                     if constexpr (KIND == kDelta) {
                         static_assert(!MIXED, "the line-search pass is FP64");
-                        const double t = delta_term<G, RPL>(b, dv, pi, xu[u], a.eps);
-                        if (lane == 0) acc[0].v += t;
+                        if (liveu[u]) {
+                            const double t = delta_term<G, RPL>(b, dv, pi, xu[u], a.eps);
+                            if (lane == 0) acc[0].v += t;
+                        }
                     } else {
                         const T s = nonzero_scale<G, RPL, MIXED, KIND, T>(b, pi, xu[u], a.eps);
                         if constexpr (KIND == kLoglik) {
@@ -818,13 +837,14 @@ Error launch_phi(const cpapr_plan* P, int mode, const double* B, const void* con
     return e;
 }
 
-Error launch_delta(const cpapr_plan* P, int mode, const double* B, const double* D, const void* const* fac,
-                   double eps, double* out, const int* skip, hipStream_t s)
+Error launch_delta(const cpapr_plan* P, int mode, const double* B, const double* D, const int32_t* live,
+                   const void* const* fac, double eps, double* out, const int* skip, hipStream_t s)
 {
     const int G = P->group;
     const int RPL = rank_block(P->R, G);
     PhiArgs a = make_args(P, mode, B, fac, eps, out, skip);
     a.D = D;
+    a.live = live;
     return dispatch_seg<false, kDelta>(G, RPL, a, s);
 }
 

@@ -7,7 +7,8 @@
 // whose gradient is g = 1 - (row i of Phi), Phi from Algorithm 2. So the Phi
 // engine supplies every gradient, and a second pass over the nonzeros (the
 // line-search kind of the Phi tile code) supplies f_i(b + delta) - f_i(b) for
-// every row's trial step at once.
+// the trial steps of every row still in a line search at once (the other rows'
+// nonzeros are skipped, gathers included).
 //
 // One inner iteration for all rows of the mode, with no host round trip:
 //   Phi pass            -> gradients (skipped once every row has converged)
@@ -22,8 +23,9 @@
 // s.y > kPqnrCurv |s| |y| (at most kPqnrMem); bound set b_r == 0 and g_r > 0;
 // two-loop L-BFGS direction on the free set with the newest usable pair's
 // scaling, else the MU direction -b .* g; projected backtracking from
-// alpha = 1 with sufficient decrease kPqnrSigma; after kPqnrTrials rejected
-// trials the MU step b + (-b .* g).
+// alpha = 1 with sufficient decrease kPqnrSigma, rejecting trials that bring
+// a model value of the row down to the floor eps (they leave the objective's
+// domain); after kPqnrTrials rejected trials the MU step b + (-b .* g).
 #include <algorithm>
 
 #include "internal.hpp"
@@ -393,7 +395,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 size_t pqnr_bytes(int64_t maxI, int R)
 {
     const size_t mat = align256((size_t)maxI * R * 8);
-    return mat * (4 + 2 * kPqnrMem) + 3 * align256((size_t)maxI * 8) + 5 * align256((size_t)maxI * 4);
+    return mat * (5 + 2 * kPqnrMem) + 3 * align256((size_t)maxI * 8) + 5 * align256((size_t)maxI * 4);
 }
 
 void pqnr_bind(PqnrState* q, char* base, int64_t maxI, int R)
@@ -409,6 +411,7 @@ void pqnr_bind(PqnrState* q, char* base, int64_t maxI, int R)
     q->Gp = (double*)take(mat);
     q->Dd = (double*)take(mat);
     q->Dt = (double*)take(mat);
+    q->T = (double*)take(mat);
     q->S = (double*)take(mat * kPqnrMem);
     q->Y = (double*)take(mat * kPqnrMem);
     q->alpha = (double*)take(align256((size_t)maxI * 8));
@@ -438,7 +441,8 @@ Error enqueue_pqnr_inner(cpapr_plan* P, int mode, double* B, const void* const* 
     const int rgrid = (int)std::min<int64_t>(std::max<int64_t>((rows + kBlock - 1) / kBlock, 1), 4096);
     pqnr_reset_kernel<<<rgrid, kBlock, 0, s>>>(P->pq, rows, st);
     CPAPR_LAUNCHED();
-    RowArgs ra{B, phi, rows, R, P->params.tol, P->pq, st};
+    RowArgs ra{B, phi, rows, R, P->params.tol, P->pq, st};   // begin reads Phi
+    RowArgs rt{B, P->pq.T, rows, R, P->params.tol, P->pq, st};  // accept reads the line-search sums
     for (int l = 0; l < P->params.lmax; ++l) {
         Error e = launch_fill(phi, n, 0.0, all_done, s);
         if (e.code) return e;
@@ -453,14 +457,14 @@ Error enqueue_pqnr_inner(cpapr_plan* P, int mode, double* B, const void* const* 
         });
         if (e.code) return e;
         for (int t = 0; t < kPqnrTrials; ++t) {
-            e = launch_fill(phi, n, 0.0, idle, s);
+            e = launch_fill(P->pq.T, n, 0.0, idle, s);
             if (e.code) return e;
-            e = launch_delta(P, mode, B, P->pq.Dt, fac, P->params.eps, phi, idle, s);
+            e = launch_delta(P, mode, B, P->pq.Dt, P->pq.status, fac, P->params.eps, P->pq.T, idle, s);
             if (e.code) return e;
             pqnr_flags_kernel<<<1, 64, 0, s>>>(st, 0);
             CPAPR_LAUNCHED();
             e = by_group(rg, [&](auto RG) -> Error {
-                pqnr_accept_kernel<decltype(RG)::value><<<grid, kBlock, 0, s>>>(ra);
+                pqnr_accept_kernel<decltype(RG)::value><<<grid, kBlock, 0, s>>>(rt);
                 CPAPR_LAUNCHED();
                 return {CPAPR_OK, ""};
             });
