@@ -77,7 +77,8 @@ enum { CPAPR_SORT_ROW = 0, CPAPR_SORT_ROW_COL = 1 };
  * sum(b) - sum_k x_k log(max(b . pi_k, eps)) over b >= 0 by L-BFGS steps (3
  * pairs) over the variables not held at zero, with a projected backtracking
  * line search (sufficient decrease 1e-4, trials that bring a model value to
- * the floor eps rejected, 4 trials, then the MU step); rows stop independently
+ * the floor eps rejected, 4 trials, then the MU step and the pairs dropped);
+ * rows stop independently
  * when max|min(b, 1 - phi)| < tol. The outer loop, S shift included, is
  * Algorithm 1's. PQNR runs in FP64 only (precision CPAPR_FP64) and needs
  * R <= 256. */

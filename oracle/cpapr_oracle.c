@@ -337,7 +337,8 @@ int oracle_mttkrp(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* i
  *      eps or below is rejected (the floor only guards a point that is
  *      already there, for which the clamped logarithms are used). With no
  *      acceptable trial the MU step b .* phi = b + (-b .* g) is taken (it
- *      never increases f and keeps every m_k positive).
+ *      never increases f and keeps every m_k positive) and the kept pairs
+ *      are dropped (they led to a direction without sufficient decrease).
  *   6. b <- b + delta; the iteration counts as an update.
  * The outer loop is Algorithm 1's, S shift included: a row entry held at
  * zero whose gradient is negative (Phi > 1) is an inadmissible zero for any
@@ -486,6 +487,7 @@ static void pqnr_row(int R, int64_t nrow, const double* xs, const double* pis, d
             const double df = lin - (ls + lc);
             if (df <= PQNR_SIGMA * gdel) accepted = 1;
         }
+        if (!accepted) P.count = 0; /* the curvature pairs misled the search: drop them */
         if (!accepted) /* the MU step b .* phi, written as b + (-b .* g) */
             for (int r = 0; r < R; ++r) delta[r] = -b[r] * g[r];
         /* 6. step */

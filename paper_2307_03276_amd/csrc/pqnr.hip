@@ -25,7 +25,8 @@
 // scaling, else the MU direction -b .* g; projected backtracking from
 // alpha = 1 with sufficient decrease kPqnrSigma, rejecting trials that bring
 // a model value of the row down to the floor eps (they leave the objective's
-// domain); after kPqnrTrials rejected trials the MU step b + (-b .* g).
+// domain); after kPqnrTrials rejected trials the MU step b + (-b .* g), and the
+// row's pairs are dropped.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -326,6 +327,7 @@ __global__ __launch_bounds__(kBlock) void pqnr_accept_kernel(RowArgs a)
     if (lane == 0) {
         q.steps[i] += 1;
         q.status[i] = kActive;
+        if (!accept) q.npairs[i] = 0;  // the pairs led to no sufficient decrease: drop them
     }
 }
 
