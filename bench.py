@@ -83,12 +83,16 @@ def cpu_baseline(X, M, modes=None, max_nnz=None):
     if max_nnz is not None and X.nnz > max_nnz:
         X = synth.SparseTensor(X.dims, np.ascontiguousarray(X.idx[:, :max_nnz]), X.vals[:max_nnz].copy())
     t0 = time.perf_counter()
-    for n in range(modes):
-        oracle.phi(X, n, M.factors[n] * M.lam, M.factors)
+    passes = 0
+    # whole passes over the sampled modes until about 10 s of CPU work (at most 4)
+    while passes < 4 and (passes == 0 or time.perf_counter() - t0 < 10.0):
+        for n in range(modes):
+            oracle.phi(X, n, M.factors[n] * M.lam, M.factors)
+        passes += 1
     dt = time.perf_counter() - t0
-    return {"value": modes * X.nnz / dt, "unit": "nonzeros/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle Phi(n) for {modes} mode(s) over the first {X.nnz} nonzeros of the same "
-                      f"tensor, single thread, {dt:.1f} s"}
+    return {"value": passes * modes * X.nnz / dt, "unit": "nonzeros/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle Phi(n), {passes} pass(es) over {modes} mode(s) of the first {X.nnz} nonzeros "
+                      f"of the same tensor, single thread, {dt:.1f} s"}
 
 
 def batch_workload(args):
