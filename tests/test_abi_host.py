@@ -84,6 +84,8 @@ def test_workspace_size_grows_with_problem(lib):
     ([4, 5, 6], 10, 4, "variant", 9, -1),
     ([4, 5, 6], 10, 4, "sort", 5, -1),
     ([4, 5, 6], 10, 4, "method", 7, -1),
+    ([2 ** 27, 5, 6], 10, 64, None, None, -6),          # I x R reaches 2^32 (32-bit row offsets)
+    ([2 ** 26, 5, 6], 10, 63, None, None, 0),           # just below
     ([4, 5, 6, 7, 8], 10, 32, "group", 16, 0),           # N = 5: 16 lanes x 2 ranks is built
     ([4, 5, 6, 7, 8], 10, 64, "group", 16, -6),          # N = 5: 16 lanes x 4 ranks is not
 ])

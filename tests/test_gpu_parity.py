@@ -265,6 +265,29 @@ def test_solve_to_kkt_tolerance_with_shift():
     st, ost = _solve_case(X, M, 30, 10, 1e-4, 1e-10)
 
 
+@pytest.mark.parametrize("dims,R,nnz,seed", [
+    ((6, 5, 4, 3, 5, 4, 3, 2), 3, 400, 31),     # eight modes
+    ((30, 20, 10), 256, 3000, 32),              # the largest rank
+    ((1, 40, 1), 4, 60, 33),                    # single-row modes
+    ((50, 40, 30), 5, 1, 34),                   # one nonzero
+])
+def test_solve_unusual_shapes(dims, R, nnz, seed):
+    """Full fixed-schedule solves at the edges of the supported shapes."""
+    X = synth.random_tensor(seed, dims, nnz)
+    M = synth.random_model(seed, dims, R)
+    _solve_case(X, M, 3, 4, 0.0, 1e-11)
+
+
+def test_solve_all_duplicates():
+    """Every nonzero at the same cell: one row per mode holds all of them."""
+    import numpy as np
+    dims = (7, 6, 5)
+    idx = np.tile(np.array([[3], [2], [4]], dtype=np.int32), (1, 500))
+    X = synth.SparseTensor(dims, idx, np.full(500, 2.0))
+    M = synth.random_model(35, dims, 4)
+    _solve_case(X, M, 3, 5, 0.0, 1e-11)
+
+
 def test_solve_mixed_precision_fixed_schedule():
     """Mixed precision against the FP64 oracle over 10 x 10 MU steps: lambda and
     every factor within 1e-5 normwise; the log-likelihood within 1e-5."""

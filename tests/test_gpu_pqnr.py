@@ -71,6 +71,24 @@ def test_pqnr_converged_rows_match_oracle(dims, R, nnz):
     P.close()
 
 
+@pytest.mark.parametrize("dims,R,nnz", [((6, 5, 4, 3, 5, 4, 3, 2), 3, 500), ((30, 20, 10), 256, 4000)])
+def test_pqnr_unusual_shapes_lockstep(dims, R, nnz):
+    """Eight modes, and the largest rank (four columns per lane of a 64-lane row group)."""
+    X = synth.random_tensor(41, dims, nnz)
+    M = synth.random_model(41, dims, R)
+    P = _plan(X, R, lmax=3, tol=0.0)
+    A = [dev(a) for a in M.factors]
+    for n in range(len(dims)):
+        Bh = M.factors[n] * M.lam
+        B = dev(Bh)
+        st = P.pqnr_inner(n, B, A)
+        Bo, ost = oracle.pqnr_inner(X, n, Bh, M.factors, lmax=3, tau=0.0)
+        assert st["row_steps"] == ost["row_steps"]
+        got = host(B)
+        assert np.max(np.abs(got - Bo)) <= 1e-12 * np.max(np.abs(Bo)), f"mode {n}"
+    P.close()
+
+
 def test_pqnr_rank_one_and_empty_rows():
     """R = 1: one step reaches the row totals exactly (the MU step is the row
     optimum); rows without nonzeros go to zero and stop."""
