@@ -314,3 +314,35 @@ def test_mttkrp_matches_oracle(dims, R):
     for n in range(len(dims)):
         assert_parity(host(P.mttkrp(n, A)), oracle.mttkrp(X, n, M.factors), TOL64, f"mode {n}")
     P.close()
+
+
+def test_phi_and_inner_loop_random_sweep():
+    """Thirty seeded random cases (2-6 modes, dims 1-300, R 1-48, uniform or
+    Zipf coordinates, FP64 and mixed): Phi of every mode and a 3-step inner
+    loop of one mode against the oracle."""
+    import numpy as np
+    rng = np.random.default_rng(77)
+    for case in range(30):
+        N = int(rng.integers(2, 7))
+        dims = tuple(int(d) for d in rng.integers(1, 300, size=N))
+        nnz = int(rng.integers(1, 5000))
+        R = int(rng.integers(1, 49))
+        zipf = tuple(1.1 if rng.random() < 0.5 else None for _ in range(N))
+        mixed = bool(rng.random() < 0.3)
+        X = synth.random_tensor(500 + case, dims, nnz, zipf=zipf)
+        M = synth.random_model(500 + case, dims, R)
+        prec = cpapr.CPAPR_MIXED if mixed else cpapr.CPAPR_FP64
+        tol = TOLMIX if mixed else TOL64
+        P = cpapr.Plan.from_tensor(X, R, precision=prec, lmax=3, tol=0.0)
+        A = [dev(a) for a in M.factors]
+        for n in range(N):
+            Bh = M.factors[n] * M.lam
+            got = host(P.phi(n, dev(Bh), A))
+            assert_parity(got, oracle.phi(X, n, Bh, M.factors), tol, f"case {case} dims={dims} R={R} mode {n}")
+        n = int(rng.integers(0, N))
+        Bh = M.factors[n] * M.lam
+        B = dev(Bh)
+        P.mu_inner(n, B, A)
+        Bo, _, _, _ = oracle.mu_inner(X, n, Bh, M.factors, lmax=3)
+        assert_parity(host(B), Bo, tol, f"case {case} inner loop", elementwise=not mixed)
+        P.close()
