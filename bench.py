@@ -1,18 +1,26 @@
 """Benchmark: CP-APR MU on one MI355X, Phi(n) nonzeros per second.
 
-One step = one whole CP-APR MU job on the 3-way 200,000 x 150,000 x 20,000
-tensor with 20M Zipf(1.1) nonzeros (duplicates kept), counts 1+Poisson(3),
-rank 16: plan creation (per-mode device sort), the fixed 5 outer x 10 inner
-schedule over all three modes (Phi, KKT, MU update, normalisation), and the
-log-likelihood of the result. Inputs are resident in HBM before timing.
+Default workload: one step = one whole CP-APR MU job on the 3-way
+200,000 x 150,000 x 20,000 tensor with 20M Zipf(1.1) nonzeros (duplicates
+kept), counts 1+Poisson(3), rank 16: plan creation (per-mode device sort), the
+fixed 5 outer x 10 inner schedule over all three modes (Phi, KKT, MU update,
+normalisation), and the log-likelihood of the result. Inputs are resident in
+HBM before timing.
 
-value = Phi nonzero visits per second over the whole step
-        (outer x modes x inner x nnz / step time).
+value = Phi nonzero visits per second over the whole step (Phi evaluations
+        the solve actually computed x nnz / step time).
 roofline: the Phi kernel, timed by HIP events on its own stream inside the
-        timed steps, against HBM peak, with its algorithmic bytes per launch
-        (per nonzero: coordinates, value, the other modes' factor rows; per
-        nonempty row: the B row read and the Phi row write).
-cpu_baseline: the FP64 CPU oracle on one core, Phi over every mode once.
+        timed steps, against HBM peak, with its compulsory bytes per launch
+        (per nonzero: coordinates and value; each referenced row of the other
+        factors once; per nonempty row: the B row read and the Phi row
+        write); traffic: bytes past L2 per launch from committed counter runs.
+hbm_probe: a measured 1 GiB device copy, for reference beside the peak.
+cpu_baseline: the FP64 CPU oracle on one core, Phi over every mode of the same
+        tensor, whole passes up to about 10 s.
+
+Other workloads: --workload zipf4 (4-way, 100M nonzeros, R = 32, solve to KKT
+1e-4), batch (512 tensors, batched graph replays), serve (a Poisson stream of
+solve requests); --precision mixed; --method pqnr.
 
 Prints one JSON line. Only one GPU is supported.
 """
@@ -93,6 +101,27 @@ def cpu_baseline(X, M, modes=None, max_nnz=None):
     return {"value": passes * modes * X.nnz / dt, "unit": "nonzeros/s", "cores": 1, "kind": "oracle",
             "sample": f"FP64 oracle Phi(n), {passes} pass(es) over {modes} mode(s) of the first {X.nnz} nonzeros "
                       f"of the same tensor, single thread, {dt:.1f} s"}
+
+
+def hbm_probe(torch):
+    """Device-to-device copy of 1 GiB (read + write), best of five, as a measured
+    reference beside the 8 TB/s peak."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    gbs = 2 * src.numel() * 8 / (best / 1000.0) / 1e9
+    del src, dst
+    return {"copy_GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "bytes": 2 * (1 << 30)}
 
 
 def batch_workload(args):
@@ -404,6 +433,7 @@ def main():
                   "phi_evals": st["phi_evals"], "trial_evals": st["trial_evals"], "row_steps": st["row_steps"],
                   "converged": bool(st["converged"]), "kkt": st["kkt_violation"], "loglik": st["loglik"]},
     }
+    out["hbm_probe"] = hbm_probe(torch)
     if not args.no_cpu_baseline:
         if args.workload == "zipf4":
             out["cpu_baseline"] = cpu_baseline(X, M, modes=1)
