@@ -325,7 +325,7 @@ int64_t sort_scratch_bytes(int64_t nnz, int N)
     const int64_t ncounts = ntiles * kRadix;
     size_t b = 0;
     b += align256((size_t)nnz * 4 * record_words(N));       // nonzero records
-    b += 4 * align256((size_t)nnz * 4);                     // keys/payload ping-pong
+    b += 5 * align256((size_t)nnz * 4);                     // keys/payload ping-pong, secondary order
     b += align256((size_t)ncounts * 4);                     // histogram table
     b += align256((size_t)cdiv(ncounts, kScanChunk) * 4 + 4);  // scan chunk sums
     b += 256;                                                // flags / counters
@@ -351,6 +351,8 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
     int32_t* kb = (int32_t*)take((size_t)nnz * 4);
     int32_t* pa = (int32_t*)take((size_t)nnz * 4);
     int32_t* pb = (int32_t*)take((size_t)nnz * 4);
+    int32_t* secperm = (int32_t*)take((size_t)nnz * 4);  // order by the secondary key, kept for reuse
+    int sec_cached = -1;
     int* counts = (int*)take((size_t)ncounts * 4);
     int* sums = (int*)take((size_t)cdiv(ncounts, kScanChunk) * 4 + 4);
     int* flags = (int*)take(256);
@@ -410,10 +412,18 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
         if (P->params.sort == CPAPR_SORT_ROW_COL)
             for (int m = 0; m < N; ++m)
                 if (m != n && (sec < 0 || P->dims[m] > P->dims[sec])) sec = m;
-        if (sec >= 0) {
+        if (sec >= 0 && sec == sec_cached) {
+            pin = secperm;  // the same secondary order as the previous mode's: reuse it
+        } else if (sec >= 0) {
             kin = X->idx + (int64_t)sec * nnz;
             Error e = passes(P->dims[sec]);
             if (e.code) return e;
+            if (pin != nullptr) {
+                CPAPR_HIP(hipMemcpyAsync(secperm, pin, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s));
+                sec_cached = sec;
+            }
+        }
+        if (sec >= 0) {
             if (pin != nullptr) {  // keys of mode n in the secondary order
                 int32_t* kout = (kin == ka) ? kb : ka;
                 permute_keys_kernel<<<grid_for(nnz), kBlock, 0, s>>>(X->idx + (int64_t)n * nnz, pin, nnz, kout);
