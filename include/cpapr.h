@@ -24,8 +24,8 @@
  *     cpapr_plan_workspace_size().
  *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
  *     stream). cpapr_phi is stream-ordered and returns without waiting.
- *     Functions that fill host results (plan creation, mu_inner, solve,
- *     loglik) wait for the stream before returning.
+ *     Functions that fill host results (plan creation, mu_inner, pqnr_inner,
+ *     solve, loglik, batch status) wait for the stream before returning.
  *   - Errors: 0 on success, a negative CPAPR_E* code otherwise, with a
  *     message from cpapr_last_error() (thread-local). No C++ exception
  *     crosses this boundary. Non-convergence is not an error.

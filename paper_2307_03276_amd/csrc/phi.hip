@@ -25,6 +25,11 @@
 // Mixed precision: factors and pi are FP32; products and sums carry an FP32
 // error term (TwoProd by FMA, Knuth TwoSum), and Phi partials leave registers
 // as FP64 hi + lo.
+//
+// The same tile code serves four kinds of pass over the nonzeros: Phi, MTTKRP
+// (Eqs. 10-12: x_k pi_k scattered), the log-likelihood terms (summed per tile)
+// and the line-search sums of the PQNR row solves (per-row changes of the
+// likelihood along trial steps).
 #include <algorithm>
 #include <type_traits>
 
