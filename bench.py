@@ -56,10 +56,16 @@ def phi_issued_bytes(N, R, nnz, segs, mode, word=8):
 
 
 def kernel_source_hash():
+    """Hash of the Phi kernel's source with comments and whitespace removed, so
+    that counters stay attached to the code they were taken on and only to it."""
+    import re
     h = hashlib.sha256()
     for f in ("phi.hip", "internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2307_03276_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2307_03276_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update("".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
