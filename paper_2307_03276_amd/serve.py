@@ -46,11 +46,10 @@ class Request:
 
 
 class _Active:
-    """Device state and loop counters of an admitted request."""
+    """Loop counters of an admitted request; `h` is the executor's handle."""
 
-    def __init__(self, req: Request, slot: int, plan, lam, A, B, phi, nbytes: int):
-        self.req, self.slot, self.plan = req, slot, plan
-        self.lam, self.A, self.B, self.phi = lam, A, B, phi
+    def __init__(self, req: Request, slot: int, h, nbytes: int):
+        self.req, self.slot, self.h = req, slot, h
         self.nbytes = nbytes
         self.N = len(req.X.dims)
         self.k, self.n = 1, 0
@@ -60,20 +59,91 @@ class _Active:
         self.dirty = True  # slot operands changed since the last commit
 
 
-class Server:
-    def __init__(self, budget_bytes: float = 200e9, max_slots: int = 64, max_tiles: int = 1 << 22,
-                 kmax: int = 20, lmax: int = 10, tol: float = 1e-4, eps: float = 1e-10,
-                 precision: int = cpapr.CPAPR_MIXED, use_graph: bool = True, stream=None,
-                 compute_loglik: bool = True):
+class GpuExecutor:
+    """Device side of the service: plans, factors and one batch whose slots
+    hold the active requests' current modes (the C ABI's batch calls)."""
+
+    def __init__(self, params: dict, max_slots: int, max_tiles: int, use_graph: bool, stream, compute_loglik: bool):
         import torch
-        self.budget = float(budget_bytes)
-        self.used = 0.0
-        self.max_slots = max_slots
-        self.params = dict(kmax=kmax, lmax=lmax, tol=tol, eps=eps, precision=precision)
+        self.params = params
         self.use_graph = use_graph
         self.compute_loglik = compute_loglik
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self.batch = cpapr.Batch(max_slots, max_tiles)
+        self.flags = cpapr.CPAPR_BATCH_F32_CURRENT if params["precision"] == cpapr.CPAPR_MIXED else 0
+
+    def footprint(self, req: Request) -> int:
+        """Device bytes a request holds while active: plan workspace, factors,
+        B, the last Phi of every mode and lambda (its upload buffers are freed
+        once the plan is built)."""
+        X, R = req.X, req.M.rank
+        d = (cpapr.C.c_int64 * len(X.dims))(*X.dims)
+        coo = cpapr.cpapr_coo(len(X.dims), cpapr.C.cast(d, cpapr.C.POINTER(cpapr.C.c_int64)), X.nnz, None, None)
+        ws = cpapr.cpapr_plan_workspace_size(coo, R, cpapr.cpapr_params_default(**self.params))
+        mats = sum(X.dims) * R * 8
+        return int(ws + 2 * mats + max(X.dims) * R * 8 + R * 8)
+
+    def admit(self, req: Request):
+        """Upload the tensor, build its plan (device sort) and place the model."""
+        import torch
+        with torch.cuda.stream(self.stream):
+            idx = torch.from_numpy(req.X.idx).to("cuda", non_blocking=False)
+            vals = torch.from_numpy(req.X.vals).to("cuda", non_blocking=False)
+            plan = cpapr.Plan(req.X.dims, idx, vals, req.M.rank, stream=self.stream, **self.params)
+            del idx, vals
+            h = dict(plan=plan, lam=torch.from_numpy(req.M.lam).to("cuda"),
+                     A=[torch.from_numpy(a).to("cuda") for a in req.M.factors],
+                     B=torch.empty((max(req.X.dims), req.M.rank), dtype=torch.float64, device="cuda"),
+                     phi=[torch.zeros((d, req.M.rank), dtype=torch.float64, device="cuda") for d in req.X.dims])
+            cpapr.cpapr_plan_sync_f32(plan.handle, h["A"], self.stream)
+        return h
+
+    def mode_begin(self, h, n: int, k: int):
+        cpapr.cpapr_mode_begin(h["plan"].handle, n, k, h["lam"], h["A"][n], h["phi"][n] if k > 1 else None, h["B"],
+                               self.stream)
+
+    def set_slot(self, slot: int, h, n: int):
+        self.batch.set(slot, h["plan"], n, h["B"], h["A"], h["phi"][n], self.flags)
+
+    def clear_slot(self, slot: int):
+        self.batch.clear(slot)
+
+    def commit(self):
+        self.batch.commit(self.stream)
+
+    def run_round(self, lmax: int):
+        """The whole inner loop of every slot's mode; per-slot (viol, updates, done)."""
+        self.batch.inner(lmax, use_graph=self.use_graph, stream=self.stream)
+        return self.batch.status(self.stream)
+
+    def mode_end(self, h, n: int):
+        cpapr.cpapr_mode_end(h["plan"].handle, n, h["B"], h["lam"], h["A"][n], self.stream)
+
+    def retire(self, h):
+        """Final model (host) and its log-likelihood; frees the request's device memory."""
+        ll = h["plan"].loglik(h["lam"], h["A"], stream=self.stream) if self.compute_loglik else None
+        self.stream.synchronize()
+        lam = h["lam"].cpu().numpy()
+        facs = [x.cpu().numpy() for x in h["A"]]
+        h["plan"].close()
+        h.clear()
+        return lam, facs, ll
+
+
+class Server:
+    """Admission, slots and the per-request loop state of Algorithm 1 over an
+    executor (the GPU executor by default)."""
+
+    def __init__(self, budget_bytes: float = 200e9, max_slots: int = 64, max_tiles: int = 1 << 22,
+                 kmax: int = 20, lmax: int = 10, tol: float = 1e-4, eps: float = 1e-10,
+                 precision: int = cpapr.CPAPR_MIXED, use_graph: bool = True, stream=None,
+                 compute_loglik: bool = True, executor=None):
+        self.budget = float(budget_bytes)
+        self.used = 0.0
+        self.max_slots = max_slots
+        self.params = dict(kmax=kmax, lmax=lmax, tol=tol, eps=eps, precision=precision)
+        self.ex = executor if executor is not None else GpuExecutor(self.params, max_slots, max_tiles, use_graph,
+                                                                   stream, compute_loglik)
         self.queue: deque = deque()
         self.active: List[_Active] = []
         self.free_slots = list(range(max_slots - 1, -1, -1))
@@ -86,22 +156,13 @@ class Server:
 
     # ------------------------------------------------------------------ admission
     def footprint(self, req: Request) -> int:
-        """Device bytes a request holds while active: plan workspace, factors,
-        B, the last Phi of every mode and lambda (its upload buffers are freed
-        once the plan is built)."""
-        X, R = req.X, req.M.rank
-        d = (cpapr.C.c_int64 * len(X.dims))(*X.dims)
-        coo = cpapr.cpapr_coo(len(X.dims), cpapr.C.cast(d, cpapr.C.POINTER(cpapr.C.c_int64)), X.nnz, None, None)
-        ws = cpapr.cpapr_plan_workspace_size(coo, R, cpapr.cpapr_params_default(**self.params))
-        mats = sum(X.dims) * R * 8
-        return int(ws + 2 * mats + max(X.dims) * R * 8 + R * 8)
+        return self.ex.footprint(req)
 
     def submit(self, req: Request):
         req.stats["t_submit"] = time.perf_counter() - self.t0
         self.queue.append(req)
 
     def _admit(self):
-        import torch
         while self.queue and self.free_slots:
             req = self.queue[0]
             need = self.footprint(req)
@@ -115,17 +176,7 @@ class Server:
                 break  # first come, first served: wait for memory
             self.queue.popleft()
             slot = self.free_slots.pop()
-            with torch.cuda.stream(self.stream):
-                idx = torch.from_numpy(req.X.idx).to("cuda", non_blocking=False)
-                vals = torch.from_numpy(req.X.vals).to("cuda", non_blocking=False)
-                plan = cpapr.Plan(req.X.dims, idx, vals, req.M.rank, stream=self.stream, **self.params)
-                del idx, vals
-                lam = torch.from_numpy(req.M.lam).to("cuda")
-                A = [torch.from_numpy(a).to("cuda") for a in req.M.factors]
-                B = torch.empty((max(req.X.dims), req.M.rank), dtype=torch.float64, device="cuda")
-                phi = [torch.zeros((d, req.M.rank), dtype=torch.float64, device="cuda") for d in req.X.dims]
-                cpapr.cpapr_plan_sync_f32(plan.handle, A, self.stream)
-            act = _Active(req, slot, plan, lam, A, B, phi, need)
+            act = _Active(req, slot, self.ex.admit(req), need)
             self.used += need
             self.peak_used = max(self.peak_used, self.used)
             req.t_admit = time.perf_counter() - self.t0
@@ -135,28 +186,22 @@ class Server:
 
     # ------------------------------------------------------------------ per request
     def _mode_begin(self, a: _Active):
-        n = a.n
-        cpapr.cpapr_mode_begin(a.plan.handle, n, a.k, a.lam, a.A[n], a.phi[n] if a.k > 1 else None, a.B,
-                               self.stream)
+        self.ex.mode_begin(a.h, a.n, a.k)
         a.dirty = True
 
     def _retire(self, a: _Active):
-        import torch
         req = a.req
-        if self.compute_loglik:
-            req.stats["loglik"] = a.plan.loglik(a.lam, a.A, stream=self.stream)
-        self.stream.synchronize()
-        req.result_lam = a.lam.cpu().numpy()
-        req.result_factors = [x.cpu().numpy() for x in a.A]
+        lam, facs, ll = self.ex.retire(a.h)
+        if ll is not None:
+            req.stats["loglik"] = ll
+        req.result_lam, req.result_factors = lam, facs
         req.stats.update(outer_iters=a.k, inner_updates=a.updates,
                          converged=bool(self.params["tol"] > 0 and not a.any_update),
                          kkt=max(a.last_viol))
         req.t_done = time.perf_counter() - self.t0
-        self.batch.clear(a.slot)
+        self.ex.clear_slot(a.slot)
         self._need_commit = True
         self.free_slots.append(a.slot)
-        a.plan.close()
-        del a.A, a.B, a.phi, a.lam
         self.used -= a.nbytes
         self.done.append(req)
 
@@ -169,20 +214,18 @@ class Server:
         self._admit()
         if not self.active:
             return bool(self.queue)
-        flags = cpapr.CPAPR_BATCH_F32_CURRENT if self.params["precision"] == cpapr.CPAPR_MIXED else 0
         changed = False
         for a in self.active:
             if a.dirty:
-                self.batch.set(a.slot, a.plan, a.n, a.B, a.A, a.phi[a.n], flags)
+                self.ex.set_slot(a.slot, a.h, a.n)
                 a.dirty = False
                 changed = True
         if changed or self._need_commit:
-            self.batch.commit(self.stream)
+            self.ex.commit()
             self._need_commit = False
         lmax, kmax, tol = self.params["lmax"], self.params["kmax"], self.params["tol"]
         # the whole inner loop of every active request's current mode, stops on the device
-        self.batch.inner(lmax, use_graph=self.use_graph, stream=self.stream)
-        viol, updates, done = self.batch.status(self.stream)
+        viol, updates, done = self.ex.run_round(lmax)
         self.ticks += 1
         keep = []
         for a in self.active:
@@ -191,7 +234,7 @@ class Server:
             if updates[a.slot] > 0:
                 a.any_update = True
             # mode finished: lambda and normalisation, then the next mode
-            cpapr.cpapr_mode_end(a.plan.handle, a.n, a.B, a.lam, a.A[a.n], self.stream)
+            self.ex.mode_end(a.h, a.n)
             a.n += 1
             if a.n == a.N:
                 a.n = 0
