@@ -107,6 +107,11 @@ typedef struct cpapr_params {
     int32_t chunk;     /* nonzeros per lane group per tile (0 = launch-policy model) */
     int32_t sort;      /* CPAPR_SORT_*: order of the nonzeros inside each row of a mode */
     int32_t method;    /* CPAPR_METHOD_*: inner solver of cpapr_solve */
+    int32_t deterministic; /* 1: rows crossing a tile boundary are summed in a fixed order by a
+                              second small kernel instead of with atomics, so single-plan
+                              results repeat bit for bit (same plan and launch shape); needs
+                              tiles of >= 128 nonzeros and the SEGMENTED variant; batches keep
+                              atomics. 0: atomics (the default). */
 } cpapr_params;
 
 /* Result summary of cpapr_mu_inner / cpapr_solve (host). */
@@ -126,7 +131,7 @@ typedef struct cpapr_plan cpapr_plan;
 
 /* Fill *p with the defaults: kmax 10, lmax 10, tol 1e-4, eps 1e-10,
  * kappa 0.01, kappa_tol 1e-10, FP64, AUTO, group 0, chunk 0, sort ROW_COL,
- * method MU. */
+ * method MU, deterministic 0. */
 void cpapr_params_default(cpapr_params* p);
 
 /* Bytes of device workspace a plan for X at rank R and parameters p needs

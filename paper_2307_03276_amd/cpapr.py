@@ -46,7 +46,7 @@ class cpapr_params(C.Structure):
     _fields_ = [("kmax", C.c_int32), ("lmax", C.c_int32), ("tol", C.c_double), ("eps", C.c_double),
                 ("kappa", C.c_double), ("kappa_tol", C.c_double), ("precision", C.c_int32),
                 ("variant", C.c_int32), ("group", C.c_int32), ("chunk", C.c_int32), ("sort", C.c_int32),
-                ("method", C.c_int32)]
+                ("method", C.c_int32), ("deterministic", C.c_int32)]
 
 
 class cpapr_stats(C.Structure):

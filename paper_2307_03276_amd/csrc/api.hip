@@ -74,6 +74,9 @@ Error check_params(const cpapr_params* p, int32_t R, int nmodes)
     if (p->chunk < 0 || p->chunk > 65536) return {CPAPR_EINVAL, "chunk must be in [0, 65536]"};
     if (p->sort != CPAPR_SORT_ROW && p->sort != CPAPR_SORT_ROW_COL) return {CPAPR_EINVAL, "unknown sort"};
     if (p->method != CPAPR_METHOD_MU && p->method != CPAPR_METHOD_PQNR) return {CPAPR_EINVAL, "unknown method"};
+    if (p->deterministic != 0 && p->deterministic != 1) return {CPAPR_EINVAL, "deterministic must be 0 or 1"};
+    if (p->deterministic && p->variant == CPAPR_VARIANT_ATOMIC)
+        return {CPAPR_EUNSUPPORTED, "the atomic variant is not deterministic"};
     if (p->method == CPAPR_METHOD_PQNR && p->precision != CPAPR_FP64)
         return {CPAPR_EUNSUPPORTED, "PQNR runs in FP64 only"};
     return {CPAPR_OK, ""};
@@ -87,11 +90,11 @@ struct Layout {
     size_t mode_rows[CPAPR_MAX_MODES], mode_cidx[CPAPR_MAX_MODES], mode_vals[CPAPR_MAX_MODES];
     size_t f32[CPAPR_MAX_MODES];
     size_t region2;
-    size_t B, phi_prev[CPAPR_MAX_MODES], partial, llpart, colsums, state, pqnr;
+    size_t B, phi_prev[CPAPR_MAX_MODES], partial, llpart, colsums, state, pqnr, det_part, det_rows;
     size_t total;
 };
 
-Layout layout(int N, int64_t nnz, const int64_t* dims, int R, bool mixed, bool pqnr)
+Layout layout(int N, int64_t nnz, const int64_t* dims, int R, bool mixed, bool pqnr, bool det)
 {
     Layout L{};
     size_t off = 0;
@@ -127,6 +130,11 @@ Layout layout(int N, int64_t nnz, const int64_t* dims, int R, bool mixed, bool p
     s += align256(sizeof(cpapr::DevState));
     L.pqnr = off + s;
     if (pqnr) s += cpapr::pqnr_bytes(maxI, R);
+    const int64_t cap = cpapr::det_tile_capacity(nnz);
+    L.det_part = off + s;
+    if (det) s += align256((size_t)2 * cap * R * 8);
+    L.det_rows = off + s;
+    if (det) s += align256((size_t)2 * cap * 4);
     s = std::max(s, (size_t)cpapr::sort_scratch_bytes(nnz, N));
     L.total = off + s;
     return L;
@@ -252,6 +260,7 @@ void cpapr_params_default(cpapr_params* p)
     p->chunk = 0;
     p->sort = CPAPR_SORT_ROW_COL;
     p->method = CPAPR_METHOD_MU;
+    p->deterministic = 0;
 }
 
 const char* cpapr_last_error(void) { return g_error.c_str(); }
@@ -265,7 +274,7 @@ int cpapr_plan_workspace_size(const cpapr_coo* X, int32_t R, const cpapr_params*
         if (e.code) return report(e);
         if (!bytes) return fail(CPAPR_EINVAL, "bytes is NULL");
         *bytes = layout(X->nmodes, X->nnz, X->dims, R, p->precision == CPAPR_MIXED,
-                        p->method == CPAPR_METHOD_PQNR).total;
+                        p->method == CPAPR_METHOD_PQNR, p->deterministic != 0).total;
         return CPAPR_OK;
     } catch (...) {
         return fail(CPAPR_EINVAL, "unexpected exception");
@@ -283,7 +292,8 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
         e = check_params(p, R, X->nmodes);
         if (e.code) return report(e);
         const bool mixed = p->precision == CPAPR_MIXED;
-        const Layout L = layout(X->nmodes, X->nnz, X->dims, R, mixed, p->method == CPAPR_METHOD_PQNR);
+        const Layout L = layout(X->nmodes, X->nnz, X->dims, R, mixed, p->method == CPAPR_METHOD_PQNR,
+                                p->deterministic != 0);
         if (!ws) return fail(CPAPR_EWORKSPACE, "workspace is NULL");
         if (((uintptr_t)ws & 255) != 0) return fail(CPAPR_EWORKSPACE, "workspace must be 256-byte aligned");
         if (ws_bytes < L.total) return fail(CPAPR_EWORKSPACE, "workspace too small");
@@ -312,6 +322,9 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
         P->llpart = (double*)(w + L.llpart);
         P->colsums = (double*)(w + L.colsums);
         P->state = (cpapr::DevState*)(w + L.state);
+        P->det_part = p->deterministic ? (double*)(w + L.det_part) : nullptr;
+        P->det_rows = p->deterministic ? (int32_t*)(w + L.det_rows) : nullptr;
+        P->det_tiles = cpapr::det_tile_capacity(X->nnz);
         if (p->method == CPAPR_METHOD_PQNR) {
             int64_t maxI = 0;
             for (int m = 0; m < P->N; ++m) maxI = std::max(maxI, P->dims[m]);
@@ -325,6 +338,10 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
             return report(e);
         }
         if (p->chunk == 0) P->chunk = cpapr::model_chunk(P, P->group);
+        if (P->det_part != nullptr && (int64_t)(cpapr::kBlock / P->group) * P->chunk < 128) {
+            delete P;
+            return fail(CPAPR_EUNSUPPORTED, "deterministic mode needs tiles of at least 128 nonzeros");
+        }
         e = cpapr::launch_reset_state(P->state, true, true, s);
         if (e.code) {
             delete P;
@@ -355,9 +372,13 @@ int cpapr_plan_set_shape(cpapr_plan* plan, int32_t group, int32_t chunk)
     p.chunk = chunk;
     Error e = check_params(&p, plan->R, plan->N);
     if (e.code) return report(e);
+    const int new_group = cpapr::resolve_group(plan->R, group, plan->N - 1);
+    const int new_chunk = chunk > 0 ? chunk : cpapr::model_chunk(plan, new_group);
+    if (plan->det_part != nullptr && (int64_t)(cpapr::kBlock / new_group) * new_chunk < 128)
+        return fail(CPAPR_EUNSUPPORTED, "deterministic mode needs tiles of at least 128 nonzeros");
     plan->params = p;
-    plan->group = cpapr::resolve_group(plan->R, group, plan->N - 1);
-    plan->chunk = chunk > 0 ? chunk : cpapr::model_chunk(plan, plan->group);
+    plan->group = new_group;
+    plan->chunk = new_chunk;
     return CPAPR_OK;
 }
 

@@ -87,6 +87,9 @@ struct PhiArgs {
     const int* done;
     const double* D;       // trial step matrix (line-search pass only)
     const int32_t* live;   // line-search pass: rows with live[row] == 1 are evaluated, the others skipped
+    double* det_part;      // deterministic mode: [2 x tiles x R] partial rows of the tile ends (head, tail)
+    int32_t* det_rows;     // deterministic mode: [tiles x 2] their row ids (-1: none)
+    int64_t det_tiles;     // tiles the partial buffers hold
     int64_t nnz;
     int R;
     int NM1;
@@ -153,6 +156,9 @@ struct cpapr_plan {
     size_t ws_bytes;
     int group, chunk;                 // resolved launch shape of the Phi kernel
     cpapr::PqnrState pq;              // PQNR row-solve state (method CPAPR_METHOD_PQNR only)
+    double* det_part;                 // deterministic mode: tile-end partial rows (nullptr: atomics)
+    int32_t* det_rows;                // deterministic mode: their row ids
+    int64_t det_tiles;                // tiles the buffers hold (launches with more tiles are refused)
 };
 
 namespace cpapr {
@@ -171,6 +177,8 @@ bool phi_shape_supported(int group, int rpl, int nmodes_other);
 int resolve_group(int R, int requested, int nm1);
 int resolve_chunk(int group, int requested);
 int model_chunk(const cpapr_plan* P, int group);  // default chunk once segments are known
+// Deterministic mode: tiles the partial buffers are sized for (tiles of >= 128 nonzeros).
+inline int64_t det_tile_capacity(int64_t nnz) { return nnz / 128 + 2; }
 // Rank columns per lane (1, 2 or 4) for rank R on `group` lanes; -1 if R > 4 * group.
 int rank_block(int R, int group);
 Error launch_phi(const cpapr_plan* P, int mode, const double* B, const void* const* fac, bool mixed,

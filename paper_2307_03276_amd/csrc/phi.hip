@@ -468,12 +468,27 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
         const int next_row = tile_end < nnz ? a.rows[tile_end] : -1;
         int run = -1;
         double v = 0.0;
+        // Deterministic mode: the tile-end rows' partials are kept (head: the row
+        // continuing from the previous tile; tail: a row starting here and
+        // continuing) and summed in tile order by det_fixup_kernel.
+        double* det = a.det_part;
+        if (det != nullptr && t == 0) {
+            a.det_rows[2 * tile] = -1;
+            a.det_rows[2 * tile + 1] = -1;
+        }
         auto emit = [&](int row, double val) {
             double* dst = a.Phi + (int64_t)row * R + t;
-            if (row == prev_row || row == next_row)
-                unsafeAtomicAdd(dst, val);
-            else
+            if (row == prev_row || row == next_row) {
+                if (det == nullptr) {
+                    unsafeAtomicAdd(dst, val);
+                } else {
+                    const int side = row == prev_row ? 0 : 1;
+                    det[((int64_t)side * a.det_tiles + tile) * R + t] = val;
+                    if (t == 0) a.det_rows[2 * tile + side] = row;
+                }
+            } else {
                 *dst = val;
+            }
         };
         for (int e = 0; e < 2 * NG; ++e) {
             const int re = prow[e];
@@ -640,6 +655,52 @@ __global__ __launch_bounds__(kBlock) void phi_atomic_kernel(PhiArgs a)
 #pragma unroll
         for (int c = 0; c < RPL; ++c)
             if (valid[c]) unsafeAtomicAdd(dst + c, s * pi[c]);
+    }
+}
+
+// Deterministic mode: a row that starts in tile t and continues is the sum of
+// tile t's tail partial and the head partials of the following tiles it
+// covers, added in a fixed order (threads strided over the tiles, then a fixed
+// tree); the row is written with a plain store.
+__global__ __launch_bounds__(kBlock) void det_fixup_kernel(const int32_t* __restrict__ rows, int64_t nnz,
+                                                           int64_t tile_nnz, int64_t tiles, int R,
+                                                           const double* __restrict__ part,
+                                                           const int32_t* __restrict__ det_rows, int64_t cap,
+                                                           double* __restrict__ Phi, const int* done)
+{
+    __shared__ double red[kBlock];
+    if (done != nullptr && *done) return;
+    const int64_t t = blockIdx.x;
+    const int r = det_rows[2 * t + 1];
+    if (r < 0) return;
+    // the run of row r ends at the first position after tile t holding a larger row
+    int64_t lo = (t + 1) * tile_nnz, hi = nnz;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (rows[mid] > r)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    const int64_t t1 = min((lo - 1) / tile_nnz, tiles - 1);  // last tile holding row r
+    int rp = 1;
+    while (rp < R) rp *= 2;
+    const int c = threadIdx.x % rp;
+    const int j = threadIdx.x / rp;
+    const int lanes = kBlock / rp;
+    for (int c0 = 0; c0 < R; c0 += rp) {
+        double v = 0.0;
+        if (c0 + c < R)
+            for (int64_t k = t + 1 + j; k <= t1; k += lanes) v += part[k * R + c0 + c];  // head partials
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = lanes / 2; w > 0; w >>= 1) {
+            if (j < w) red[threadIdx.x] += red[threadIdx.x + w * rp];
+            __syncthreads();
+        }
+        if (j == 0 && c0 + c < R)
+            Phi[(int64_t)r * R + c0 + c] = part[(cap + t) * R + c0 + c] + red[threadIdx.x];
+        __syncthreads();
     }
 }
 
@@ -823,6 +884,30 @@ int model_chunk(const cpapr_plan* P, int group)
     return std::max(1, tile / (kBlock / group));
 }
 
+// Deterministic mode: attach the plan's tile-end buffers to a single-plan launch.
+Error attach_det(const cpapr_plan* P, PhiArgs& a)
+{
+    if (P->det_part == nullptr) return {CPAPR_OK, ""};
+    const int64_t tiles = cdiv(a.nnz, (int64_t)(kBlock / P->group) * a.L);
+    if (tiles > P->det_tiles) return {CPAPR_EUNSUPPORTED, "deterministic mode: tiles smaller than 128 nonzeros"};
+    a.det_part = P->det_part;
+    a.det_rows = P->det_rows;
+    a.det_tiles = P->det_tiles;
+    return {CPAPR_OK, ""};
+}
+
+Error launch_det_fixup(const cpapr_plan* P, int mode, const PhiArgs& a, double* out, const int* done, hipStream_t s)
+{
+    if (a.det_part == nullptr) return {CPAPR_OK, ""};
+    const int64_t tile_nnz = (int64_t)(kBlock / P->group) * a.L;
+    const int64_t tiles = cdiv(a.nnz, tile_nnz);
+    if (tiles <= 0) return {CPAPR_OK, ""};
+    det_fixup_kernel<<<(unsigned)tiles, kBlock, 0, s>>>(P->mode[mode].rows, a.nnz, tile_nnz, tiles, P->R, a.det_part,
+                                                        a.det_rows, a.det_tiles, out, done);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
 Error launch_phi(const cpapr_plan* P, int mode, const double* B, const void* const* fac, bool mixed,
                  double eps, double* Phi, const int* done, hipStream_t s)
 {
@@ -836,10 +921,13 @@ Error launch_phi(const cpapr_plan* P, int mode, const double* B, const void* con
         prof_end(s);
         return e;
     }
+    Error e = attach_det(P, a);
+    if (e.code) return e;
     prof_begin(mode, s);
-    Error e = mixed ? dispatch_seg<true, kPhi>(G, RPL, a, s) : dispatch_seg<false, kPhi>(G, RPL, a, s);
+    e = mixed ? dispatch_seg<true, kPhi>(G, RPL, a, s) : dispatch_seg<false, kPhi>(G, RPL, a, s);
     prof_end(s);
-    return e;
+    if (e.code) return e;
+    return launch_det_fixup(P, mode, a, Phi, done, s);
 }
 
 Error launch_delta(const cpapr_plan* P, int mode, const double* B, const double* D, const int32_t* live,
@@ -850,7 +938,11 @@ Error launch_delta(const cpapr_plan* P, int mode, const double* B, const double*
     PhiArgs a = make_args(P, mode, B, fac, eps, out, skip);
     a.D = D;
     a.live = live;
-    return dispatch_seg<false, kDelta>(G, RPL, a, s);
+    Error e = attach_det(P, a);
+    if (e.code) return e;
+    e = dispatch_seg<false, kDelta>(G, RPL, a, s);
+    if (e.code) return e;
+    return launch_det_fixup(P, mode, a, out, skip, s);
 }
 
 Error launch_mttkrp(const cpapr_plan* P, int mode, const double* const* A, double* M, hipStream_t s)
@@ -860,7 +952,11 @@ Error launch_mttkrp(const cpapr_plan* P, int mode, const double* const* A, doubl
     PhiArgs a = make_args(P, mode, nullptr, (const void* const*)A, 0.0, M, nullptr);
     Error e = zero_matrix(M, P->dims[mode] * (int64_t)P->R, s);
     if (e.code) return e;
-    return dispatch_seg<false, kMttkrp>(G, RPL, a, s);
+    e = attach_det(P, a);
+    if (e.code) return e;
+    e = dispatch_seg<false, kMttkrp>(G, RPL, a, s);
+    if (e.code) return e;
+    return launch_det_fixup(P, mode, a, M, nullptr, s);
 }
 
 int64_t loglik_partials(int64_t nnz) { return cdiv(nnz, 512) + 1; }

@@ -38,7 +38,7 @@ def test_params_default(lib):
     p = cpapr.cpapr_params_default()
     assert (p.kmax, p.lmax, p.tol, p.eps, p.kappa, p.kappa_tol) == (10, 10, 1e-4, 1e-10, 0.01, 1e-10)
     assert p.precision == cpapr.CPAPR_FP64 and p.variant == 0 and p.group == 0 and p.chunk == 0
-    assert p.sort == cpapr.CPAPR_SORT_ROW_COL and p.method == cpapr.CPAPR_METHOD_MU
+    assert p.sort == cpapr.CPAPR_SORT_ROW_COL and p.method == cpapr.CPAPR_METHOD_MU and p.deterministic == 0
 
 
 def _coo(dims, nnz):
@@ -84,6 +84,7 @@ def test_workspace_size_grows_with_problem(lib):
     ([4, 5, 6], 10, 4, "variant", 9, -1),
     ([4, 5, 6], 10, 4, "sort", 5, -1),
     ([4, 5, 6], 10, 4, "method", 7, -1),
+    ([4, 5, 6], 10, 4, "deterministic", 2, -1),
     ([2 ** 27, 5, 6], 10, 64, None, None, -6),          # I x R reaches 2^32 (32-bit row offsets)
     ([2 ** 26, 5, 6], 10, 63, None, None, 0),           # just below
     ([4, 5, 6, 7, 8], 10, 32, "group", 16, 0),           # N = 5: 16 lanes x 2 ranks is built
@@ -97,6 +98,16 @@ def test_workspace_size_rejects(lib, dims, nnz, R, field, val, code):
     assert rc == code
     if code:
         assert cpapr.cpapr_last_error()
+
+
+def test_deterministic_params(lib):
+    coo = _coo([100, 80, 60], 10_000)
+    p = cpapr.cpapr_params_default(deterministic=1)
+    rc, a = _size(coo, 16, p)
+    rc0, b = _size(coo, 16, cpapr.cpapr_params_default())
+    assert rc == 0 and rc0 == 0 and a >= b
+    rc, _ = _size(coo, 16, cpapr.cpapr_params_default(deterministic=1, variant=2))
+    assert rc == -6  # the atomic variant cannot be deterministic
 
 
 def test_pqnr_params(lib):

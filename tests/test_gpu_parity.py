@@ -149,6 +149,46 @@ def test_phi_deterministic_repeat():
     P.close()
 
 
+def test_deterministic_mode_repeats_bit_for_bit():
+    """Deterministic plans: Phi, MTTKRP, a solve and PQNR row solves repeat bit
+    for bit, and still match the oracle; heavy Zipf rows span many tiles."""
+    import numpy as np
+    X = synth.random_tensor(13, (3000, 2000, 100), 300_000, zipf=(1.2, 1.1, 1.1))
+    M = synth.random_model(13, X.dims, 16)
+    P = cpapr.Plan.from_tensor(X, 16, deterministic=1, kmax=2, lmax=3, tol=0.0)
+    A = [dev(a) for a in M.factors]
+    for n in range(3):
+        Bh = M.factors[n] * M.lam
+        B = dev(Bh)
+        a, b = host(P.phi(n, B, A)), host(P.phi(n, B, A))
+        assert np.array_equal(a, b), f"Phi mode {n} differs between runs"
+        assert_parity(a, oracle.phi(X, n, Bh, M.factors), TOL64, f"deterministic Phi mode {n}")
+        m1, m2 = host(P.mttkrp(n, A)), host(P.mttkrp(n, A))
+        assert np.array_equal(m1, m2)
+        assert_parity(m1, oracle.mttkrp(X, n, M.factors), TOL64, f"deterministic MTTKRP mode {n}")
+    outs = []
+    for _ in range(2):
+        lam = dev(M.lam)
+        Af = [dev(a) for a in M.factors]
+        P.solve(lam, Af)
+        outs.append([host(lam)] + [host(x) for x in Af])
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y), "solve differs between runs"
+    with pytest.raises(cpapr.CpaprError) as ei:
+        P.set_shape(8, 8)  # 256-nonzero tiles are fine; 64 are not
+        P.set_shape(8, 2)
+    assert ei.value.code == -6
+    P.close()
+    Pq = cpapr.Plan.from_tensor(X, 16, deterministic=1, lmax=4, tol=0.0, method=cpapr.CPAPR_METHOD_PQNR)
+    res = []
+    for _ in range(2):
+        B = dev(M.factors[0] * M.lam)
+        Pq.pqnr_inner(0, B, A)
+        res.append(host(B))
+    assert np.array_equal(res[0], res[1]), "PQNR differs between runs"
+    Pq.close()
+
+
 def test_plan_segments_counts():
     X, M, _ = synth.config_small()
     P = cpapr.Plan.from_tensor(X, 10)
