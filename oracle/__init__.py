@@ -169,12 +169,7 @@ def mttkrp(X, mode, factors):
     return out
 
 
-def pqnr_inner(X, mode, B, factors, lmax, tau=0.0, eps=1e-10, rows=None):
-    """PQNR row solves of one mode (projected quasi-Newton per row of B; the
-    paper names the variant in its Background). Rows are independent, so
-    ``rows`` restricts the work exactly for any tau. Returns (B, stats) with
-    stats: n_updates (most steps of any row), row_steps (sum over rows),
-    last_viol (largest last KKT violation over rows), steps (per row)."""
+def _rows_inner(fn, X, mode, B, factors, lmax, tau, eps, rows):
     lib = _load()
     keep = _tensor_args(X)
     R = B.shape[1]
@@ -190,20 +185,17 @@ def pqnr_inner(X, mode, B, factors, lmax, tau=0.0, eps=1e-10, rows=None):
     last = C.c_double(0)
     steps = np.zeros(In, dtype=np.int32)
     phi_last = np.full((In, R), np.nan) if rows is not None else np.zeros((In, R))
-    rc = lib.oracle_pqnr_inner_rows(*keep[3], C.c_int(mode), C.c_int(R), _ptr(Bw), ptrs, C.c_int(lmax),
-                                    C.c_double(tau), C.c_double(eps),
-                                    _ptr(mask, C.c_uint8) if mask is not None else None,
-                                    C.byref(nup), C.byref(total), C.byref(last), _ptr(steps, C.c_int32),
-                                    _ptr(phi_last))
-    _check(rc, "pqnr_inner")
+    rc = getattr(lib, fn)(*keep[3], C.c_int(mode), C.c_int(R), _ptr(Bw), ptrs, C.c_int(lmax),
+                          C.c_double(tau), C.c_double(eps),
+                          _ptr(mask, C.c_uint8) if mask is not None else None,
+                          C.byref(nup), C.byref(total), C.byref(last), _ptr(steps, C.c_int32),
+                          _ptr(phi_last))
+    _check(rc, fn)
     return Bw, dict(n_updates=int(nup.value), row_steps=int(total.value), last_viol=last.value, steps=steps,
                     phi_last=phi_last)
 
 
-def pqnr_solve(X, model, kmax, lmax, tau=0.0, eps=1e-10, kappa=0.01, kappa_tol=1e-10):
-    """CP-APR with PQNR row solves in place of the MU inner loop (Algorithm 1's
-    outer loop, S shift included). Returns (model, stats dict); the input model
-    is not modified."""
+def _rows_solve(fn, X, model, kmax, lmax, tau, eps, kappa, kappa_tol):
     lib = _load()
     keep = _tensor_args(X)
     lam = np.array(model.lam, dtype=np.float64, copy=True)
@@ -212,9 +204,39 @@ def pqnr_solve(X, model, kmax, lmax, tau=0.0, eps=1e-10, kappa=0.01, kappa_tol=1
     steps = C.c_int64(0)
     conv = C.c_int(0)
     kkt = C.c_double(0)
-    rc = lib.oracle_pqnr_solve(*keep[3], C.c_int(model.rank), _ptr(lam), ptrs, C.c_int(kmax), C.c_int(lmax),
-                               C.c_double(tau), C.c_double(eps), C.c_double(kappa), C.c_double(kappa_tol),
-                               C.byref(outer), C.byref(steps), C.byref(conv), C.byref(kkt))
-    _check(rc, "pqnr_solve")
+    rc = getattr(lib, fn)(*keep[3], C.c_int(model.rank), _ptr(lam), ptrs, C.c_int(kmax), C.c_int(lmax),
+                          C.c_double(tau), C.c_double(eps), C.c_double(kappa), C.c_double(kappa_tol),
+                          C.byref(outer), C.byref(steps), C.byref(conv), C.byref(kkt))
+    _check(rc, fn)
     return _Kruskal(lam, arrs), dict(outer_iters=outer.value, row_steps=steps.value,
                                   converged=bool(conv.value), kkt=kkt.value)
+
+
+def pqnr_inner(X, mode, B, factors, lmax, tau=0.0, eps=1e-10, rows=None):
+    """PQNR row solves of one mode (projected quasi-Newton per row of B; the
+    paper names the variant in its Background). Rows are independent, so
+    ``rows`` restricts the work exactly for any tau. Returns (B, stats) with
+    stats: n_updates (most steps of any row), row_steps (sum over rows),
+    last_viol (largest last KKT violation over rows), steps (per row),
+    phi_last (the last Phi row computed per row)."""
+    return _rows_inner("oracle_pqnr_inner_rows", X, mode, B, factors, lmax, tau, eps, rows)
+
+
+def pqnr_solve(X, model, kmax, lmax, tau=0.0, eps=1e-10, kappa=0.01, kappa_tol=1e-10):
+    """CP-APR with PQNR row solves in place of the MU inner loop (Algorithm 1's
+    outer loop, S shift included). Returns (model, stats dict); the input model
+    is not modified."""
+    return _rows_solve("oracle_pqnr_solve", X, model, kmax, lmax, tau, eps, kappa, kappa_tol)
+
+
+def pdnr_inner(X, mode, B, factors, lmax, tau=0.0, eps=1e-10, rows=None):
+    """PDNR row solves of one mode (projected damped Newton per row of B with
+    the row's exact Hessian; the other row-wise variant the Background names).
+    Same arguments and results as :func:`pqnr_inner`."""
+    return _rows_inner("oracle_pdnr_inner_rows", X, mode, B, factors, lmax, tau, eps, rows)
+
+
+def pdnr_solve(X, model, kmax, lmax, tau=0.0, eps=1e-10, kappa=0.01, kappa_tol=1e-10):
+    """CP-APR with PDNR row solves in place of the MU inner loop (Algorithm 1's
+    outer loop, S shift included). Returns (model, stats dict)."""
+    return _rows_solve("oracle_pdnr_solve", X, model, kmax, lmax, tau, eps, kappa, kappa_tol)

@@ -504,16 +504,227 @@ static void pqnr_row(int R, int64_t nrow, const double* xs, const double* pis, d
         for (int r = 0; r < R; ++r) phi_out[r] = phi[r]; /* the last Phi row computed */
 }
 
-/* PQNR inner iterations of one mode, row by row (rows are independent).
- * B in/out (I_n x R). Outputs: the largest number of steps any row took
- * (n_updates), the sum of steps over rows (row_steps), the largest last
- * violation over rows (last_viol) and per-row steps (row_steps_out, may be
- * NULL). With row_mask only those rows are solved. R <= 256. */
-int oracle_pqnr_inner_rows(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
-                           const double* vals, int mode, int R, double* B,
-                           const double* const* A, int lmax, double tau, double eps,
-                           const uint8_t* row_mask, int* n_updates, int64_t* row_steps,
-                           double* last_viol, int* row_steps_out, double* Phi_last)
+/* ------------------------------------------------------------------------
+ * PDNR: projected damped Newton for the row subproblems, the other row-wise
+ * variant the Background names. Same row objective f_i, gradient g = 1 - phi
+ * and KKT test as PQNR above; the direction comes from the row's Hessian
+ *
+ *   H = sum_{k in row i} x_k / max(m_k, eps)^2  pi_k pi_k^T,   m_k = b . pi_k
+ *
+ * (the second derivative of -x log(b . pi) is x pi pi^T / (b . pi)^2; with the
+ * floor it is taken at the clamped value, as phi is). The paper prints no
+ * algorithm for the variant; the readings below are this library's:
+ *
+ * One iteration of one row, given b >= 0 and the row's damping mu:
+ *   1. phi, g, viol as PQNR; stop the row when tau > 0 and viol < tau.
+ *   2. H as above (w_k = (x_k / mm_k) / mm_k, mm_k = max(m_k, eps)).
+ *   3. Held set: g_r > 0 and b_r <= PDNR_HELD; the other entries are free.
+ *   4. Direction: d = -g on held entries; on the free set F the damped Newton
+ *      system (H_FF + mu t I) d_F = -g_F, t = trace(H_FF) / |F| (so the
+ *      damping scales with the row's curvature), solved by Cholesky in index
+ *      order. If F is empty, d = -g. If t is not > 0, a Cholesky pivot is not
+ *      > 0, or g.d >= 0: the MU direction -b .* g.
+ *   5. Projected backtracking along d exactly as PQNR's (PDNR_TRIALS trials,
+ *      sufficient decrease PDNR_SIGMA, trials leaving the objective's domain
+ *      rejected). With no acceptable trial: the MU step b + (-b .* g) and
+ *      mu <- min(PDNR_MU_STEP mu, PDNR_MU_MAX).
+ *   6. Accepted step delta with change df: predicted change of the quadratic
+ *      model pred = -(g.delta + delta^T H delta / 2), rho = -df / pred (0 if
+ *      pred <= 0); rho < 1/4: mu <- min(PDNR_MU_STEP mu, PDNR_MU_MAX);
+ *      rho > 3/4: mu <- max(mu / PDNR_MU_STEP, PDNR_MU_MIN).
+ *   7. b <- b + delta; the iteration counts as a step.
+ * mu starts at PDNR_MU0 for every row at the start of an inner loop.
+ * ------------------------------------------------------------------------ */
+#define PDNR_TRIALS 4
+#define PDNR_SIGMA 1e-4
+#define PDNR_HELD 1e-10
+#define PDNR_MU0 1e-3
+#define PDNR_MU_MIN 1e-8
+#define PDNR_MU_MAX 1e8
+#define PDNR_MU_STEP 4.0
+
+/* Projected backtracking from b along d (gradient g): trials alpha = 1, 1/2,
+ * ...; the first with g.delta < 0 and f(b + delta) - f(b) <= sigma g.delta
+ * whose model values all stay in the objective's domain is accepted (delta
+ * and df written, returns 1); none: returns 0. */
+static int projected_search(int R, int64_t nrow, const double* xs, const double* pis, const double* b,
+                            const double* g, const double* d, double eps, int trials, double sigma,
+                            double* delta, double* df_out)
+{
+    double alpha = 1.0;
+    for (int t = 0; t < trials; ++t, alpha *= 0.5) {
+        double gdel = 0.0, lin = 0.0;
+        for (int r = 0; r < R; ++r) {
+            const double nb = b[r] + alpha * d[r];
+            delta[r] = (nb > 0.0 ? nb : 0.0) - b[r];
+            gdel += g[r] * delta[r];
+            lin += delta[r];
+        }
+        if (!(gdel < 0.0)) continue;
+        double ls = 0.0, lc = 0.0;
+        int outside = 0;
+        for (int64_t j = 0; j < nrow; ++j) {
+            const double* pi = pis + j * R;
+            double m = 0.0, dm = 0.0;
+            for (int r = 0; r < R; ++r) {
+                m += b[r] * pi[r];
+                dm += delta[r] * pi[r];
+            }
+            const double m1 = m + dm;
+            double term;
+            if (m > eps && m1 > eps) {
+                term = log1p(dm / m);
+            } else if (m > eps) {
+                outside = 1;
+                break;
+            } else {
+                term = log(m1 > eps ? m1 : eps) - log(eps);
+            }
+            neumaier_add(&ls, &lc, xs[j] * term);
+        }
+        if (outside) continue;
+        const double df = lin - (ls + lc);
+        if (df <= sigma * gdel) {
+            *df_out = df;
+            return 1;
+        }
+    }
+    return 0;
+}
+
+/* one row of one mode; work holds 3 R x R matrices */
+static void pdnr_row(int R, int64_t nrow, const double* xs, const double* pis, double* b, int lmax,
+                     double tau, double eps, int* steps_out, double* viol_out, double* phi_out, double* work)
+{
+    double* H = work;              /* Hessian */
+    double* Hc = work + R * R;     /* its compensation terms */
+    double* L = work + 2 * R * R;  /* damped free-set matrix, overwritten by its Cholesky factor */
+    double phi[256], comp[256], g[256], d[256], delta[256], y[256];
+    int fidx[256];
+    double mu = PDNR_MU0;
+    int steps = 0;
+    double viol = 0.0;
+    for (int l = 0; l < lmax; ++l) {
+        /* 1-2. gradient and Hessian */
+        for (int r = 0; r < R; ++r) phi[r] = comp[r] = 0.0;
+        for (int e = 0; e < R * R; ++e) H[e] = Hc[e] = 0.0;
+        for (int64_t j = 0; j < nrow; ++j) {
+            const double* pi = pis + j * R;
+            double m = 0.0;
+            for (int r = 0; r < R; ++r) m += b[r] * pi[r];
+            const double mm = m > eps ? m : eps;
+            const double sc = xs[j] / mm;
+            const double w = sc / mm;
+            for (int r = 0; r < R; ++r) {
+                neumaier_add(&phi[r], &comp[r], sc * pi[r]);
+                for (int c = 0; c < R; ++c) neumaier_add(&H[r * R + c], &Hc[r * R + c], w * pi[r] * pi[c]);
+            }
+        }
+        for (int e = 0; e < R * R; ++e) H[e] += Hc[e];
+        viol = 0.0;
+        for (int r = 0; r < R; ++r) {
+            phi[r] += comp[r];
+            g[r] = 1.0 - phi[r];
+            const double t = fabs(b[r] < g[r] ? b[r] : g[r]);
+            if (t > viol) viol = t;
+        }
+        if (tau > 0.0 && viol < tau) break;
+        /* 3. held and free entries */
+        int nf = 0;
+        double trace = 0.0;
+        for (int r = 0; r < R; ++r) {
+            if (g[r] > 0.0 && b[r] <= PDNR_HELD) continue;
+            fidx[nf++] = r;
+            trace += H[r * R + r];
+        }
+        /* 4. direction */
+        int newton = 0;
+        for (int r = 0; r < R; ++r) d[r] = -g[r]; /* held entries (and all of d if F is empty) */
+        if (nf == 0) {
+            newton = 1;
+        } else if (trace > 0.0) {
+            const double damp = mu * (trace / nf);
+            for (int a = 0; a < nf; ++a)
+                for (int c = 0; c < nf; ++c)
+                    L[a * nf + c] = H[fidx[a] * R + fidx[c]] + (a == c ? damp : 0.0);
+            newton = 1;
+            for (int c = 0; c < nf && newton; ++c) { /* Cholesky, column by column */
+                double piv = L[c * nf + c];
+                for (int k = 0; k < c; ++k) piv -= L[c * nf + k] * L[c * nf + k];
+                if (!(piv > 0.0)) {
+                    newton = 0;
+                    break;
+                }
+                const double lcc = sqrt(piv);
+                L[c * nf + c] = lcc;
+                for (int a = c + 1; a < nf; ++a) {
+                    double v = L[a * nf + c];
+                    for (int k = 0; k < c; ++k) v -= L[a * nf + k] * L[c * nf + k];
+                    L[a * nf + c] = v / lcc;
+                }
+            }
+            if (newton) {
+                for (int a = 0; a < nf; ++a) { /* L y = -g_F */
+                    double v = -g[fidx[a]];
+                    for (int k = 0; k < a; ++k) v -= L[a * nf + k] * y[k];
+                    y[a] = v / L[a * nf + a];
+                }
+                for (int a = nf - 1; a >= 0; --a) { /* L^T d_F = y */
+                    double v = y[a];
+                    for (int k = a + 1; k < nf; ++k) v -= L[k * nf + a] * d[fidx[k]];
+                    d[fidx[a]] = v / L[a * nf + a];
+                }
+            }
+        }
+        if (newton) {
+            double gd = 0.0;
+            for (int r = 0; r < R; ++r) gd += g[r] * d[r];
+            newton = gd < 0.0;
+        }
+        if (!newton)
+            for (int r = 0; r < R; ++r) d[r] = -b[r] * g[r];
+        /* 5-6. line search and damping */
+        double df = 0.0;
+        if (projected_search(R, nrow, xs, pis, b, g, d, eps, PDNR_TRIALS, PDNR_SIGMA, delta, &df)) {
+            double gdel = 0.0, quad = 0.0;
+            for (int r = 0; r < R; ++r) {
+                double hd = 0.0;
+                for (int c = 0; c < R; ++c) hd += H[r * R + c] * delta[c];
+                gdel += g[r] * delta[r];
+                quad += delta[r] * hd;
+            }
+            const double pred = -(gdel + 0.5 * quad);
+            const double rho = pred > 0.0 ? -df / pred : 0.0;
+            if (rho < 0.25)
+                mu = mu * PDNR_MU_STEP < PDNR_MU_MAX ? mu * PDNR_MU_STEP : PDNR_MU_MAX;
+            else if (rho > 0.75)
+                mu = mu / PDNR_MU_STEP > PDNR_MU_MIN ? mu / PDNR_MU_STEP : PDNR_MU_MIN;
+        } else {
+            for (int r = 0; r < R; ++r) delta[r] = -b[r] * g[r];
+            mu = mu * PDNR_MU_STEP < PDNR_MU_MAX ? mu * PDNR_MU_STEP : PDNR_MU_MAX;
+        }
+        /* 7. step */
+        for (int r = 0; r < R; ++r) b[r] += delta[r];
+        ++steps;
+    }
+    *steps_out = steps;
+    *viol_out = viol;
+    if (phi_out)
+        for (int r = 0; r < R; ++r) phi_out[r] = phi[r];
+}
+
+enum { ROWS_PQNR = 0, ROWS_PDNR = 1 };
+
+/* Row-subproblem inner iterations of one mode (PQNR or PDNR), row by row
+ * (rows are independent). B in/out (I_n x R). Outputs: the largest number of
+ * steps any row took (n_updates), the sum of steps over rows (row_steps), the
+ * largest last violation over rows (last_viol) and per-row steps
+ * (row_steps_out, may be NULL). With row_mask only those rows are solved.
+ * R <= 256. */
+static int rows_inner(int method, int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                      const double* vals, int mode, int R, double* B, const double* const* A, int lmax,
+                      double tau, double eps, const uint8_t* row_mask, int* n_updates, int64_t* row_steps,
+                      double* last_viol, int* row_steps_out, double* Phi_last)
 {
     if (check_args(nmodes, dims, nnz, idx, vals, R) || mode < 0 || mode >= nmodes || lmax < 1 ||
         R > 256 || !B)
@@ -537,7 +748,8 @@ int oracle_pqnr_inner_rows(int nmodes, const int64_t* dims, int64_t nnz, const i
         if (start[i + 1] - start[i] > maxrow) maxrow = start[i + 1] - start[i];
     double* xs = (double*)malloc((size_t)(maxrow > 0 ? maxrow : 1) * sizeof(double));
     double* pis = (double*)malloc((size_t)(maxrow > 0 ? maxrow : 1) * R * sizeof(double));
-    if (!xs || !pis) { free(start); free(order); free(xs); free(pis); return -2; }
+    double* work = (double*)malloc((size_t)4 * R * R * sizeof(double)); /* PDNR matrices */
+    if (!xs || !pis || !work) { free(start); free(order); free(xs); free(pis); free(work); return -2; }
     int maxsteps = 0;
     int64_t total = 0;
     double vmax = 0.0;
@@ -557,7 +769,11 @@ int oracle_pqnr_inner_rows(int nmodes, const int64_t* dims, int64_t nnz, const i
         }
         int st = 0;
         double v = 0.0;
-        pqnr_row(R, nrow, xs, pis, B + i * R, lmax, tau, eps, &st, &v, Phi_last ? Phi_last + i * R : NULL);
+        if (method == ROWS_PDNR)
+            pdnr_row(R, nrow, xs, pis, B + i * R, lmax, tau, eps, &st, &v, Phi_last ? Phi_last + i * R : NULL,
+                     work);
+        else
+            pqnr_row(R, nrow, xs, pis, B + i * R, lmax, tau, eps, &st, &v, Phi_last ? Phi_last + i * R : NULL);
         if (row_steps_out) row_steps_out[i] = st;
         if (st > maxsteps) maxsteps = st;
         total += st;
@@ -566,14 +782,34 @@ int oracle_pqnr_inner_rows(int nmodes, const int64_t* dims, int64_t nnz, const i
     if (n_updates) *n_updates = maxsteps;
     if (row_steps) *row_steps = total;
     if (last_viol) *last_viol = vmax;
-    free(start); free(order); free(xs); free(pis);
+    free(start); free(order); free(xs); free(pis); free(work);
     return 0;
 }
 
-/* CP-APR with PQNR row solves: the outer loop of Algorithm 1 (S shift
- * included, from the last Phi of each mode) with the MU inner loop replaced by
- * the row solves. lam and A[m] in/out. */
-int oracle_pqnr_solve(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
+int oracle_pqnr_inner_rows(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                           const double* vals, int mode, int R, double* B,
+                           const double* const* A, int lmax, double tau, double eps,
+                           const uint8_t* row_mask, int* n_updates, int64_t* row_steps,
+                           double* last_viol, int* row_steps_out, double* Phi_last)
+{
+    return rows_inner(ROWS_PQNR, nmodes, dims, nnz, idx, vals, mode, R, B, A, lmax, tau, eps, row_mask,
+                      n_updates, row_steps, last_viol, row_steps_out, Phi_last);
+}
+
+int oracle_pdnr_inner_rows(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                           const double* vals, int mode, int R, double* B,
+                           const double* const* A, int lmax, double tau, double eps,
+                           const uint8_t* row_mask, int* n_updates, int64_t* row_steps,
+                           double* last_viol, int* row_steps_out, double* Phi_last)
+{
+    return rows_inner(ROWS_PDNR, nmodes, dims, nnz, idx, vals, mode, R, B, A, lmax, tau, eps, row_mask,
+                      n_updates, row_steps, last_viol, row_steps_out, Phi_last);
+}
+
+/* CP-APR with row-subproblem solves (PQNR or PDNR): the outer loop of
+ * Algorithm 1 (S shift included, from the last Phi of each mode) with the MU
+ * inner loop replaced by the row solves. lam and A[m] in/out. */
+static int rows_solve(int method, int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
                       const double* vals, int R, double* lam, double* const* A, int kmax, int lmax,
                       double tau, double eps, double kappa, double kappa_tol, int* outer_iters,
                       int64_t* row_steps, int* converged, double* kkt)
@@ -610,9 +846,8 @@ int oracle_pqnr_solve(int nmodes, const int64_t* dims, int64_t nnz, const int32_
             int upd = 0;
             int64_t st = 0;
             double v = 0.0;
-            rc = oracle_pqnr_inner_rows(nmodes, dims, nnz, idx, vals, n, R, B,
-                                        (const double* const*)A, lmax, tau, eps, NULL, &upd, &st,
-                                        &v, NULL, phi_prev[n]);
+            rc = rows_inner(method, nmodes, dims, nnz, idx, vals, n, R, B, (const double* const*)A, lmax,
+                            tau, eps, NULL, &upd, &st, &v, NULL, phi_prev[n]);
             if (rc) goto done;
             if (upd > 0) any_update = 1;
             total += st;
@@ -638,4 +873,22 @@ done:
     free(phi_prev);
     free(B);
     return rc;
+}
+
+int oracle_pqnr_solve(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                      const double* vals, int R, double* lam, double* const* A, int kmax, int lmax,
+                      double tau, double eps, double kappa, double kappa_tol, int* outer_iters,
+                      int64_t* row_steps, int* converged, double* kkt)
+{
+    return rows_solve(ROWS_PQNR, nmodes, dims, nnz, idx, vals, R, lam, A, kmax, lmax, tau, eps, kappa,
+                      kappa_tol, outer_iters, row_steps, converged, kkt);
+}
+
+int oracle_pdnr_solve(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                      const double* vals, int R, double* lam, double* const* A, int kmax, int lmax,
+                      double tau, double eps, double kappa, double kappa_tol, int* outer_iters,
+                      int64_t* row_steps, int* converged, double* kkt)
+{
+    return rows_solve(ROWS_PDNR, nmodes, dims, nnz, idx, vals, R, lam, A, kmax, lmax, tau, eps, kappa,
+                      kappa_tol, outer_iters, row_steps, converged, kkt);
 }

@@ -48,6 +48,23 @@ MUTATIONS = [
      ["pqnr:test_pqnr_objective_decreases_every_step", "pqnr:test_pqnr_converges_faster_than_mu"]),
     ("pqnr-two-loop-sign", "if (fr[r]) q[r] += (a[c] - beta) * P.s[j][r];", "if (fr[r]) q[r] -= (a[c] - beta) * P.s[j][r];",
      ["pqnr:test_pqnr_converges_faster_than_mu", "pqnr:test_pqnr_matches_independent_lbfgsb"]),
+    ("pdnr-hessian-drops-m", "const double w = sc / mm;", "const double w = sc;",
+     ["pdnr:test_pdnr_first_step_is_damped_newton", "pdnr:test_pdnr_converges_in_few_steps"]),
+    ("pdnr-hessian-no-cross-terms", "w * pi[r] * pi[c]", "w * pi[r] * pi[r]",
+     ["pdnr:test_pdnr_first_step_is_damped_newton"]),
+    ("pdnr-damping-unscaled", "trace += H[r * R + r];", "trace += 1.0;",
+     ["pdnr:test_pdnr_first_step_is_damped_newton"]),
+    ("pdnr-pivot-sign", "for (int k = 0; k < c; ++k) piv -= L[c * nf + k] * L[c * nf + k];",
+     "for (int k = 0; k < c; ++k) piv += L[c * nf + k] * L[c * nf + k];",
+     ["pdnr:test_pdnr_first_step_is_damped_newton"]),
+    ("pdnr-backsolve-transposed", "v -= L[k * nf + a] * d[fidx[k]];", "v -= L[a * nf + k] * d[fidx[k]];",
+     ["pdnr:test_pdnr_first_step_is_damped_newton"]),
+    ("pdnr-damping-never-relaxed",
+     "mu = mu / PDNR_MU_STEP > PDNR_MU_MIN ? mu / PDNR_MU_STEP : PDNR_MU_MIN;",
+     "mu = mu * PDNR_MU_STEP < PDNR_MU_MAX ? mu * PDNR_MU_STEP : PDNR_MU_MAX;",
+     ["pdnr:test_pdnr_converges_in_few_steps"]),
+    ("pdnr-held-sign", "if (g[r] > 0.0 && b[r] <= PDNR_HELD) continue;", "if (g[r] < 0.0 && b[r] <= PDNR_HELD) continue;",
+     ["pdnr:test_pdnr_converges_in_few_steps", "pdnr:test_pdnr_kkt_at_convergence"]),
 ]
 
 PARAMS = {
@@ -60,6 +77,10 @@ def _run_pin(name):
     if name.startswith("pqnr:"):
         from tests import test_oracle_pqnr as pq
         getattr(pq, name[5:])(oracle)
+        return
+    if name.startswith("pdnr:"):
+        from tests import test_oracle_pdnr as pd
+        getattr(pd, name[5:])(oracle)
         return
     fn = getattr(pins, name)
     cases = PARAMS.get(name, [()])
