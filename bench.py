@@ -48,6 +48,15 @@ def phi_kernel_bytes(N, R, nnz, segs, mode, word=8):
     return nnz * per_nnz + fac + segs[mode] * R * (8 + 8)
 
 
+def hess_kernel_bytes(N, R, nnz, segs, mode, word=8):
+    """Compulsory HBM bytes of one PDNR Hessian pass for `mode`: the Phi pass's
+    reads, and per nonempty row of this mode one B row read and one row of
+    R*R + R accumulated doubles (Hessian and Phi) written."""
+    per_nnz = 4 * N + 8
+    fac = sum(segs[m] for m in range(N) if m != mode) * R * word
+    return nnz * per_nnz + fac + segs[mode] * (R * 8 + (R * R + R) * 8)
+
+
 def phi_issued_bytes(N, R, nnz, segs, mode, word=8):
     """Bytes the kernel issues with no reuse at all (every gathered factor row
     counted per nonzero): the fused-kernel model of the paper's Section 3.2
@@ -296,8 +305,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--method", choices=["mu", "pqnr"], default="mu",
-                    help="inner solver of the zipf3 / zipf4 jobs: MU (Algorithm 1) or PQNR row solves")
+    ap.add_argument("--method", choices=["mu", "pqnr", "pdnr"], default="mu",
+                    help="inner solver of the zipf3 / zipf4 jobs: MU (Algorithm 1), PQNR or PDNR row solves")
     ap.add_argument("--nnz", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["zipf3", "zipf4", "batch", "serve"], default="zipf3",
@@ -339,9 +348,10 @@ def main():
                                               "5 outer x 10 inner, plan + solve + loglik per step")
     N, R = X.nmodes, M.rank
     prec = cpapr.CPAPR_MIXED if args.precision == "mixed" else cpapr.CPAPR_FP64
-    method = cpapr.CPAPR_METHOD_PQNR if args.method == "pqnr" else cpapr.CPAPR_METHOD_MU
-    if method == cpapr.CPAPR_METHOD_PQNR:
-        wl_desc = wl_desc.replace("cpapr-mu", "cpapr-pqnr")
+    method = {"mu": cpapr.CPAPR_METHOD_MU, "pqnr": cpapr.CPAPR_METHOD_PQNR,
+              "pdnr": cpapr.CPAPR_METHOD_PDNR}[args.method]
+    if method != cpapr.CPAPR_METHOD_MU:
+        wl_desc = wl_desc.replace("cpapr-mu", "cpapr-" + args.method)
     params = cpapr.cpapr_params_default(kmax=sched["kmax"], lmax=sched["lmax"], tol=sched["tau"],
                                         eps=sched["eps"], precision=prec, method=method)
     dev = torch.device("cuda")
@@ -403,13 +413,15 @@ def main():
     med = sorted(ms for _, ms in recs)[len(recs) // 2] if recs else 0.0
     recs = [(m, ms) for m, ms in recs if ms > 0.2 * med]
     word = 4 if prec == cpapr.CPAPR_MIXED else 8
-    tot_bytes = sum(phi_kernel_bytes(N, R, X.nnz, segs, m, word) for m, _ in recs)
+    # the timed launches: Phi (MU, PQNR) or the Hessian pass (PDNR)
+    kbytes = hess_kernel_bytes if method == cpapr.CPAPR_METHOD_PDNR else phi_kernel_bytes
+    tot_bytes = sum(kbytes(N, R, X.nnz, segs, m, word) for m, _ in recs)
     issued = sum(phi_issued_bytes(N, R, X.nnz, segs, m, word) for m, _ in recs)
     tot_ms = sum(ms for _, ms in recs)
     achieved = tot_bytes / (tot_ms / 1000.0) / 1e9
     avg_ms = tot_ms / max(1, len(recs))
     per_mode_ms = [sum(ms for m, ms in recs if m == n) / max(1, sum(1 for m, _ in recs if m == n)) for n in range(N)]
-    traffic_bytes = measured_traffic(wl_name, args.precision)
+    traffic_bytes = measured_traffic(wl_name, args.precision) if method != cpapr.CPAPR_METHOD_PDNR else None
     traffic = None if traffic_bytes is None else traffic_bytes / (avg_ms / 1000.0) / 1e9
     out = {
         "metric": "Phi^(n) nonzeros/s" if args.method == "mu" else "nonzero passes/s (Phi + line search)",
@@ -428,7 +440,8 @@ def main():
                    "tol": sched["tau"], "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
-        "phi_kernel": {"launches": len(recs), "avg_ms": avg_ms, "avg_ms_per_mode": per_mode_ms,
+        "phi_kernel": {"kernel": "pdnr_hess_kernel" if method == cpapr.CPAPR_METHOD_PDNR else "phi_seg_kernel",
+                       "launches": len(recs), "avg_ms": avg_ms, "avg_ms_per_mode": per_mode_ms,
                        "nnz_per_s": X.nnz / (avg_ms / 1000.0),
                        "compulsory_bytes_per_launch": tot_bytes / max(1, len(recs)),
                        "issued_bytes_per_launch": issued / max(1, len(recs)),

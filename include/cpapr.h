@@ -81,8 +81,17 @@ enum { CPAPR_SORT_ROW = 0, CPAPR_SORT_ROW_COL = 1 };
  * rows stop independently
  * when max|min(b, 1 - phi)| < tol. The outer loop, S shift included, is
  * Algorithm 1's. PQNR runs in FP64 only (precision CPAPR_FP64) and needs
- * R <= 256. */
-enum { CPAPR_METHOD_MU = 0, CPAPR_METHOD_PQNR = 1 };
+ * R <= 256.
+ *
+ * PDNR: projected damped Newton solves of the same row subproblems (the
+ * Background's other row-wise variant). Each iteration forms the row's exact
+ * Hessian H = sum_k x_k / max(b . pi_k, eps)^2 pi_k pi_k^T in one pass over the
+ * nonzeros, holds entries with b_r <= 1e-10 and g_r > 0 at the bound, solves
+ * (H_FF + mu t I) d_F = -g_F on the other entries (t = trace(H_FF) / |F|,
+ * Cholesky), and runs the same projected line search; mu starts at 1e-3 and
+ * moves by a factor 4 with the ratio of actual to predicted decrease (within
+ * [1e-8, 1e8]). FP64 only, R <= 64, not with deterministic = 1. */
+enum { CPAPR_METHOD_MU = 0, CPAPR_METHOD_PQNR = 1, CPAPR_METHOD_PDNR = 2 };
 
 /* Sparse count tensor in coordinate format (the paper's I[n][j], X[j]). */
 typedef struct cpapr_coo {
@@ -123,8 +132,8 @@ typedef struct cpapr_stats {
     double loglik;        /* Poisson log-likelihood of the result (solve only) */
     int64_t phi_evals;    /* Phi computations performed (an inner loop stopped by the KKT test
                              computes one Phi more than it updates) */
-    int64_t row_steps;    /* PQNR: steps taken, summed over rows and modes (MU: 0) */
-    int64_t trial_evals;  /* PQNR: line-search passes over the nonzeros (MU: 0) */
+    int64_t row_steps;    /* PQNR / PDNR: steps taken, summed over rows and modes (MU: 0) */
+    int64_t trial_evals;  /* PQNR / PDNR: line-search passes over the nonzeros (MU: 0) */
 } cpapr_stats;
 
 typedef struct cpapr_plan cpapr_plan;
@@ -200,6 +209,16 @@ int cpapr_mu_inner(cpapr_plan* plan, int32_t mode, double* B, const double* cons
  * with method CPAPR_METHOD_PQNR (its workspace holds the row state);
  * otherwise CPAPR_EINVAL. */
 int cpapr_pqnr_inner(cpapr_plan* plan, int32_t mode, double* B, const double* const* A, cpapr_stats* out,
+                     void* stream);
+
+/* PDNR row solves of one mode (see CPAPR_METHOD_PDNR): the same arguments,
+ * results and stream behaviour as cpapr_pqnr_inner; every iteration is one
+ * pass over the nonzeros that forms each active row's Phi row and Hessian (the
+ * phi_evals count) and up to 4 line-search passes. The plan must have been
+ * created with method CPAPR_METHOD_PDNR; otherwise CPAPR_EINVAL. Workspace:
+ * (R*R + 5R) doubles and 7 scalars per row of the largest mode on top of the
+ * MU plan's. */
+int cpapr_pdnr_inner(cpapr_plan* plan, int32_t mode, double* B, const double* const* A, cpapr_stats* out,
                      void* stream);
 
 /* Full CP-APR MU (Algorithm 1) with the plan's parameters.

@@ -28,6 +28,7 @@ CPAPR_SORT_ROW = 0
 CPAPR_SORT_ROW_COL = 1
 CPAPR_METHOD_MU = 0
 CPAPR_METHOD_PQNR = 1
+CPAPR_METHOD_PDNR = 2
 MAX_MODES = 8
 
 
@@ -82,6 +83,7 @@ def load():
         "cpapr_phi": (C.c_int, [vp, i32, vp, P(vp), dbl, vp, vp]),
         "cpapr_mu_inner": (C.c_int, [vp, i32, vp, P(vp), vp, P(cpapr_stats), vp]),
         "cpapr_pqnr_inner": (C.c_int, [vp, i32, vp, P(vp), P(cpapr_stats), vp]),
+        "cpapr_pdnr_inner": (C.c_int, [vp, i32, vp, P(vp), P(cpapr_stats), vp]),
         "cpapr_solve": (C.c_int, [vp, vp, P(vp), P(cpapr_stats), vp]),
         "cpapr_loglik": (C.c_int, [vp, vp, P(vp), dbl, P(dbl), vp]),
         "cpapr_mttkrp": (C.c_int, [vp, i32, P(vp), vp, vp]),
@@ -114,7 +116,8 @@ def load():
 
 
 EXPORTED = ("cpapr_params_default", "cpapr_plan_workspace_size", "cpapr_plan_create", "cpapr_plan_destroy",
-            "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_plan_shape", "cpapr_phi", "cpapr_mu_inner", "cpapr_pqnr_inner", "cpapr_solve", "cpapr_loglik",
+            "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_plan_shape", "cpapr_phi", "cpapr_mu_inner", "cpapr_pqnr_inner",
+            "cpapr_pdnr_inner", "cpapr_solve", "cpapr_loglik",
             "cpapr_mttkrp", "cpapr_batch_workspace_size", "cpapr_batch_tiles", "cpapr_batch_create", "cpapr_batch_create2",
             "cpapr_batch_destroy", "cpapr_batch_set", "cpapr_batch_clear", "cpapr_batch_commit", "cpapr_batch_run",
             "cpapr_batch_mu", "cpapr_batch_inner", "cpapr_batch_status", "cpapr_mode_begin", "cpapr_mode_end", "cpapr_plan_sync_f32",
@@ -215,6 +218,12 @@ def cpapr_mu_inner(h, mode, B, A, Phi_last, stream=None) -> dict:
 def cpapr_pqnr_inner(h, mode, B, A, stream=None) -> dict:
     st = cpapr_stats()
     _check(load().cpapr_pqnr_inner(h, mode, B.data_ptr(), _ptr_array(A), C.byref(st), _stream(stream)))
+    return st.as_dict()
+
+
+def cpapr_pdnr_inner(h, mode, B, A, stream=None) -> dict:
+    st = cpapr_stats()
+    _check(load().cpapr_pdnr_inner(h, mode, B.data_ptr(), _ptr_array(A), C.byref(st), _stream(stream)))
     return st.as_dict()
 
 
@@ -426,6 +435,10 @@ class Plan:
     def pqnr_inner(self, mode, B, A, stream=None):
         """PQNR row solves of one mode (plan created with method=CPAPR_METHOD_PQNR); B in/out."""
         return cpapr_pqnr_inner(self.handle, mode, B, A, stream)
+
+    def pdnr_inner(self, mode, B, A, stream=None):
+        """PDNR row solves of one mode (plan created with method=CPAPR_METHOD_PDNR); B in/out."""
+        return cpapr_pdnr_inner(self.handle, mode, B, A, stream)
 
     def solve(self, lam, A, stream=None):
         return cpapr_solve(self.handle, lam, A, stream)

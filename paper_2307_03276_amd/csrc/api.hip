@@ -73,12 +73,18 @@ Error check_params(const cpapr_params* p, int32_t R, int nmodes)
         return {CPAPR_EUNSUPPORTED, "no Phi kernel for this lane group and rank block at this mode count"};
     if (p->chunk < 0 || p->chunk > 65536) return {CPAPR_EINVAL, "chunk must be in [0, 65536]"};
     if (p->sort != CPAPR_SORT_ROW && p->sort != CPAPR_SORT_ROW_COL) return {CPAPR_EINVAL, "unknown sort"};
-    if (p->method != CPAPR_METHOD_MU && p->method != CPAPR_METHOD_PQNR) return {CPAPR_EINVAL, "unknown method"};
+    if (p->method != CPAPR_METHOD_MU && p->method != CPAPR_METHOD_PQNR && p->method != CPAPR_METHOD_PDNR)
+        return {CPAPR_EINVAL, "unknown method"};
     if (p->deterministic != 0 && p->deterministic != 1) return {CPAPR_EINVAL, "deterministic must be 0 or 1"};
     if (p->deterministic && p->variant == CPAPR_VARIANT_ATOMIC)
         return {CPAPR_EUNSUPPORTED, "the atomic variant is not deterministic"};
     if (p->method == CPAPR_METHOD_PQNR && p->precision != CPAPR_FP64)
         return {CPAPR_EUNSUPPORTED, "PQNR runs in FP64 only"};
+    if (p->method == CPAPR_METHOD_PDNR) {
+        if (p->precision != CPAPR_FP64) return {CPAPR_EUNSUPPORTED, "PDNR runs in FP64 only"};
+        if (R > cpapr::kPdnrMaxRank) return {CPAPR_EUNSUPPORTED, "PDNR supports R <= 64"};
+        if (p->deterministic) return {CPAPR_EUNSUPPORTED, "PDNR's Hessian pass is not deterministic"};
+    }
     return {CPAPR_OK, ""};
 }
 
@@ -90,11 +96,11 @@ struct Layout {
     size_t mode_rows[CPAPR_MAX_MODES], mode_cidx[CPAPR_MAX_MODES], mode_vals[CPAPR_MAX_MODES];
     size_t f32[CPAPR_MAX_MODES];
     size_t region2;
-    size_t B, phi_prev[CPAPR_MAX_MODES], partial, llpart, colsums, state, pqnr, det_part, det_rows;
+    size_t B, phi_prev[CPAPR_MAX_MODES], partial, llpart, colsums, state, pqnr, pdnr, det_part, det_rows;
     size_t total;
 };
 
-Layout layout(int N, int64_t nnz, const int64_t* dims, int R, bool mixed, bool pqnr, bool det)
+Layout layout(int N, int64_t nnz, const int64_t* dims, int R, bool mixed, int method, bool det)
 {
     Layout L{};
     size_t off = 0;
@@ -129,7 +135,9 @@ Layout layout(int N, int64_t nnz, const int64_t* dims, int R, bool mixed, bool p
     L.state = off + s;
     s += align256(sizeof(cpapr::DevState));
     L.pqnr = off + s;
-    if (pqnr) s += cpapr::pqnr_bytes(maxI, R);
+    if (method == CPAPR_METHOD_PQNR) s += cpapr::pqnr_bytes(maxI, R);
+    L.pdnr = off + s;
+    if (method == CPAPR_METHOD_PDNR) s += cpapr::pdnr_bytes(maxI, R);
     const int64_t cap = cpapr::det_tile_capacity(nnz);
     L.det_part = off + s;
     if (det) s += align256((size_t)2 * cap * R * 8);
@@ -273,8 +281,8 @@ int cpapr_plan_workspace_size(const cpapr_coo* X, int32_t R, const cpapr_params*
         e = check_params(p, R, X->nmodes);
         if (e.code) return report(e);
         if (!bytes) return fail(CPAPR_EINVAL, "bytes is NULL");
-        *bytes = layout(X->nmodes, X->nnz, X->dims, R, p->precision == CPAPR_MIXED,
-                        p->method == CPAPR_METHOD_PQNR, p->deterministic != 0).total;
+        *bytes = layout(X->nmodes, X->nnz, X->dims, R, p->precision == CPAPR_MIXED, p->method,
+                        p->deterministic != 0).total;
         return CPAPR_OK;
     } catch (...) {
         return fail(CPAPR_EINVAL, "unexpected exception");
@@ -292,8 +300,7 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
         e = check_params(p, R, X->nmodes);
         if (e.code) return report(e);
         const bool mixed = p->precision == CPAPR_MIXED;
-        const Layout L = layout(X->nmodes, X->nnz, X->dims, R, mixed, p->method == CPAPR_METHOD_PQNR,
-                                p->deterministic != 0);
+        const Layout L = layout(X->nmodes, X->nnz, X->dims, R, mixed, p->method, p->deterministic != 0);
         if (!ws) return fail(CPAPR_EWORKSPACE, "workspace is NULL");
         if (((uintptr_t)ws & 255) != 0) return fail(CPAPR_EWORKSPACE, "workspace must be 256-byte aligned");
         if (ws_bytes < L.total) return fail(CPAPR_EWORKSPACE, "workspace too small");
@@ -325,11 +332,10 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
         P->det_part = p->deterministic ? (double*)(w + L.det_part) : nullptr;
         P->det_rows = p->deterministic ? (int32_t*)(w + L.det_rows) : nullptr;
         P->det_tiles = cpapr::det_tile_capacity(X->nnz);
-        if (p->method == CPAPR_METHOD_PQNR) {
-            int64_t maxI = 0;
-            for (int m = 0; m < P->N; ++m) maxI = std::max(maxI, P->dims[m]);
-            cpapr::pqnr_bind(&P->pq, w + L.pqnr, maxI, R);
-        }
+        int64_t maxI = 0;
+        for (int m = 0; m < P->N; ++m) maxI = std::max(maxI, P->dims[m]);
+        if (p->method == CPAPR_METHOD_PQNR) cpapr::pqnr_bind(&P->pq, w + L.pqnr, maxI, R);
+        if (p->method == CPAPR_METHOD_PDNR) cpapr::pdnr_bind(&P->pd, w + L.pdnr, maxI, R);
 
         hipStream_t s = (hipStream_t)stream;
         e = cpapr::build_sorted(P, X, w + L.region2, s);
@@ -455,13 +461,18 @@ int cpapr_mu_inner(cpapr_plan* plan, int32_t mode, double* B, const double* cons
     }
 }
 
-int cpapr_pqnr_inner(cpapr_plan* plan, int32_t mode, double* B, const double* const* A, cpapr_stats* out,
-                     void* stream)
+namespace {
+
+// Row-solve inner loop of one mode (PQNR or PDNR) behind the two entry points.
+int rows_inner(cpapr_plan* plan, int32_t method, int32_t mode, double* B, const double* const* A,
+               cpapr_stats* out, void* stream)
 {
     try {
         Error e = check_plan_call(plan, mode);
         if (e.code) return report(e);
-        if (plan->params.method != CPAPR_METHOD_PQNR) return fail(CPAPR_EINVAL, "the plan was not created for PQNR");
+        if (plan->params.method != method)
+            return fail(CPAPR_EINVAL, method == CPAPR_METHOD_PQNR ? "the plan was not created for PQNR"
+                                                                  : "the plan was not created for PDNR");
         e = check_factors(plan, A, mode);
         if (e.code) return report(e);
         if (!B) return fail(CPAPR_EINVAL, "B is NULL");
@@ -471,7 +482,8 @@ int cpapr_pqnr_inner(cpapr_plan* plan, int32_t mode, double* B, const double* co
         if (e.code) return report(e);
         e = cpapr::launch_reset_state(plan->state, true, true, s);
         if (e.code) return report(e);
-        e = cpapr::enqueue_pqnr_inner(plan, mode, B, fac, plan->phi_prev[mode], s);
+        e = method == CPAPR_METHOD_PQNR ? cpapr::enqueue_pqnr_inner(plan, mode, B, fac, plan->phi_prev[mode], s)
+                                        : cpapr::enqueue_pdnr_inner(plan, mode, B, fac, plan->phi_prev[mode], s);
         if (e.code) return report(e);
         HostState h{};
         e = read_state(plan, &h, s);
@@ -490,6 +502,20 @@ int cpapr_pqnr_inner(cpapr_plan* plan, int32_t mode, double* B, const double* co
     } catch (...) {
         return fail(CPAPR_EINVAL, "unexpected exception");
     }
+}
+
+}  // namespace
+
+int cpapr_pqnr_inner(cpapr_plan* plan, int32_t mode, double* B, const double* const* A, cpapr_stats* out,
+                     void* stream)
+{
+    return rows_inner(plan, CPAPR_METHOD_PQNR, mode, B, A, out, stream);
+}
+
+int cpapr_pdnr_inner(cpapr_plan* plan, int32_t mode, double* B, const double* const* A, cpapr_stats* out,
+                     void* stream)
+{
+    return rows_inner(plan, CPAPR_METHOD_PDNR, mode, B, A, out, stream);
 }
 
 int cpapr_solve(cpapr_plan* plan, double* lambda, double* const* A, cpapr_stats* out, void* stream)
@@ -522,12 +548,13 @@ int cpapr_solve(cpapr_plan* plan, double* lambda, double* const* A, cpapr_stats*
                 const int64_t In = P->dims[n];
                 e = cpapr::launch_reset_state(P->state, n == 0, false, s);
                 if (e.code) return report(e);
-                const bool pqnr = P->params.method == CPAPR_METHOD_PQNR;
+                const int32_t method = P->params.method;
                 e = cpapr::launch_shift_scale(A[n], P->phi_prev[n], lambda, P->B, In, R, P->params.kappa,
                                               P->params.kappa_tol, k > 1, s);
                 if (e.code) return report(e);
-                e = pqnr ? cpapr::enqueue_pqnr_inner(P, n, P->B, fac, P->phi_prev[n], s)
-                         : enqueue_inner(P, n, P->B, fac, P->phi_prev[n], s);
+                e = method == CPAPR_METHOD_PQNR   ? cpapr::enqueue_pqnr_inner(P, n, P->B, fac, P->phi_prev[n], s)
+                    : method == CPAPR_METHOD_PDNR ? cpapr::enqueue_pdnr_inner(P, n, P->B, fac, P->phi_prev[n], s)
+                                                  : enqueue_inner(P, n, P->B, fac, P->phi_prev[n], s);
                 if (e.code) return report(e);
                 e = cpapr::launch_colsum(P->B, In, R, P->partial, lambda, s);
                 if (e.code) return report(e);

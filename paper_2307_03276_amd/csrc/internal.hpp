@@ -10,7 +10,7 @@
 
 namespace cpapr {
 
-constexpr int kBlock = 256;  // threads per workgroup for every kernel here (4 wave64s)
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64s); the PDNR row kernels use one wave per row
 constexpr int kXcds = 8;     // MI355X: 8 accelerator complex dies, each with its own L2
 
 struct Error {
@@ -35,10 +35,10 @@ struct DevState {
     long long total_updates;                                // MU updates since the last reset
     long long phi_evals;                                    // Phi computations since the last reset
     double ll;                                              // log-likelihood result
-    long long row_steps;                                    // PQNR: steps summed over rows since the last reset
-    long long trial_evals;                                  // PQNR: line-search passes since the last reset
-    int pq_all_done;                                        // PQNR: no row of the current mode is active
-    int pq_idle;                                            // PQNR: no row is in a line search
+    long long row_steps;                                    // row solves: steps summed over rows since the last reset
+    long long trial_evals;                                  // row solves: line-search passes since the last reset
+    int pq_all_done;                                        // row solves: no row of the current mode is active
+    int pq_idle;                                            // row solves: no row is in a line search
 };
 
 // PQNR (projected quasi-Newton row solves): constants shared by every kernel.
@@ -65,6 +65,33 @@ struct PqnrState {
     int32_t* npairs;  // per row: kept pairs
     int32_t* head;    // per row: ring position of the next pair
     int64_t stride;   // rows of every matrix (largest mode)
+};
+
+// PDNR (projected damped Newton row solves): constants shared by every kernel.
+constexpr int kPdnrMaxRank = 64;       // one wave per row: lane r holds row r of the Newton system
+constexpr int kPdnrTrials = 4;         // backtracking trials before the MU step
+constexpr double kPdnrSigma = 1e-4;    // sufficient-decrease constant
+constexpr double kPdnrHeld = 1e-10;    // entries at or below this with g > 0 are held at the bound
+constexpr double kPdnrMu0 = 1e-3;      // damping at the start of an inner loop (times trace(H_FF) / |F|)
+constexpr double kPdnrMuMin = 1e-8;
+constexpr double kPdnrMuMax = 1e8;
+constexpr double kPdnrMuStep = 4.0;    // damping growth / shrink factor
+
+// PDNR state of the mode being solved.
+struct PdnrState {
+    double* HP;         // rows x (R*R + R): Hessian (row-major) then the Phi row, accumulated per pass
+    int64_t hp_stride;  // R*R + R
+    double* G;          // gradient 1 - Phi at the current b
+    double* Dd;         // search direction
+    double* Dt;         // trial step (after a step: the step taken)
+    double* T;          // line-search sums (column 0 of each row)
+    double* mu;         // per row: damping
+    double* alpha;      // per row: current trial length
+    double* gdel;       // per row: g . trial step
+    double* viol;       // per row: last KKT violation
+    int32_t* status;    // per row: 0 active, 1 in a line search, 3 converged
+    int32_t* trials;    // per row: rejected trials in this line search
+    int32_t* steps;     // per row: steps taken
 };
 
 struct PlanMode {
@@ -156,6 +183,7 @@ struct cpapr_plan {
     size_t ws_bytes;
     int group, chunk;                 // resolved launch shape of the Phi kernel
     cpapr::PqnrState pq;              // PQNR row-solve state (method CPAPR_METHOD_PQNR only)
+    cpapr::PdnrState pd;              // PDNR row-solve state (method CPAPR_METHOD_PDNR only)
     double* det_part;                 // deterministic mode: tile-end partial rows (nullptr: atomics)
     int32_t* det_rows;                // deterministic mode: their row ids
     int64_t det_tiles;                // tiles the buffers hold (launches with more tiles are refused)
@@ -225,6 +253,13 @@ void pqnr_bind(PqnrState* q, char* base, int64_t maxI, int R);
 // computed. Leaves per-mode stats in the device state (updates = most steps of
 // a row, row_steps, last_viol[mode]).
 Error enqueue_pqnr_inner(cpapr_plan* P, int mode, double* B, const void* const* fac, double* phi, hipStream_t s);
+
+// ---- PDNR row solves (pdnr.hip) ----
+size_t pdnr_bytes(int64_t maxI, int R);
+void pdnr_bind(PdnrState* d, char* base, int64_t maxI, int R);
+// One PDNR inner loop (lmax iterations) for the rows of `mode`; B in/out,
+// `phi` as for PQNR, the same per-mode stats in the device state.
+Error enqueue_pdnr_inner(cpapr_plan* P, int mode, double* B, const void* const* fac, double* phi, hipStream_t s);
 Error launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 Error launch_reset_state(DevState* st, bool new_sweep, bool all, hipStream_t s);
 Error launch_kkt(const double* B, const double* Phi, int64_t n, DevState* st, int l, hipStream_t s);

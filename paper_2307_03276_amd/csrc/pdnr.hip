@@ -1,0 +1,599 @@
+// PDNR: projected damped Newton solves of the row subproblems of one mode.
+//
+// The second row-wise CP-APR variant of the paper's Background. Every row b of
+// B = A(n) Lambda minimises the same objective as in PQNR,
+//   f_i(b) = sum_r b_r - sum_{k in row i} x_k log(max(b . pi_k, eps)),  b >= 0,
+// with gradient g = 1 - (row i of Phi) and, here, its exact Hessian
+//   H = sum_k x_k / max(m_k, eps)^2  pi_k pi_k^T,   m_k = b . pi_k.
+//
+// One inner iteration for all rows of the mode, with no host round trip:
+//   pdnr_hess_kernel   -> Phi row and H of every active row (one pass over the
+//                         mode-sorted nonzeros; skipped once every row has converged)
+//   pdnr_begin_kernel  -> KKT test, held set, damped Newton direction (Cholesky of
+//                         the free block in LDS, one wave per row), first trial
+//   kPdnrTrials x { line-search pass (the Phi engine's line-search kind),
+//                   pdnr_accept_kernel: accept (damping from the ratio of actual to
+//                   predicted decrease), shorten the step, or take the MU step }
+//
+// Row rules (the oracle documents the same ones): stop when tau > 0 and
+// max|min(b, g)| < tau; entries with g_r > 0 and b_r <= kPdnrHeld are held
+// (d_r = -g_r); on the free set F solve (H_FF + mu t I) d_F = -g_F with
+// t = trace(H_FF) / |F|; the MU direction -b .* g when t is not > 0, a pivot
+// is not > 0 or g.d >= 0; projected backtracking from alpha = 1 with
+// sufficient decrease kPdnrSigma, trials that bring a model value of the row
+// to the floor eps rejected; after kPdnrTrials rejected trials the MU step and
+// mu grows. An accepted step sets rho = actual / predicted decrease of the
+// quadratic model (-(g.delta + delta^T H delta / 2)): rho < 1/4 grows mu,
+// rho > 3/4 shrinks it (factor kPdnrMuStep, within [kPdnrMuMin, kPdnrMuMax]).
+//
+// H and the Phi row live together in one accumulation row of R*R + R doubles
+// per matrix row. The Hessian pass adds into it (plain stores for rows that lie
+// inside one wave's tile, atomics for rows at tile ends); the row kernels clear
+// it once the row's line search is over, so it is zero again for the next pass
+// (and stays zero for converged rows, whose nonzeros the pass skips).
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace cpapr {
+namespace {
+
+enum : int32_t { kActive = 0, kSearching = 1, kConverged = 3 };
+
+constexpr int kHessWaves = kBlock / 64;  // waves per workgroup of the Hessian pass
+constexpr int kHessTile = 512;           // nonzeros per wave
+constexpr int kHessDepth = 4;            // nonzeros whose factor rows are gathered ahead
+
+// Lane `src`'s value of v (src uniform across the wave).
+__device__ __forceinline__ double lane_value(double v, int src)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffu), src);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int W>
+__device__ __forceinline__ double seg_sum(double v)
+{
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return seg_sum<64>(v); }
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct HessArgs {
+    const int32_t* rows;
+    const uint32_t* cofs;
+    const double* vals;
+    const double* fac[kMaxOther];
+    const double* B;
+    const int32_t* status;
+    double* HP;
+    const int* skip;
+    int64_t nnz;
+    int64_t hp_stride;
+    int R;
+    int NM1;
+    double eps;
+};
+
+// H and Phi rows of the active rows. A wave owns kHessTile consecutive
+// nonzeros; lane l serves column s = l % RM of the rank and rows
+// r = (l / RM) * E + e (e < E) of H, so a wave holds a whole RM x RM block.
+// For each nonzero, lanes gather pi_s, the RM-lane segments reduce m = b . pi,
+// and pi goes through LDS to the lanes that need pi_r. NMAX bounds the other
+// modes' count (exact for 1-3 other modes).
+template <int RM, int NMAX>
+__global__ __launch_bounds__(kBlock) void pdnr_hess_kernel(HessArgs a)
+{
+    if (*a.skip) return;
+    constexpr int NQ = 64 / RM;
+    constexpr int E = RM / NQ;
+    __shared__ double spi[kHessWaves][RM];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int s = lane % RM, q = lane / RM;
+    const int64_t p0 = ((int64_t)blockIdx.x * kHessWaves + wv) * kHessTile;
+    const int64_t p1 = min(p0 + kHessTile, a.nnz);
+    if (p0 >= p1) return;  // the whole wave; no workgroup barriers below
+    const int R = a.R;
+    const bool sv = s < R;
+    double h[E];
+    double ph = 0.0, b = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) h[e] = 0.0;
+    int cur = -1, nseg = 0;
+
+    auto flush = [&](bool atomic) {
+        double* base = a.HP + (int64_t)cur * a.hp_stride;
+        if (sv) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int r = q * E + e;
+                if (r < R) {
+                    if (atomic)
+                        unsafeAtomicAdd(base + r * R + s, h[e]);
+                    else
+                        base[r * R + s] = h[e];
+                }
+            }
+            if (q == 0) {
+                if (atomic)
+                    unsafeAtomicAdd(base + R * R + s, ph);
+                else
+                    base[R * R + s] = ph;
+            }
+        }
+    };
+
+    for (int64_t base = p0; base < p1; base += 64) {
+        const int cnt = (int)min((int64_t)64, p1 - base);
+        int myrow = -1;
+        uint32_t myc[NMAX];
+        double myx = 0.0;
+#pragma unroll
+        for (int m = 0; m < NMAX; ++m) myc[m] = 0;
+        if (lane < cnt) {
+            myrow = a.rows[base + lane];
+            if (a.status[myrow] == kConverged) myrow = -1;  // converged rows are skipped
+#pragma unroll
+            for (int m = 0; m < NMAX; ++m)
+                if (m < a.NM1) myc[m] = a.cofs[(int64_t)m * a.nnz + base + lane];
+            myx = a.vals[base + lane];
+        }
+        for (int u0 = 0; u0 < cnt; u0 += kHessDepth) {
+            double fu[kHessDepth][NMAX];
+            int rowu[kHessDepth];
+#pragma unroll
+            for (int k = 0; k < kHessDepth; ++k) {
+                const int u = min(u0 + k, cnt - 1);
+                const int ru = __builtin_amdgcn_readlane(myrow, u);
+                rowu[k] = u0 + k < cnt ? ru : -1;
+#pragma unroll
+                for (int m = 0; m < NMAX; ++m) {
+                    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)myc[m], u);
+                    fu[k][m] = 1.0;
+                    if (m < a.NM1 && rowu[k] >= 0 && sv) fu[k][m] = a.fac[m][(uint64_t)c + s];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kHessDepth; ++k) {
+                const int row = rowu[k];
+                if (row < 0) continue;
+                const double x = lane_value(myx, u0 + k);
+                if (row != cur) {
+                    if (cur >= 0) flush(nseg == 1);
+                    cur = row;
+                    ++nseg;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) h[e] = 0.0;
+                    ph = 0.0;
+                    b = sv ? a.B[(int64_t)row * R + s] : 0.0;
+                }
+                double pi = 0.0;
+                if (sv) {
+                    pi = fu[k][0];
+#pragma unroll
+                    for (int m = 1; m < NMAX; ++m)
+                        if (m < a.NM1) pi *= fu[k][m];
+                }
+                const double mk = seg_sum<RM>(b * pi);
+                const double mm = mk > a.eps ? mk : a.eps;
+                const double sc = x / mm;
+                const double w = sc / mm;
+                ph += sc * pi;
+                if (q == 0) spi[wv][s] = pi;
+                wave_sync();
+                const double wp = w * pi;
+#pragma unroll
+                for (int e = 0; e < E; ++e) h[e] = __builtin_fma(wp, spi[wv][q * E + e], h[e]);
+                wave_sync();
+            }
+        }
+    }
+    if (cur >= 0) flush(true);
+}
+
+struct RowArgs {
+    double* B;
+    double* phi;  // receives the Phi row of every row that is evaluated
+    int64_t rows;
+    int R;
+    double tau;
+    PdnrState d;
+    DevState* st;
+};
+
+__global__ __launch_bounds__(kBlock) void pdnr_reset_kernel(PdnrState d, int64_t rows, DevState* st)
+{
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < rows; i += (int64_t)gridDim.x * kBlock) {
+        d.status[i] = kActive;
+        d.trials[i] = 0;
+        d.steps[i] = 0;
+        d.mu[i] = kPdnrMu0;
+        d.viol[i] = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->pq_all_done = rows == 0 ? 1 : 0;
+        st->pq_idle = 1;
+    }
+}
+
+// Before the rows decide: assume every row done / no row searching; rows that
+// keep working clear the flags. Counts the pass that just ran, if any.
+__global__ void pdnr_flags_kernel(DevState* st, int before_begin)
+{
+    if (threadIdx.x == 0) {
+        if (before_begin) {
+            if (!st->pq_all_done) st->phi_evals += 1;
+            st->pq_all_done = 1;
+        } else {
+            if (!st->pq_idle) st->trial_evals += 1;
+        }
+        st->pq_idle = 1;
+    }
+}
+
+__device__ __forceinline__ void clear_row(double* hp, int64_t n, int lane)
+{
+    for (int64_t e = lane; e < n; e += 64) hp[e] = 0.0;
+}
+
+// Trial step of length alpha along the stored direction; returns g . delta.
+__device__ __forceinline__ double make_trial(const RowArgs& a, int64_t i, int lane, double alpha, double b, double g)
+{
+    double gd = 0.0;
+    if (lane < a.R) {
+        const double nb = b + alpha * a.d.Dd[i * a.R + lane];
+        const double delta = (nb > 0.0 ? nb : 0.0) - b;
+        a.d.Dt[i * a.R + lane] = delta;
+        gd = g * delta;
+    }
+    return wave_sum(gd);
+}
+
+// One wave per row; lane i holds row i of the free-set matrix in registers
+// (RM >= R columns, the unused ones an identity block) and the columns of its
+// Cholesky factor go through LDS.
+template <int RM>
+__global__ __launch_bounds__(64) void pdnr_begin_kernel(RowArgs a)
+{
+    __shared__ double lcol[RM][RM + 1];  // lcol[k][j] = L[j][k]; padded against bank conflicts
+    const int lane = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    if (i >= a.rows || a.d.status[i] == kConverged) return;
+    const int R = a.R;
+    const bool on = lane < R;
+    double* hp = a.d.HP + i * a.d.hp_stride;
+    double b = 0.0, g = 0.0;
+    if (on) {
+        b = a.B[i * R + lane];
+        const double ph = hp[(int64_t)R * R + lane];
+        g = 1.0 - ph;
+        a.phi[i * R + lane] = ph;
+        a.d.G[i * R + lane] = g;
+    }
+    const double viol = wave_max(on ? fabs(b < g ? b : g) : 0.0);
+    if (lane == 0) a.d.viol[i] = viol;
+    if (a.tau > 0.0 && viol < a.tau) {
+        if (lane == 0) a.d.status[i] = kConverged;
+        clear_row(hp, a.d.hp_stride, lane);
+        return;
+    }
+    if (lane == 0) a.st->pq_all_done = 0;
+
+    const bool fre = on && !(g > 0.0 && b <= kPdnrHeld);
+    const unsigned long long fmask = __ballot(fre);
+    const int nf = __popcll(fmask);
+    double d = -g;  // held entries (and every entry when no entry is free)
+    bool newton = nf == 0;
+    if (nf > 0) {
+        const double trace = wave_sum(fre ? hp[(int64_t)lane * R + lane] : 0.0);
+        if (trace > 0.0) {
+            const double damp = a.d.mu[i] * (trace / nf);
+            double M[RM];
+#pragma unroll
+            for (int j = 0; j < RM; ++j) {
+                const bool fj = j < R && ((fmask >> j) & 1ull);
+                M[j] = fre ? (fj ? hp[(int64_t)lane * R + j] : 0.0) + (j == lane ? damp : 0.0) : (j == lane ? 1.0 : 0.0);
+            }
+            // Right-looking Cholesky: at step k lane k's diagonal becomes L[k][k],
+            // lanes below it take L[lane][k] and update their row's later columns.
+            bool ok = true;
+#pragma unroll
+            for (int k = 0; k < RM; ++k) {
+                const double piv = lane_value(M[k], k);
+                if (!(piv > 0.0)) {
+                    ok = false;
+                    break;
+                }
+                const double lkk = sqrt(piv);
+                const double lik = lane == k ? lkk : M[k] / lkk;
+                M[k] = lik;
+                if (lane < RM) lcol[k][lane] = lik;
+                __syncthreads();
+#pragma unroll
+                for (int j = k + 1; j < RM; ++j) M[j] = __builtin_fma(-lik, lcol[k][j], M[j]);
+            }
+            if (ok) {
+                // L y = -g_F (rows of L in registers), then L^T d_F = y (columns from LDS)
+                double z = fre ? -g : 0.0;
+#pragma unroll
+                for (int j = 0; j < RM; ++j) {
+                    const double yj = lane_value(z, j) / lane_value(M[j], j);
+                    if (lane > j)
+                        z = __builtin_fma(-M[j], yj, z);
+                    else if (lane == j)
+                        z = yj;
+                }
+#pragma unroll
+                for (int j = RM - 1; j >= 0; --j) {
+                    const double dj = lane_value(z, j) / lane_value(M[j], j);
+                    if (lane < j)
+                        z = __builtin_fma(-lcol[lane][j], dj, z);
+                    else if (lane == j)
+                        z = dj;
+                }
+                if (fre) d = z;
+                newton = true;
+            }
+        }
+    }
+    if (newton) newton = wave_sum(on ? g * d : 0.0) < 0.0;
+    if (!newton) d = -b * g;
+    if (on) a.d.Dd[i * R + lane] = d;
+    const double gd = make_trial(a, i, lane, 1.0, b, g);
+    if (lane == 0) {
+        a.d.alpha[i] = 1.0;
+        a.d.gdel[i] = gd;
+        a.d.trials[i] = 0;
+        a.d.status[i] = kSearching;
+        a.st->pq_idle = 0;
+    }
+}
+
+// One wave per row: the line-search decision for the current trial.
+__global__ __launch_bounds__(64) void pdnr_accept_kernel(RowArgs a)
+{
+    const int lane = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    if (i >= a.rows || a.d.status[i] != kSearching) return;
+    const int R = a.R;
+    const bool on = lane < R;
+    double b = 0.0, g = 0.0, delta = 0.0;
+    if (on) {
+        b = a.B[i * R + lane];
+        g = a.d.G[i * R + lane];
+        delta = a.d.Dt[i * R + lane];
+    }
+    const double lin = wave_sum(delta);
+    const double gdel = a.d.gdel[i];
+    const double df = lin - a.d.T[i * R];
+    const bool accept = gdel < 0.0 && df <= kPdnrSigma * gdel;
+    const int t = a.d.trials[i] + 1;
+    if (!accept && t < kPdnrTrials) {
+        const double alpha = a.d.alpha[i] * 0.5;
+        const double gd = make_trial(a, i, lane, alpha, b, g);
+        if (lane == 0) {
+            a.d.alpha[i] = alpha;
+            a.d.gdel[i] = gd;
+            a.d.trials[i] = t;
+            a.st->pq_idle = 0;
+        }
+        return;
+    }
+    double* hp = a.d.HP + i * a.d.hp_stride;
+    double mu = a.d.mu[i];
+    if (accept) {
+        // predicted decrease of the quadratic model along the accepted step
+        double hd = 0.0;
+        for (int r = 0; r < R; ++r) {
+            const double dr = lane_value(delta, r);
+            if (on) hd = __builtin_fma(hp[(int64_t)r * R + lane], dr, hd);
+        }
+        const double quad = wave_sum(on ? delta * hd : 0.0);
+        const double pred = -(gdel + 0.5 * quad);
+        const double rho = pred > 0.0 ? -df / pred : 0.0;
+        if (rho < 0.25)
+            mu = fmin(mu * kPdnrMuStep, kPdnrMuMax);
+        else if (rho > 0.75)
+            mu = fmax(mu / kPdnrMuStep, kPdnrMuMin);
+    } else {
+        delta = -b * g;  // the MU step
+        mu = fmin(mu * kPdnrMuStep, kPdnrMuMax);
+    }
+    if (on) {
+        a.B[i * R + lane] = b + delta;
+        a.d.Dt[i * R + lane] = delta;
+    }
+    clear_row(hp, a.d.hp_stride, lane);
+    if (lane == 0) {
+        a.d.mu[i] = mu;
+        a.d.steps[i] += 1;
+        a.d.status[i] = kActive;
+    }
+}
+
+// Per-mode results: most steps of a row, steps summed, largest last violation.
+__global__ __launch_bounds__(kBlock) void pdnr_stats_kernel(PdnrState d, int64_t rows, int mode, DevState* st)
+{
+    __shared__ long long ssum[kBlock / 64];
+    __shared__ int smax[kBlock / 64];
+    __shared__ double svio[kBlock / 64];
+    long long sum = 0;
+    int mx = 0;
+    double vio = 0.0;
+    for (int64_t i = threadIdx.x; i < rows; i += kBlock) {
+        sum += d.steps[i];
+        mx = max(mx, (int)d.steps[i]);
+        vio = fmax(vio, d.viol[i]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sum += __shfl_xor(sum, off);
+        mx = max(mx, __shfl_xor(mx, off));
+        vio = fmax(vio, __shfl_xor(vio, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        ssum[threadIdx.x >> 6] = sum;
+        smax[threadIdx.x >> 6] = mx;
+        svio[threadIdx.x >> 6] = vio;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) {
+            sum += ssum[w];
+            mx = max(mx, smax[w]);
+            vio = fmax(vio, svio[w]);
+        }
+        st->updates = mx;
+        st->sweep_updates += mx;
+        st->total_updates += mx;
+        st->row_steps += sum;
+        st->last_viol[mode] = vio;
+        st->done = st->pq_all_done;
+    }
+}
+
+int rank_tile(int R) { return R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 64; }
+
+template <typename F>
+Error by_tile(int rm, F&& f)
+{
+    switch (rm) {
+        case 8: return f(std::integral_constant<int, 8>{});
+        case 16: return f(std::integral_constant<int, 16>{});
+        case 32: return f(std::integral_constant<int, 32>{});
+        default: return f(std::integral_constant<int, 64>{});
+    }
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+size_t pdnr_bytes(int64_t maxI, int R)
+{
+    const size_t mat = align256((size_t)maxI * R * 8);
+    const size_t hp = align256((size_t)maxI * ((size_t)R * R + R) * 8);
+    return hp + 4 * mat + 4 * align256((size_t)maxI * 8) + 3 * align256((size_t)maxI * 4);
+}
+
+void pdnr_bind(PdnrState* d, char* base, int64_t maxI, int R)
+{
+    const size_t mat = align256((size_t)maxI * R * 8);
+    char* p = base;
+    auto take = [&](size_t n) {
+        char* r = p;
+        p += n;
+        return r;
+    };
+    d->hp_stride = (int64_t)R * R + R;
+    d->HP = (double*)take(align256((size_t)maxI * d->hp_stride * 8));
+    d->G = (double*)take(mat);
+    d->Dd = (double*)take(mat);
+    d->Dt = (double*)take(mat);
+    d->T = (double*)take(mat);
+    d->mu = (double*)take(align256((size_t)maxI * 8));
+    d->alpha = (double*)take(align256((size_t)maxI * 8));
+    d->gdel = (double*)take(align256((size_t)maxI * 8));
+    d->viol = (double*)take(align256((size_t)maxI * 8));
+    d->status = (int32_t*)take(align256((size_t)maxI * 4));
+    d->trials = (int32_t*)take(align256((size_t)maxI * 4));
+    d->steps = (int32_t*)take(align256((size_t)maxI * 4));
+}
+
+Error enqueue_pdnr_inner(cpapr_plan* P, int mode, double* B, const void* const* fac, double* phi, hipStream_t s)
+{
+    const int64_t rows = P->dims[mode];
+    const int R = P->R;
+    if (R > kPdnrMaxRank) return {CPAPR_EUNSUPPORTED, "PDNR supports R <= 64"};
+    if (rows > 0x7fffffff) return {CPAPR_EUNSUPPORTED, "too many rows"};
+    const int64_t n = rows * (int64_t)R;
+    DevState* st = P->state;
+    const int* all_done = &st->pq_all_done;
+    const int* idle = &st->pq_idle;
+    const int rm = rank_tile(R);
+    const dim3 rgrid((unsigned)std::max<int64_t>(rows, 1));
+    const int64_t hwaves = (P->nnz + kHessTile - 1) / kHessTile;
+    const dim3 hgrid((unsigned)std::max<int64_t>((hwaves + kHessWaves - 1) / kHessWaves, 1));
+    if ((hwaves + kHessWaves - 1) / kHessWaves > 0x7fffffff) return {CPAPR_EUNSUPPORTED, "too many nonzeros"};
+
+    HessArgs h{};
+    const PlanMode& pm = P->mode[mode];
+    h.rows = pm.rows;
+    h.cofs = pm.cofs;
+    h.vals = pm.vals;
+    int j = 0;
+    for (int m = 0; m < P->N; ++m)
+        if (m != mode) h.fac[j++] = (const double*)fac[m];
+    h.B = B;
+    h.status = P->pd.status;
+    h.HP = P->pd.HP;
+    h.skip = all_done;
+    h.nnz = P->nnz;
+    h.hp_stride = P->pd.hp_stride;
+    h.R = R;
+    h.NM1 = P->N - 1;
+    h.eps = P->params.eps;
+
+    const int zgrid = (int)std::min<int64_t>(std::max<int64_t>((rows + kBlock - 1) / kBlock, 1), 4096);
+    pdnr_reset_kernel<<<zgrid, kBlock, 0, s>>>(P->pd, rows, st);
+    CPAPR_LAUNCHED();
+    Error e = launch_fill(P->pd.HP, rows * P->pd.hp_stride, 0.0, nullptr, s);
+    if (e.code) return e;
+    RowArgs ra{B, phi, rows, R, P->params.tol, P->pd, st};
+    for (int l = 0; l < P->params.lmax; ++l) {
+        prof_begin(mode, s);
+        e = by_tile(rm, [&](auto RM) -> Error {
+            constexpr int T = decltype(RM)::value;
+            switch (h.NM1) {
+                case 1: pdnr_hess_kernel<T, 1><<<hgrid, kBlock, 0, s>>>(h); break;
+                case 2: pdnr_hess_kernel<T, 2><<<hgrid, kBlock, 0, s>>>(h); break;
+                case 3: pdnr_hess_kernel<T, 3><<<hgrid, kBlock, 0, s>>>(h); break;
+                default: pdnr_hess_kernel<T, kMaxOther><<<hgrid, kBlock, 0, s>>>(h); break;
+            }
+            CPAPR_LAUNCHED();
+            return {CPAPR_OK, ""};
+        });
+        prof_end(s);
+        if (e.code) return e;
+        pdnr_flags_kernel<<<1, 64, 0, s>>>(st, 1);
+        CPAPR_LAUNCHED();
+        e = by_tile(rm, [&](auto RM) -> Error {
+            pdnr_begin_kernel<decltype(RM)::value><<<rgrid, 64, 0, s>>>(ra);
+            CPAPR_LAUNCHED();
+            return {CPAPR_OK, ""};
+        });
+        if (e.code) return e;
+        for (int t = 0; t < kPdnrTrials; ++t) {
+            e = launch_fill(P->pd.T, n, 0.0, idle, s);
+            if (e.code) return e;
+            e = launch_delta(P, mode, B, P->pd.Dt, P->pd.status, fac, P->params.eps, P->pd.T, idle, s);
+            if (e.code) return e;
+            pdnr_flags_kernel<<<1, 64, 0, s>>>(st, 0);
+            CPAPR_LAUNCHED();
+            pdnr_accept_kernel<<<rgrid, 64, 0, s>>>(ra);
+            CPAPR_LAUNCHED();
+        }
+    }
+    pdnr_stats_kernel<<<1, kBlock, 0, s>>>(P->pd, rows, mode, st);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+}  // namespace cpapr

@@ -123,6 +123,30 @@ def test_pqnr_params(lib):
     assert rc == -6
 
 
+def test_pdnr_params(lib):
+    """PDNR needs FP64, R <= 64 and atomics; its workspace holds an R x R
+    Hessian and the Phi row per row of the largest mode (exactly that growth
+    over PQNR's single-matrix buffers, up to alignment)."""
+    dims = [5000, 80, 60]
+    coo = _coo(dims, 10_000)
+    mu = cpapr.cpapr_params_default()
+    pd = cpapr.cpapr_params_default(method=cpapr.CPAPR_METHOD_PDNR)
+    for R in (1, 16, 33, 64):
+        rc, a = _size(coo, R, mu)
+        rc2, b = _size(coo, R, pd)
+        assert rc == 0 and rc2 == 0 and b >= a
+        hess = max(dims) * (R * R + R) * 8
+        if R >= 16:  # below that the plan's sort scratch, shared with this region, dominates
+            assert hess <= b - a <= hess + max(dims) * (4 * R * 8 + 7 * 8) + 16 * 256
+    for bad in (dict(precision=cpapr.CPAPR_MIXED), dict(deterministic=1)):
+        rc, _ = _size(coo, 16, cpapr.cpapr_params_default(method=cpapr.CPAPR_METHOD_PDNR, **bad))
+        assert rc == -6
+    rc, _ = _size(coo, 65, pd)
+    assert rc == -6
+    rc, _ = _size(coo, 16, cpapr.cpapr_params_default(method=3))
+    assert rc == -1
+
+
 def test_plan_create_host_checks(lib):
     p = cpapr.cpapr_params_default()
     coo = _coo([4, 5, 6], 10)
