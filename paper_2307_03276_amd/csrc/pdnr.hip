@@ -42,7 +42,6 @@ enum : int32_t { kActive = 0, kSearching = 1, kConverged = 3 };
 
 constexpr int kHessWaves = kBlock / 64;  // waves per workgroup of the Hessian pass
 constexpr int kHessTile = 512;           // nonzeros per wave
-constexpr int kHessDepth = 4;            // nonzeros whose factor rows are gathered ahead
 
 // Lane `src`'s value of v (src uniform across the wave).
 __device__ __forceinline__ double lane_value(double v, int src)
@@ -53,11 +52,27 @@ __device__ __forceinline__ double lane_value(double v, int src)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u & 0xffffffffu), CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over aligned segments of W lanes, every lane receiving its segment's
+// total (called with the whole wave active). DPP controls: quad_perm [1,0,3,2],
+// quad_perm [2,3,0,1], row_half_mirror, row_mirror; then lane ^ 16, lane ^ 32.
 template <int W>
 __device__ __forceinline__ double seg_sum(double v)
 {
-#pragma unroll
-    for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if constexpr (W >= 2) v += dpp<0xB1>(v);
+    if constexpr (W >= 4) v += dpp<0x4E>(v);
+    if constexpr (W >= 8) v += dpp<0x141>(v);
+    if constexpr (W >= 16) v += dpp<0x140>(v);
+    if constexpr (W >= 32) v += __shfl_xor(v, 16);
+    if constexpr (W >= 64) v += __shfl_xor(v, 32);
     return v;
 }
 
@@ -94,10 +109,12 @@ struct HessArgs {
 };
 
 // H and Phi rows of the active rows. A wave owns kHessTile consecutive
-// nonzeros; lane l serves column s = l % RM of the rank and rows
-// r = (l / RM) * E + e (e < E) of H, so a wave holds a whole RM x RM block.
-// For each nonzero, lanes gather pi_s, the RM-lane segments reduce m = b . pi,
-// and pi goes through LDS to the lanes that need pi_r. NMAX bounds the other
+// nonzeros and takes them NQ = 64 / RM at a time, one per RM-lane segment:
+// lane s of a segment gathers pi_s and b_s of its nonzero, the segment reduces
+// m = b . pi, and every segment forms its nonzero's scale x / m and weight
+// x / m^2. The NQ pi vectors go through LDS; then the whole wave adds the
+// nonzeros' outer products in order, lane l holding column s = l % RM and rows
+// r = (l / RM) * E + e (e < E) of the RM x RM block. NMAX bounds the other
 // modes' count (exact for 1-3 other modes).
 template <int RM, int NMAX>
 __global__ __launch_bounds__(kBlock) void pdnr_hess_kernel(HessArgs a)
@@ -105,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void pdnr_hess_kernel(HessArgs a)
     if (*a.skip) return;
     constexpr int NQ = 64 / RM;
     constexpr int E = RM / NQ;
-    __shared__ double spi[kHessWaves][RM];
+    __shared__ double spi[kHessWaves][NQ][RM];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int s = lane % RM, q = lane / RM;
     const int64_t p0 = ((int64_t)blockIdx.x * kHessWaves + wv) * kHessTile;
@@ -114,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void pdnr_hess_kernel(HessArgs a)
     const int R = a.R;
     const bool sv = s < R;
     double h[E];
-    double ph = 0.0, b = 0.0;
+    double ph = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) h[e] = 0.0;
     int cur = -1, nseg = 0;
@@ -143,67 +160,59 @@ __global__ __launch_bounds__(kBlock) void pdnr_hess_kernel(HessArgs a)
 
     for (int64_t base = p0; base < p1; base += 64) {
         const int cnt = (int)min((int64_t)64, p1 - base);
-        int myrow = -1;
-        uint32_t myc[NMAX];
+        int myrow = -1;  // -1: past the range, or a converged row (skipped)
+        int myc[NMAX];
         double myx = 0.0;
 #pragma unroll
         for (int m = 0; m < NMAX; ++m) myc[m] = 0;
         if (lane < cnt) {
             myrow = a.rows[base + lane];
-            if (a.status[myrow] == kConverged) myrow = -1;  // converged rows are skipped
+            if (a.status[myrow] == kConverged) myrow = -1;
 #pragma unroll
             for (int m = 0; m < NMAX; ++m)
-                if (m < a.NM1) myc[m] = a.cofs[(int64_t)m * a.nnz + base + lane];
+                if (m < a.NM1) myc[m] = (int)a.cofs[(int64_t)m * a.nnz + base + lane];
             myx = a.vals[base + lane];
         }
-        for (int u0 = 0; u0 < cnt; u0 += kHessDepth) {
-            double fu[kHessDepth][NMAX];
-            int rowu[kHessDepth];
+        for (int u0 = 0; u0 < cnt; u0 += NQ) {
+            const int u = u0 + q;  // this segment's nonzero (<= 63: u0 steps by NQ, which divides 64)
+            const int row = __shfl(myrow, u);
+            const double x = __shfl(myx, u);
+            int c[NMAX];
 #pragma unroll
-            for (int k = 0; k < kHessDepth; ++k) {
-                const int u = min(u0 + k, cnt - 1);
-                const int ru = __builtin_amdgcn_readlane(myrow, u);
-                rowu[k] = u0 + k < cnt ? ru : -1;
+            for (int m = 0; m < NMAX; ++m) c[m] = __shfl(myc[m], u);
+            double pi = 0.0, b = 0.0;
+            if (row >= 0 && sv) {
+                b = a.B[(int64_t)row * R + s];
+                pi = a.fac[0][(uint64_t)(uint32_t)c[0] + s];
 #pragma unroll
-                for (int m = 0; m < NMAX; ++m) {
-                    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)myc[m], u);
-                    fu[k][m] = 1.0;
-                    if (m < a.NM1 && rowu[k] >= 0 && sv) fu[k][m] = a.fac[m][(uint64_t)c + s];
-                }
+                for (int m = 1; m < NMAX; ++m)
+                    if (m < a.NM1) pi *= a.fac[m][(uint64_t)(uint32_t)c[m] + s];
             }
+            const double mk = seg_sum<RM>(b * pi);
+            const double mm = mk > a.eps ? mk : a.eps;
+            const double sc = x / mm;
+            const double w = sc / mm;
+            spi[wv][q][s] = pi;
+            wave_sync();
 #pragma unroll
-            for (int k = 0; k < kHessDepth; ++k) {
-                const int row = rowu[k];
-                if (row < 0) continue;
-                const double x = lane_value(myx, u0 + k);
-                if (row != cur) {
+            for (int j = 0; j < NQ; ++j) {
+                const int rj = __builtin_amdgcn_readlane(row, j * RM);
+                if (rj < 0) continue;
+                if (rj != cur) {
                     if (cur >= 0) flush(nseg == 1);
-                    cur = row;
+                    cur = rj;
                     ++nseg;
 #pragma unroll
                     for (int e = 0; e < E; ++e) h[e] = 0.0;
                     ph = 0.0;
-                    b = sv ? a.B[(int64_t)row * R + s] : 0.0;
                 }
-                double pi = 0.0;
-                if (sv) {
-                    pi = fu[k][0];
+                const double ps = spi[wv][j][s];
+                const double wp = lane_value(w, j * RM) * ps;
 #pragma unroll
-                    for (int m = 1; m < NMAX; ++m)
-                        if (m < a.NM1) pi *= fu[k][m];
-                }
-                const double mk = seg_sum<RM>(b * pi);
-                const double mm = mk > a.eps ? mk : a.eps;
-                const double sc = x / mm;
-                const double w = sc / mm;
-                ph += sc * pi;
-                if (q == 0) spi[wv][s] = pi;
-                wave_sync();
-                const double wp = w * pi;
-#pragma unroll
-                for (int e = 0; e < E; ++e) h[e] = __builtin_fma(wp, spi[wv][q * E + e], h[e]);
-                wave_sync();
+                for (int e = 0; e < E; ++e) h[e] = __builtin_fma(wp, spi[wv][j][q * E + e], h[e]);
+                ph = __builtin_fma(lane_value(sc, j * RM), ps, ph);
             }
+            wave_sync();
         }
     }
     if (cur >= 0) flush(true);

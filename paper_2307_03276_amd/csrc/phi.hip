@@ -397,7 +397,9 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (q0 + u < cnt) {
+                // line-search pass: nonzeros of rows not in a line search are
+                // passed over as if absent (no row change, no B load, no flush)
+                if (q0 + u < cnt && (KIND != kDelta || liveu[u])) {
                     const int row = rowu[u];
                     T pi[RPL];
 #pragma unroll
@@ -419,19 +421,15 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
                             for (int c = 0; c < RPL; ++c) b[c] = own[c] ? (T)brow[c] : (T)0;
                         }
                         if constexpr (KIND == kDelta) {
-                            if (liveu[u]) {
-                                const double* drow = a.D + (int64_t)row * R + colbase;
+                            const double* drow = a.D + (int64_t)row * R + colbase;
 #pragma unroll
-                                for (int c = 0; c < RPL; ++c) dv[c] = own[c] ? drow[c] : 0.0;
-                            }
+                            for (int c = 0; c < RPL; ++c) dv[c] = own[c] ? drow[c] : 0.0;
                         }
                     }
                     if constexpr (KIND == kDelta) {
                         static_assert(!MIXED, "the line-search pass is FP64");
-                        if (liveu[u]) {
-                            const double t = delta_term<G, RPL>(b, dv, pi, xu[u], a.eps);
-                            if (lane == 0) acc[0].v += t;
-                        }
+                        const double t = delta_term<G, RPL>(b, dv, pi, xu[u], a.eps);
+                        if (lane == 0) acc[0].v += t;
                     } else {
                         const T s = nonzero_scale<G, RPL, MIXED, KIND, T>(b, pi, xu[u], a.eps);
                         if constexpr (KIND == kLoglik) {
