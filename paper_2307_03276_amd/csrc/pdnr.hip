@@ -276,15 +276,20 @@ __device__ __forceinline__ double make_trial(const RowArgs& a, int64_t i, int la
     return wave_sum(gd);
 }
 
+// Waves per workgroup of the begin kernel (its LDS: RM x (RM + 1) doubles per wave).
+template <int RM>
+constexpr int begin_waves() { return RM == 64 ? 1 : 4; }
+
 // One wave per row; lane i holds row i of the free-set matrix in registers
 // (RM >= R columns, the unused ones an identity block) and the columns of its
-// Cholesky factor go through LDS.
+// Cholesky factor go through the wave's LDS.
 template <int RM>
-__global__ __launch_bounds__(64) void pdnr_begin_kernel(RowArgs a)
+__global__ __launch_bounds__(64 * begin_waves<RM>()) void pdnr_begin_kernel(RowArgs a)
 {
-    __shared__ double lcol[RM][RM + 1];  // lcol[k][j] = L[j][k]; padded against bank conflicts
-    const int lane = threadIdx.x;
-    const int64_t i = blockIdx.x;
+    __shared__ double lcol_all[begin_waves<RM>()][RM][RM + 1];  // lcol[k][j] = L[j][k]; padded against bank conflicts
+    const int lane = threadIdx.x & 63;
+    auto& lcol = lcol_all[threadIdx.x >> 6];
+    const int64_t i = (int64_t)blockIdx.x * begin_waves<RM>() + (threadIdx.x >> 6);
     if (i >= a.rows || a.d.status[i] == kConverged) return;
     const int R = a.R;
     const bool on = lane < R;
@@ -335,7 +340,7 @@ __global__ __launch_bounds__(64) void pdnr_begin_kernel(RowArgs a)
                 const double lik = lane == k ? lkk : M[k] / lkk;
                 M[k] = lik;
                 if (lane < RM) lcol[k][lane] = lik;
-                __syncthreads();
+                wave_sync();
 #pragma unroll
                 for (int j = k + 1; j < RM; ++j) M[j] = __builtin_fma(-lik, lcol[k][j], M[j]);
             }
@@ -377,10 +382,10 @@ __global__ __launch_bounds__(64) void pdnr_begin_kernel(RowArgs a)
 }
 
 // One wave per row: the line-search decision for the current trial.
-__global__ __launch_bounds__(64) void pdnr_accept_kernel(RowArgs a)
+__global__ __launch_bounds__(kBlock) void pdnr_accept_kernel(RowArgs a)
 {
-    const int lane = threadIdx.x;
-    const int64_t i = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (i >= a.rows || a.d.status[i] != kSearching) return;
     const int R = a.R;
     const bool on = lane < R;
@@ -537,7 +542,7 @@ Error enqueue_pdnr_inner(cpapr_plan* P, int mode, double* B, const void* const* 
     const int* all_done = &st->pq_all_done;
     const int* idle = &st->pq_idle;
     const int rm = rank_tile(R);
-    const dim3 rgrid((unsigned)std::max<int64_t>(rows, 1));
+    const dim3 agrid((unsigned)std::max<int64_t>((rows + kBlock / 64 - 1) / (kBlock / 64), 1));
     const int64_t hwaves = (P->nnz + kHessTile - 1) / kHessTile;
     const dim3 hgrid((unsigned)std::max<int64_t>((hwaves + kHessWaves - 1) / kHessWaves, 1));
     if ((hwaves + kHessWaves - 1) / kHessWaves > 0x7fffffff) return {CPAPR_EUNSUPPORTED, "too many nonzeros"};
@@ -584,7 +589,9 @@ Error enqueue_pdnr_inner(cpapr_plan* P, int mode, double* B, const void* const* 
         pdnr_flags_kernel<<<1, 64, 0, s>>>(st, 1);
         CPAPR_LAUNCHED();
         e = by_tile(rm, [&](auto RM) -> Error {
-            pdnr_begin_kernel<decltype(RM)::value><<<rgrid, 64, 0, s>>>(ra);
+            constexpr int W = begin_waves<decltype(RM)::value>();
+            const dim3 bgrid((unsigned)std::max<int64_t>((rows + W - 1) / W, 1));
+            pdnr_begin_kernel<decltype(RM)::value><<<bgrid, 64 * W, 0, s>>>(ra);
             CPAPR_LAUNCHED();
             return {CPAPR_OK, ""};
         });
@@ -596,7 +603,7 @@ Error enqueue_pdnr_inner(cpapr_plan* P, int mode, double* B, const void* const* 
             if (e.code) return e;
             pdnr_flags_kernel<<<1, 64, 0, s>>>(st, 0);
             CPAPR_LAUNCHED();
-            pdnr_accept_kernel<<<rgrid, 64, 0, s>>>(ra);
+            pdnr_accept_kernel<<<agrid, kBlock, 0, s>>>(ra);
             CPAPR_LAUNCHED();
         }
     }

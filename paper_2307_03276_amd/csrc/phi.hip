@@ -186,14 +186,16 @@ constexpr int kLoglik = 2;  // x_k log(max(m_k, eps)) summed per tile (no scatte
 constexpr int kDelta = 3;   // x_k log(max(m_k + dm_k, eps) / max(m_k, eps)) summed per row (column 0)
 
 // The change of the likelihood term of one nonzero along a trial step d of its
-// row, m = b . pi and dm = d . pi: log1p(dm / m) when neither end is at the
+// row, m = b . pi and dm = d . pi: x log1p(dm / m) when neither end is at the
 // floor (accurate for small steps, unlike a difference of two logarithms);
 // -infinity when the step brings m from above eps down to eps or below (the
 // trial leaves the domain of the row objective and must be rejected); from a
 // point already at the floor, the difference of the clamped logarithms.
+// Returns true with the ratio dm / m in *ratio for the common case (the caller
+// batches the logarithms), false with the whole term in *term otherwise.
 template <int G, int RPL>
-__device__ __forceinline__ double delta_term(const double (&b)[RPL], const double (&d)[RPL],
-                                             const double (&pi)[RPL], double x, double eps)
+__device__ __forceinline__ bool delta_ratio(const double (&b)[RPL], const double (&d)[RPL], const double (&pi)[RPL],
+                                            double x, double eps, double* ratio, double* term)
 {
     double m = 0.0, dm = 0.0;
 #pragma unroll
@@ -204,12 +206,12 @@ __device__ __forceinline__ double delta_term(const double (&b)[RPL], const doubl
     m = group_sum<G>(m);
     dm = group_sum<G>(dm);
     const double m1 = m + dm;
-    double t;
-    if (m > eps)
-        t = m1 > eps ? log1p(div_pos(dm, m)) : -__builtin_inf();
-    else
-        t = log(m1 > eps ? m1 : eps) - log(eps);
-    return x * t;
+    if (m > eps && m1 > eps) {
+        *ratio = div_pos(dm, m);
+        return true;
+    }
+    *term = m > eps ? -__builtin_inf() : x * (log(m1 > eps ? m1 : eps) - log(eps));
+    return false;
 }
 
 // One nonzero's dot product and scale: s_k for Phi, x_k for MTTKRP, the
@@ -313,6 +315,11 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
     Acc<MIXED> acc[RPL];
     T b[RPL];
     double dv[RPL];  // the row's trial step (line-search pass)
+    // Line-search pass: the log1p terms of a row are batched over the lane
+    // group, lane j holding the ratio and value of the row's j-th pending
+    // nonzero; one log1p per lane and one group sum then cover G nonzeros.
+    int pend = 0;
+    double pr = 0.0, px = 0.0;
 #pragma unroll
     for (int c = 0; c < RPL; ++c) {
         acc[c].zero();
@@ -333,6 +340,17 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
             for (int c = 0; c < RPL; ++c)
                 if (own[c]) part[e][colbase + c] = acc[c].value();
             if (lane == 0) prow[e] = row;
+        }
+    };
+
+    auto drain = [&]() {
+        if constexpr (KIND == kDelta) {
+            if (pend > 0) {
+                double v = lane < pend ? px * log1p(pr) : 0.0;
+                v = group_sum<G>(v);
+                if (lane == 0) acc[0].v += v;
+                pend = 0;
+            }
         }
     };
 
@@ -409,6 +427,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
                         for (int m = 1; m < NM1; ++m) pi[c] *= fu[u][m][c];
                     }
                     if (row != cur) {
+                        if constexpr (KIND == kDelta) drain();
                         if constexpr (KIND != kLoglik)
                             if (cur >= 0) flush(cur, nseg == 1 ? 0 : 2);
                         cur = row;
@@ -428,8 +447,16 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
                     }
                     if constexpr (KIND == kDelta) {
                         static_assert(!MIXED, "the line-search pass is FP64");
-                        const double t = delta_term<G, RPL>(b, dv, pi, xu[u], a.eps);
-                        if (lane == 0) acc[0].v += t;
+                        double ratio, term;
+                        if (delta_ratio<G, RPL>(b, dv, pi, xu[u], a.eps, &ratio, &term)) {
+                            if (lane == pend) {
+                                pr = ratio;
+                                px = xu[u];
+                            }
+                            if (++pend == G) drain();
+                        } else if (lane == 0) {
+                            acc[0].v += term;
+                        }
                     } else {
                         const T s = nonzero_scale<G, RPL, MIXED, KIND, T>(b, pi, xu[u], a.eps);
                         if constexpr (KIND == kLoglik) {
@@ -456,6 +483,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
         }
         return;
     }
+    if constexpr (KIND == kDelta) drain();
     if (cur >= 0) flush(cur, nseg == 1 ? 0 : 1);
     __syncthreads();
 
