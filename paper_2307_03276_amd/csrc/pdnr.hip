@@ -276,9 +276,10 @@ __device__ __forceinline__ double make_trial(const RowArgs& a, int64_t i, int la
     return wave_sum(gd);
 }
 
-// Waves per workgroup of the begin kernel (its LDS: RM x (RM + 1) doubles per wave).
+// Waves per workgroup of the begin kernel (its LDS: RM x (RM + 1) doubles per
+// wave). One: four per workgroup measured no faster.
 template <int RM>
-constexpr int begin_waves() { return RM == 64 ? 1 : 4; }
+constexpr int begin_waves() { return 1; }
 
 // One wave per row; lane i holds row i of the free-set matrix in registers
 // (RM >= R columns, the unused ones an identity block) and the columns of its
