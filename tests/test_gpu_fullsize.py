@@ -89,3 +89,28 @@ def test_pqnr_inner_fullsize_sampled_rows(big):
         assert_parity(got[i:i + 1], Bo[i:i + 1], 1e-10, f"PQNR row {i}", elementwise=False)
     assert st["inner_iters"] >= ost["n_updates"]
     P.close()
+
+
+def test_pdnr_inner_fullsize_sampled_rows(big):
+    """PDNR row solves of mode 0 at full size (the Hessian pass over 20M
+    nonzeros, rows spanning many ranges); the oracle solves the sampled rows
+    alone. Gate: the damped solve's condition-number bound after four steps
+    at R = 16 (tests/test_gpu_pdnr.py derives it), 1.1e-10."""
+    from tests.test_gpu_pdnr import _lockstep_tol
+    X, M, sched = big
+    lmax = 4
+    P = cpapr.Plan.from_tensor(X, M.rank, method=cpapr.CPAPR_METHOD_PDNR, lmax=lmax, tol=1e-6)
+    A = [dev(a) for a in M.factors]
+    rng = np.random.default_rng(3)
+    n = 0
+    Bh = M.factors[n] * M.lam
+    B = dev(Bh)
+    st = P.pdnr_inner(n, B, A)
+    rows, _ = _sample_rows(X, n, rng, k_random=10)
+    Bo, ost = oracle.pdnr_inner(X, n, Bh, M.factors, lmax=lmax, tau=1e-6, rows=rows)
+    got = host(B)
+    tol = _lockstep_tol(M.rank, lmax)
+    for i in rows:
+        assert_parity(got[i:i + 1], Bo[i:i + 1], tol, f"PDNR row {i}", elementwise=False)
+    assert st["inner_iters"] >= ost["n_updates"]
+    P.close()
