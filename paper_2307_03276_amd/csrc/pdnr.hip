@@ -108,52 +108,74 @@ struct HessArgs {
     double eps;
 };
 
-// H and Phi rows of the active rows. A wave owns kHessTile consecutive
-// nonzeros and takes them NQ = 64 / RM at a time, one per RM-lane segment:
-// lane s of a segment gathers pi_s and b_s of its nonzero, the segment reduces
-// m = b . pi, and every segment forms its nonzero's scale x / m and weight
-// x / m^2. The NQ pi vectors go through LDS; then the whole wave adds the
-// nonzeros' outer products in order, lane l holding column s = l % RM and rows
-// r = (l / RM) * E + e (e < E) of the RM x RM block. NMAX bounds the other
+// v_mfma_f64_16x16x4_f64 computes D = A B + C for A 16 x 4 and B 4 x 16 with one
+// double per lane for A and B and four for C and D: A[i][k] comes from lane
+// i + 16k, B[k][j] from lane j + 16k, and D[i][j] is element i / 4 of lane
+// j + 16 (i % 4) (checked on gfx950 with lane-coded operands).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// H and Phi rows of the active rows: per row, H = sum_k w_k pi_k pi_k^T is a
+// rank-n_i update, which the matrix cores take four nonzeros at a time. A wave
+// owns kHessTile consecutive nonzeros in rounds of four, one per 16-lane slot
+// q: lane s of slot q gathers columns 16t + s (t < NT) of its nonzero's pi and
+// b, the slot reduces m = b . pi, and forms x / m (the Phi scale) and w = x / m^2.
+// Then lane (s, q) holds exactly A[s][q] = w_q pi_q[16ta + s] and B[q][s] =
+// pi_q[16tb + s] of the 16 x 16 block (ta, tb) of H, so one MFMA per block adds
+// the round's four outer products. A round whose nonzeros belong to several
+// rows runs once per row, with the other slots' A set to zero. Phi's row is
+// summed per slot and across the slots at the flush. NMAX bounds the other
 // modes' count (exact for 1-3 other modes).
 template <int RM, int NMAX>
 __global__ __launch_bounds__(kBlock) void pdnr_hess_kernel(HessArgs a)
 {
     if (*a.skip) return;
-    constexpr int NQ = 64 / RM;
-    constexpr int E = RM / NQ;
-    __shared__ double spi[kHessWaves][NQ][RM];
+    constexpr int NT = RM / 16;  // 16-column blocks of the rank
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int s = lane % RM, q = lane / RM;
+    const int s = lane & 15, q = lane >> 4;
     const int64_t p0 = ((int64_t)blockIdx.x * kHessWaves + wv) * kHessTile;
     const int64_t p1 = min(p0 + kHessTile, a.nnz);
     if (p0 >= p1) return;  // the whole wave; no workgroup barriers below
     const int R = a.R;
-    const bool sv = s < R;
-    double h[E];
-    double ph = 0.0;
+    f64x4 acc[NT][NT];
+    double ph[NT];
+    auto zero = [&]() {
 #pragma unroll
-    for (int e = 0; e < E; ++e) h[e] = 0.0;
+        for (int ta = 0; ta < NT; ++ta) {
+            ph[ta] = 0.0;
+#pragma unroll
+            for (int tb = 0; tb < NT; ++tb) acc[ta][tb] = f64x4{0.0, 0.0, 0.0, 0.0};
+        }
+    };
+    zero();
     int cur = -1, nseg = 0;
 
     auto flush = [&](bool atomic) {
         double* base = a.HP + (int64_t)cur * a.hp_stride;
-        if (sv) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int r = q * E + e;
-                if (r < R) {
-                    if (atomic)
-                        unsafeAtomicAdd(base + r * R + s, h[e]);
-                    else
-                        base[r * R + s] = h[e];
+        for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * ta + 4 * v + q, c = 16 * tb + s;
+                    if (r < R && c < R) {
+                        if (atomic)
+                            unsafeAtomicAdd(base + r * R + c, acc[ta][tb][v]);
+                        else
+                            base[r * R + c] = acc[ta][tb][v];
+                    }
                 }
-            }
-            if (q == 0) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            double tot = ph[t];
+            tot += __shfl_xor(tot, 16);
+            tot += __shfl_xor(tot, 32);
+            const int c = 16 * t + s;
+            if (q == 0 && c < R) {
                 if (atomic)
-                    unsafeAtomicAdd(base + R * R + s, ph);
+                    unsafeAtomicAdd(base + R * R + c, tot);
                 else
-                    base[R * R + s] = ph;
+                    base[R * R + c] = tot;
             }
         }
     };
@@ -173,46 +195,63 @@ __global__ __launch_bounds__(kBlock) void pdnr_hess_kernel(HessArgs a)
                 if (m < a.NM1) myc[m] = (int)a.cofs[(int64_t)m * a.nnz + base + lane];
             myx = a.vals[base + lane];
         }
-        for (int u0 = 0; u0 < cnt; u0 += NQ) {
-            const int u = u0 + q;  // this segment's nonzero (<= 63: u0 steps by NQ, which divides 64)
+        for (int u0 = 0; u0 < cnt; u0 += 4) {
+            const int u = u0 + q;  // this slot's nonzero (<= 63: u0 steps by 4)
             const int row = __shfl(myrow, u);
             const double x = __shfl(myx, u);
             int c[NMAX];
 #pragma unroll
             for (int m = 0; m < NMAX; ++m) c[m] = __shfl(myc[m], u);
-            double pi = 0.0, b = 0.0;
-            if (row >= 0 && sv) {
-                b = a.B[(int64_t)row * R + s];
-                pi = a.fac[0][(uint64_t)(uint32_t)c[0] + s];
+            double pi[NT], bv[NT];
 #pragma unroll
-                for (int m = 1; m < NMAX; ++m)
-                    if (m < a.NM1) pi *= a.fac[m][(uint64_t)(uint32_t)c[m] + s];
+            for (int t = 0; t < NT; ++t) {
+                pi[t] = 0.0;
+                bv[t] = 0.0;
+                const int col = 16 * t + s;
+                if (row >= 0 && col < R) {
+                    bv[t] = a.B[(int64_t)row * R + col];
+                    double p = a.fac[0][(uint64_t)(uint32_t)c[0] + col];
+#pragma unroll
+                    for (int m = 1; m < NMAX; ++m)
+                        if (m < a.NM1) p *= a.fac[m][(uint64_t)(uint32_t)c[m] + col];
+                    pi[t] = p;
+                }
             }
-            const double mk = seg_sum<RM>(b * pi);
+            double mk = 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) mk = __builtin_fma(bv[t], pi[t], mk);
+            mk = seg_sum<16>(mk);
             const double mm = mk > a.eps ? mk : a.eps;
             const double sc = x / mm;
             const double w = sc / mm;
-            spi[wv][q][s] = pi;
-            wave_sync();
+            int rk[4];
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) {
-                const int rj = __builtin_amdgcn_readlane(row, j * RM);
-                if (rj < 0) continue;
-                if (rj != cur) {
+            for (int k = 0; k < 4; ++k) rk[k] = __builtin_amdgcn_readlane(row, 16 * k);
+            // runs of equal rows among the four slots, in order
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int r = rk[k];
+                if (r < 0 || (k > 0 && rk[k - 1] == r)) continue;
+                int k2 = k + 1;
+#pragma unroll
+                for (int j = k + 1; j < 4; ++j)
+                    if (k2 == j && rk[j] == r) k2 = j + 1;
+                if (r != cur) {
                     if (cur >= 0) flush(nseg == 1);
-                    cur = rj;
+                    cur = r;
                     ++nseg;
-#pragma unroll
-                    for (int e = 0; e < E; ++e) h[e] = 0.0;
-                    ph = 0.0;
+                    zero();
                 }
-                const double ps = spi[wv][j][s];
-                const double wp = lane_value(w, j * RM) * ps;
+                const bool mine = q >= k && q < k2;
 #pragma unroll
-                for (int e = 0; e < E; ++e) h[e] = __builtin_fma(wp, spi[wv][j][q * E + e], h[e]);
-                ph = __builtin_fma(lane_value(sc, j * RM), ps, ph);
+                for (int ta = 0; ta < NT; ++ta) {
+                    const double av = mine ? w * pi[ta] : 0.0;
+#pragma unroll
+                    for (int tb = 0; tb < NT; ++tb)
+                        acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, pi[tb], acc[ta][tb], 0, 0, 0);
+                    if (mine) ph[ta] = __builtin_fma(sc, pi[ta], ph[ta]);
+                }
             }
-            wave_sync();
         }
     }
     if (cur >= 0) flush(true);
@@ -574,8 +613,8 @@ Error enqueue_pdnr_inner(cpapr_plan* P, int mode, double* B, const void* const* 
     RowArgs ra{B, phi, rows, R, P->params.tol, P->pd, st};
     for (int l = 0; l < P->params.lmax; ++l) {
         prof_begin(mode, s);
-        e = by_tile(rm, [&](auto RM) -> Error {
-            constexpr int T = decltype(RM)::value;
+        e = by_tile(std::max(rm, 16), [&](auto RM) -> Error {
+            constexpr int T = decltype(RM)::value < 16 ? 16 : decltype(RM)::value;
             switch (h.NM1) {
                 case 1: pdnr_hess_kernel<T, 1><<<hgrid, kBlock, 0, s>>>(h); break;
                 case 2: pdnr_hess_kernel<T, 2><<<hgrid, kBlock, 0, s>>>(h); break;
