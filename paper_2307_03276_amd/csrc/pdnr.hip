@@ -126,9 +126,8 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // summed per slot and across the slots at the flush. NMAX bounds the other
 // modes' count (exact for 1-3 other modes).
 template <int RM, int NMAX>
-__global__ __launch_bounds__(kBlock) void pdnr_hess_kernel(HessArgs a)
+__device__ __forceinline__ void hess_tiles(const HessArgs& a)
 {
-    if (*a.skip) return;
     constexpr int NT = RM / 16;  // 16-column blocks of the rank
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int s = lane & 15, q = lane >> 4;
@@ -148,6 +147,10 @@ __global__ __launch_bounds__(kBlock) void pdnr_hess_kernel(HessArgs a)
     };
     zero();
     int cur = -1, nseg = 0;
+    int brow = -1;  // row whose B columns bv holds (a slot's rows repeat across rounds)
+    double bv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bv[t] = 0.0;
 
     auto flush = [&](bool atomic) {
         double* base = a.HP + (int64_t)cur * a.hp_stride;
@@ -202,14 +205,20 @@ __global__ __launch_bounds__(kBlock) void pdnr_hess_kernel(HessArgs a)
             int c[NMAX];
 #pragma unroll
             for (int m = 0; m < NMAX; ++m) c[m] = __shfl(myc[m], u);
-            double pi[NT], bv[NT];
+            double pi[NT];
+            if (row != brow) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const int col = 16 * t + s;
+                    bv[t] = row >= 0 && col < R ? a.B[(int64_t)row * R + col] : 0.0;
+                }
+                brow = row;
+            }
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 pi[t] = 0.0;
-                bv[t] = 0.0;
                 const int col = 16 * t + s;
                 if (row >= 0 && col < R) {
-                    bv[t] = a.B[(int64_t)row * R + col];
                     double p = a.fac[0][(uint64_t)(uint32_t)c[0] + col];
 #pragma unroll
                     for (int m = 1; m < NMAX; ++m)
@@ -255,6 +264,23 @@ __global__ __launch_bounds__(kBlock) void pdnr_hess_kernel(HessArgs a)
         }
     }
     if (cur >= 0) flush(true);
+}
+
+// Up to R = 32 the registers are capped for four waves per SIMD (-15 % at
+// R = 32 against the compiler's three); at R = 64 the accumulators alone take
+// 128 registers, so that kernel is left uncapped.
+template <int RM, int NMAX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void pdnr_hess_kernel(HessArgs a)
+{
+    if (*a.skip) return;
+    hess_tiles<RM, NMAX>(a);
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(kBlock) void pdnr_hess_kernel_r64(HessArgs a)
+{
+    if (*a.skip) return;
+    hess_tiles<64, NMAX>(a);
 }
 
 struct RowArgs {
@@ -615,11 +641,20 @@ Error enqueue_pdnr_inner(cpapr_plan* P, int mode, double* B, const void* const* 
         prof_begin(mode, s);
         e = by_tile(std::max(rm, 16), [&](auto RM) -> Error {
             constexpr int T = decltype(RM)::value < 16 ? 16 : decltype(RM)::value;
-            switch (h.NM1) {
-                case 1: pdnr_hess_kernel<T, 1><<<hgrid, kBlock, 0, s>>>(h); break;
-                case 2: pdnr_hess_kernel<T, 2><<<hgrid, kBlock, 0, s>>>(h); break;
-                case 3: pdnr_hess_kernel<T, 3><<<hgrid, kBlock, 0, s>>>(h); break;
-                default: pdnr_hess_kernel<T, kMaxOther><<<hgrid, kBlock, 0, s>>>(h); break;
+            if constexpr (T == 64) {
+                switch (h.NM1) {
+                    case 1: pdnr_hess_kernel_r64<1><<<hgrid, kBlock, 0, s>>>(h); break;
+                    case 2: pdnr_hess_kernel_r64<2><<<hgrid, kBlock, 0, s>>>(h); break;
+                    case 3: pdnr_hess_kernel_r64<3><<<hgrid, kBlock, 0, s>>>(h); break;
+                    default: pdnr_hess_kernel_r64<kMaxOther><<<hgrid, kBlock, 0, s>>>(h); break;
+                }
+            } else {
+                switch (h.NM1) {
+                    case 1: pdnr_hess_kernel<T, 1><<<hgrid, kBlock, 0, s>>>(h); break;
+                    case 2: pdnr_hess_kernel<T, 2><<<hgrid, kBlock, 0, s>>>(h); break;
+                    case 3: pdnr_hess_kernel<T, 3><<<hgrid, kBlock, 0, s>>>(h); break;
+                    default: pdnr_hess_kernel<T, kMaxOther><<<hgrid, kBlock, 0, s>>>(h); break;
+                }
             }
             CPAPR_LAUNCHED();
             return {CPAPR_OK, ""};
