@@ -201,7 +201,8 @@ int cpapr_mu_inner(cpapr_plan* plan, int32_t mode, double* B, const double* cons
  * iterations for every row of B (device, I_mode x R, in/out, the row
  * subproblems' starting point, e.g. A(mode) Lambda) with the other factors A
  * (device, columns summing to one). Every iteration is one Phi pass for the
- * gradients and up to 4 line-search passes over the nonzeros, all ordered on
+ * gradients and one line-search pass over the nonzeros that evaluates the four
+ * trial steps at once (R < 4: up to four passes, one per trial), all ordered on
  * `stream` with stops decided on the device. out (host, may be NULL):
  * inner_iters = most steps taken by a row, row_steps = steps summed over rows,
  * kkt_violation = largest last violation over rows, converged = every row met
@@ -214,7 +215,7 @@ int cpapr_pqnr_inner(cpapr_plan* plan, int32_t mode, double* B, const double* co
 /* PDNR row solves of one mode (see CPAPR_METHOD_PDNR): the same arguments,
  * results and stream behaviour as cpapr_pqnr_inner; every iteration is one
  * pass over the nonzeros that forms each active row's Phi row and Hessian (the
- * phi_evals count) and up to 4 line-search passes. The plan must have been
+ * phi_evals count) and the same line-search pass(es). The plan must have been
  * created with method CPAPR_METHOD_PDNR; otherwise CPAPR_EINVAL. Workspace:
  * (R*R + 5R) doubles and 7 scalars per row of the largest mode on top of the
  * MU plan's. */

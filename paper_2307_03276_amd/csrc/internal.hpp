@@ -244,6 +244,11 @@ Error launch_fill(double* p, int64_t n, double v, const int* done, hipStream_t s
 // for rows with live[row] == 1 only; skipped when *skip != 0.
 Error launch_delta(const cpapr_plan* P, int mode, const double* B, const double* D, const int32_t* live,
                    const void* const* fac, double eps, double* out, const int* skip, hipStream_t s);
+// The same for the four trial steps max(b + alpha d, 0) - b, alpha = 1, 1/2,
+// 1/4, 1/8, along the directions D, in one pass: trial k's sum in column k of
+// `out`, the other columns 0. Needs R >= 4.
+Error launch_delta4(const cpapr_plan* P, int mode, const double* B, const double* D, const int32_t* live,
+                    const void* const* fac, double eps, double* out, const int* skip, hipStream_t s);
 
 // ---- PQNR row solves (pqnr.hip) ----
 size_t pqnr_bytes(int64_t maxI, int R);

@@ -447,36 +447,14 @@ __global__ __launch_bounds__(64 * begin_waves<RM>()) void pdnr_begin_kernel(RowA
     }
 }
 
-// One wave per row: the line-search decision for the current trial.
-__global__ __launch_bounds__(kBlock) void pdnr_accept_kernel(RowArgs a)
+// End of a row's line search (one wave per row; lane r holds entry r): the
+// accepted step, or the MU step if none was; the damping update from the
+// ratio of actual to predicted decrease; the accumulation row cleared.
+__device__ __forceinline__ void finish_step(const RowArgs& a, int64_t i, int lane, bool accept, double b, double g,
+                                            double delta, double gdel, double df)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (i >= a.rows || a.d.status[i] != kSearching) return;
     const int R = a.R;
     const bool on = lane < R;
-    double b = 0.0, g = 0.0, delta = 0.0;
-    if (on) {
-        b = a.B[i * R + lane];
-        g = a.d.G[i * R + lane];
-        delta = a.d.Dt[i * R + lane];
-    }
-    const double lin = wave_sum(delta);
-    const double gdel = a.d.gdel[i];
-    const double df = lin - a.d.T[i * R];
-    const bool accept = gdel < 0.0 && df <= kPdnrSigma * gdel;
-    const int t = a.d.trials[i] + 1;
-    if (!accept && t < kPdnrTrials) {
-        const double alpha = a.d.alpha[i] * 0.5;
-        const double gd = make_trial(a, i, lane, alpha, b, g);
-        if (lane == 0) {
-            a.d.alpha[i] = alpha;
-            a.d.gdel[i] = gd;
-            a.d.trials[i] = t;
-            a.st->pq_idle = 0;
-        }
-        return;
-    }
     double* hp = a.d.HP + i * a.d.hp_stride;
     double mu = a.d.mu[i];
     if (accept) {
@@ -507,6 +485,78 @@ __global__ __launch_bounds__(kBlock) void pdnr_accept_kernel(RowArgs a)
         a.d.steps[i] += 1;
         a.d.status[i] = kActive;
     }
+}
+
+// One wave per row: the line-search decision for the current trial.
+__global__ __launch_bounds__(kBlock) void pdnr_accept_kernel(RowArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (i >= a.rows || a.d.status[i] != kSearching) return;
+    const int R = a.R;
+    const bool on = lane < R;
+    double b = 0.0, g = 0.0, delta = 0.0;
+    if (on) {
+        b = a.B[i * R + lane];
+        g = a.d.G[i * R + lane];
+        delta = a.d.Dt[i * R + lane];
+    }
+    const double lin = wave_sum(delta);
+    const double gdel = a.d.gdel[i];
+    const double df = lin - a.d.T[i * R];
+    const bool accept = gdel < 0.0 && df <= kPdnrSigma * gdel;
+    const int t = a.d.trials[i] + 1;
+    if (!accept && t < kPdnrTrials) {
+        const double alpha = a.d.alpha[i] * 0.5;
+        const double gd = make_trial(a, i, lane, alpha, b, g);
+        if (lane == 0) {
+            a.d.alpha[i] = alpha;
+            a.d.gdel[i] = gd;
+            a.d.trials[i] = t;
+            a.st->pq_idle = 0;
+        }
+        return;
+    }
+    finish_step(a, i, lane, accept, b, g, delta, gdel, df);
+}
+
+// The same decision for all trials at once (R >= 4): the line-search pass has
+// summed the four trials alpha = 1, 1/2, 1/4, 1/8 into columns 0-3, and the
+// first acceptable one is taken, as the trial-by-trial rounds would.
+__global__ __launch_bounds__(kBlock) void pdnr_accept4_kernel(RowArgs a)
+{
+    static_assert(kPdnrTrials == 4, "the fused line-search pass evaluates four trials");
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (i >= a.rows || a.d.status[i] != kSearching) return;
+    const int R = a.R;
+    const bool on = lane < R;
+    double b = 0.0, g = 0.0, d = 0.0;
+    if (on) {
+        b = a.B[i * R + lane];
+        g = a.d.G[i * R + lane];
+        d = a.d.Dd[i * R + lane];
+    }
+    bool accept = false;
+    double delta = 0.0, gdel = 0.0, df = 0.0;
+    double alpha = 1.0;
+#pragma unroll
+    for (int k = 0; k < kPdnrTrials; ++k, alpha *= 0.5) {
+        double dl = 0.0;
+        if (on) {
+            const double nb = b + alpha * d;
+            dl = (nb > 0.0 ? nb : 0.0) - b;
+        }
+        const double gd = wave_sum(g * dl);
+        const double dfk = wave_sum(dl) - a.d.T[i * R + k];
+        if (!accept && gd < 0.0 && dfk <= kPdnrSigma * gd) {
+            accept = true;
+            delta = dl;
+            gdel = gd;
+            df = dfk;
+        }
+    }
+    finish_step(a, i, lane, accept, b, g, delta, gdel, df);
 }
 
 // Per-mode results: most steps of a row, steps summed, largest last violation.
@@ -671,7 +721,18 @@ Error enqueue_pdnr_inner(cpapr_plan* P, int mode, double* B, const void* const* 
             return {CPAPR_OK, ""};
         });
         if (e.code) return e;
-        for (int t = 0; t < kPdnrTrials; ++t) {
+        if (R >= kPdnrTrials) {  // all trials in one line-search pass
+            e = launch_fill(P->pd.T, n, 0.0, idle, s);
+            if (e.code) return e;
+            e = launch_delta4(P, mode, B, P->pd.Dd, P->pd.status, fac, P->params.eps, P->pd.T, idle, s);
+            if (e.code) return e;
+            pdnr_flags_kernel<<<1, 64, 0, s>>>(st, 0);
+            CPAPR_LAUNCHED();
+            pdnr_accept4_kernel<<<agrid, kBlock, 0, s>>>(ra);
+            CPAPR_LAUNCHED();
+            continue;
+        }
+        for (int t = 0; t < kPdnrTrials; ++t) {  // R < 4: one pass per trial
             e = launch_fill(P->pd.T, n, 0.0, idle, s);
             if (e.code) return e;
             e = launch_delta(P, mode, B, P->pd.Dt, P->pd.status, fac, P->params.eps, P->pd.T, idle, s);

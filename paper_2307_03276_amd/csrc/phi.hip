@@ -184,6 +184,8 @@ constexpr int kPhi = 0;     // s_k = x_k / max(m_k, eps); Phi[i_n] += s_k pi_k
 constexpr int kMttkrp = 1;  // s_k = x_k;                  M[i_n]  += s_k pi_k
 constexpr int kLoglik = 2;  // x_k log(max(m_k, eps)) summed per tile (no scatter)
 constexpr int kDelta = 3;   // x_k log(max(m_k + dm_k, eps) / max(m_k, eps)) summed per row (column 0)
+constexpr int kDelta4 = 4;  // the same for the four trial steps max(b + alpha d, 0) - b, alpha = 1, 1/2, 1/4, 1/8 (columns 0-3)
+constexpr int kTrials4 = 4;
 
 // The change of the likelihood term of one nonzero along a trial step d of its
 // row, m = b . pi and dm = d . pi: x log1p(dm / m) when neither end is at the
@@ -314,18 +316,34 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
     double ll = 0.0;  // likelihood terms of this lane group (Loglik)
     Acc<MIXED> acc[RPL];
     T b[RPL];
-    double dv[RPL];  // the row's trial step (line-search pass)
+    constexpr bool LS = KIND == kDelta || KIND == kDelta4;  // a line-search pass
+    constexpr int NTR = KIND == kDelta4 ? kTrials4 : 1;      // trial steps it evaluates
+    double dv[RPL];  // the row's trial step (kDelta) or search direction (kDelta4)
+    double dk[NTR][RPL];  // kDelta4: the row's trial steps
     // Line-search pass: the log1p terms of a row are batched over the lane
-    // group, lane j holding the ratio and value of the row's j-th pending
-    // nonzero; one log1p per lane and one group sum then cover G nonzeros.
+    // group, lane j holding the ratios and value of the row's j-th pending
+    // nonzero; one log1p per lane and trial and one group sum then cover G
+    // nonzeros.
     int pend = 0;
-    double pr = 0.0, px = 0.0;
+    double pr[NTR], px = 0.0;
+#pragma unroll
+    for (int k = 0; k < NTR; ++k) pr[k] = 0.0;
 #pragma unroll
     for (int c = 0; c < RPL; ++c) {
         acc[c].zero();
         b[c] = (T)0;
         dv[c] = 0.0;
+#pragma unroll
+        for (int k = 0; k < NTR; ++k) dk[k][c] = 0.0;
     }
+    // kDelta4: trial k's sum goes to column k (owned by lane k / RPL; R >= 4)
+    auto add_trial = [&](int k, double v) {
+        if constexpr (KIND == kDelta4) {
+#pragma unroll
+            for (int c = 0; c < RPL; ++c)
+                if (own[c] && colbase + c == k) acc[c].v += v;
+        }
+    };
 
     // Flush kinds: 0 = head partial (LDS), 1 = tail partial (LDS), 2 = owned row (store).
     auto flush = [&](int row, int kind) {
@@ -346,9 +364,18 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
     auto drain = [&]() {
         if constexpr (KIND == kDelta) {
             if (pend > 0) {
-                double v = lane < pend ? px * log1p(pr) : 0.0;
+                double v = lane < pend ? px * log1p(pr[0]) : 0.0;
                 v = group_sum<G>(v);
                 if (lane == 0) acc[0].v += v;
+                pend = 0;
+            }
+        } else if constexpr (KIND == kDelta4) {
+            if (pend > 0) {
+#pragma unroll
+                for (int k = 0; k < NTR; ++k) {
+                    double v = lane < pend ? px * log1p(pr[k]) : 0.0;
+                    add_trial(k, group_sum<G>(v));
+                }
                 pend = 0;
             }
         }
@@ -370,7 +397,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
                 pre[k].row = a.rows[p];
                 // line-search pass: a row not in a line search is staged as ~row
                 // (negative), so the skip costs no load in the gather loop
-                if constexpr (KIND == kDelta)
+                if constexpr (LS)
                     if (a.live[pre[k].row] != 1) pre[k].row = ~pre[k].row;
 #pragma unroll
                 for (int m = 0; m < NM1; ++m) pre[k].c[m] = a.cofs[(int64_t)m * nnz + p];
@@ -400,7 +427,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
                 if (q0 + u < cnt) {
                     const Staged<NM1> e = my[q0 + u];
                     // line-search pass: rows not in a line search contribute nothing
-                    liveu[u] = KIND != kDelta || e.row >= 0;
+                    liveu[u] = !LS || e.row >= 0;
                     rowu[u] = liveu[u] ? e.row : ~e.row;
                     xu[u] = e.x;
                     if (liveu[u]) {
@@ -417,7 +444,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
             for (int u = 0; u < U; ++u) {
                 // line-search pass: nonzeros of rows not in a line search are
                 // passed over as if absent (no row change, no B load, no flush)
-                if (q0 + u < cnt && (KIND != kDelta || liveu[u])) {
+                if (q0 + u < cnt && (!LS || liveu[u])) {
                     const int row = rowu[u];
                     T pi[RPL];
 #pragma unroll
@@ -427,7 +454,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
                         for (int m = 1; m < NM1; ++m) pi[c] *= fu[u][m][c];
                     }
                     if (row != cur) {
-                        if constexpr (KIND == kDelta) drain();
+                        if constexpr (LS) drain();
                         if constexpr (KIND != kLoglik)
                             if (cur >= 0) flush(cur, nseg == 1 ? 0 : 2);
                         cur = row;
@@ -439,10 +466,20 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
 #pragma unroll
                             for (int c = 0; c < RPL; ++c) b[c] = own[c] ? (T)brow[c] : (T)0;
                         }
-                        if constexpr (KIND == kDelta) {
+                        if constexpr (LS) {
                             const double* drow = a.D + (int64_t)row * R + colbase;
 #pragma unroll
                             for (int c = 0; c < RPL; ++c) dv[c] = own[c] ? drow[c] : 0.0;
+                        }
+                        if constexpr (KIND == kDelta4) {
+                            double alpha = 1.0;
+#pragma unroll
+                            for (int k = 0; k < NTR; ++k, alpha *= 0.5)
+#pragma unroll
+                                for (int c = 0; c < RPL; ++c) {
+                                    const double nb = (double)b[c] + alpha * dv[c];
+                                    dk[k][c] = (nb > 0.0 ? nb : 0.0) - (double)b[c];
+                                }
                         }
                     }
                     if constexpr (KIND == kDelta) {
@@ -450,13 +487,45 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
                         double ratio, term;
                         if (delta_ratio<G, RPL>(b, dv, pi, xu[u], a.eps, &ratio, &term)) {
                             if (lane == pend) {
-                                pr = ratio;
+                                pr[0] = ratio;
                                 px = xu[u];
                             }
                             if (++pend == G) drain();
                         } else if (lane == 0) {
                             acc[0].v += term;
                         }
+                    } else if constexpr (KIND == kDelta4) {
+                        static_assert(!MIXED, "the line-search pass is FP64");
+                        // m = b . pi and dm_k = delta_k . pi, then as delta_ratio for each trial
+                        double m = 0.0, dm[NTR];
+#pragma unroll
+                        for (int k = 0; k < NTR; ++k) dm[k] = 0.0;
+#pragma unroll
+                        for (int c = 0; c < RPL; ++c) {
+                            m = __builtin_fma(b[c], pi[c], m);
+#pragma unroll
+                            for (int k = 0; k < NTR; ++k) dm[k] = __builtin_fma(dk[k][c], pi[c], dm[k]);
+                        }
+                        m = group_sum<G>(m);
+                        double ratios[NTR];
+#pragma unroll
+                        for (int k = 0; k < NTR; ++k) {
+                            dm[k] = group_sum<G>(dm[k]);
+                            const double m1 = m + dm[k];
+                            if (m > a.eps && m1 > a.eps) {
+                                ratios[k] = div_pos(dm[k], m);
+                            } else {
+                                ratios[k] = 0.0;  // log1p(0) adds nothing at the drain
+                                add_trial(k, m > a.eps ? -__builtin_inf()
+                                                       : xu[u] * (log(m1 > a.eps ? m1 : a.eps) - log(a.eps)));
+                            }
+                        }
+                        if (lane == pend) {
+#pragma unroll
+                            for (int k = 0; k < NTR; ++k) pr[k] = ratios[k];
+                            px = xu[u];
+                        }
+                        if (++pend == G) drain();
                     } else {
                         const T s = nonzero_scale<G, RPL, MIXED, KIND, T>(b, pi, xu[u], a.eps);
                         if constexpr (KIND == kLoglik) {
@@ -483,7 +552,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
         }
         return;
     }
-    if constexpr (KIND == kDelta) drain();
+    if constexpr (LS) drain();
     if (cur >= 0) flush(cur, nseg == 1 ? 0 : 1);
     __syncthreads();
 
@@ -967,6 +1036,22 @@ Error launch_delta(const cpapr_plan* P, int mode, const double* B, const double*
     Error e = attach_det(P, a);
     if (e.code) return e;
     e = dispatch_seg<false, kDelta>(G, RPL, a, s);
+    if (e.code) return e;
+    return launch_det_fixup(P, mode, a, out, skip, s);
+}
+
+Error launch_delta4(const cpapr_plan* P, int mode, const double* B, const double* D, const int32_t* live,
+                    const void* const* fac, double eps, double* out, const int* skip, hipStream_t s)
+{
+    if (P->R < kTrials4) return {CPAPR_EUNSUPPORTED, "the four-trial line-search pass needs R >= 4"};
+    const int G = P->group;
+    const int RPL = rank_block(P->R, G);
+    PhiArgs a = make_args(P, mode, B, fac, eps, out, skip);
+    a.D = D;
+    a.live = live;
+    Error e = attach_det(P, a);
+    if (e.code) return e;
+    e = dispatch_seg<false, kDelta4>(G, RPL, a, s);
     if (e.code) return e;
     return launch_det_fixup(P, mode, a, out, skip, s);
 }

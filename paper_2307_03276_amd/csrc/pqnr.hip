@@ -331,6 +331,73 @@ __global__ __launch_bounds__(kBlock) void pqnr_accept_kernel(RowArgs a)
     }
 }
 
+// The same decision for all trials at once (R >= 4): the line-search pass has
+// summed the four trials alpha = 1, 1/2, 1/4, 1/8 into columns 0-3, and the
+// first acceptable one is taken, as the trial-by-trial rounds would.
+template <int RG>
+__global__ __launch_bounds__(kBlock) void pqnr_accept4_kernel(RowArgs a)
+{
+    static_assert(kPqnrTrials == 4, "the fused line-search pass evaluates four trials");
+    constexpr int RPB = kBlock / RG;
+    const int lane = threadIdx.x % RG;
+    const int64_t i = (int64_t)blockIdx.x * RPB + threadIdx.x / RG;
+    if (i >= a.rows) return;
+    if (a.q.status[i] != kSearching) return;
+    const int R = a.R;
+    const PqnrState& q = a.q;
+    double b[kCpl], g[kCpl], d[kCpl], step[kCpl];
+#pragma unroll
+    for (int j = 0; j < kCpl; ++j) {
+        const int c = lane + j * RG;
+        b[j] = g[j] = d[j] = step[j] = 0.0;
+        if (c < R) {
+            b[j] = a.B[i * R + c];
+            g[j] = q.G[i * R + c];
+            d[j] = q.Dd[i * R + c];
+        }
+    }
+    bool accept = false;
+    double alpha = 1.0;
+#pragma unroll
+    for (int k = 0; k < kPqnrTrials; ++k, alpha *= 0.5) {
+        double dl[kCpl], gd = 0.0, lin = 0.0;
+#pragma unroll
+        for (int j = 0; j < kCpl; ++j) {
+            const int c = lane + j * RG;
+            dl[j] = 0.0;
+            if (c < R) {
+                const double nb = b[j] + alpha * d[j];
+                dl[j] = (nb > 0.0 ? nb : 0.0) - b[j];
+                gd += g[j] * dl[j];
+                lin += dl[j];
+            }
+        }
+        gd = rg_sum<RG>(gd);
+        lin = rg_sum<RG>(lin);
+        const double df = lin - a.buf[i * R + k];
+        if (!accept && gd < 0.0 && df <= kPqnrSigma * gd) {
+            accept = true;
+#pragma unroll
+            for (int j = 0; j < kCpl; ++j) step[j] = dl[j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kCpl; ++j) {
+        const int c = lane + j * RG;
+        if (c < R) {
+            const double delta = accept ? step[j] : -b[j] * g[j];  // else the MU step
+            a.B[i * R + c] = b[j] + delta;
+            q.Dt[i * R + c] = delta;
+            q.Gp[i * R + c] = g[j];
+        }
+    }
+    if (lane == 0) {
+        q.steps[i] += 1;
+        q.status[i] = kActive;
+        if (!accept) q.npairs[i] = 0;
+    }
+}
+
 // Per-mode results: most steps of a row, steps summed, largest last violation.
 __global__ __launch_bounds__(kBlock) void pqnr_stats_kernel(PqnrState q, int64_t rows, int mode, DevState* st)
 {
@@ -458,7 +525,22 @@ Error enqueue_pqnr_inner(cpapr_plan* P, int mode, double* B, const void* const* 
             return {CPAPR_OK, ""};
         });
         if (e.code) return e;
-        for (int t = 0; t < kPqnrTrials; ++t) {
+        if (R >= kPqnrTrials) {  // all trials in one line-search pass
+            e = launch_fill(P->pq.T, n, 0.0, idle, s);
+            if (e.code) return e;
+            e = launch_delta4(P, mode, B, P->pq.Dd, P->pq.status, fac, P->params.eps, P->pq.T, idle, s);
+            if (e.code) return e;
+            pqnr_flags_kernel<<<1, 64, 0, s>>>(st, 0);
+            CPAPR_LAUNCHED();
+            e = by_group(rg, [&](auto RG) -> Error {
+                pqnr_accept4_kernel<decltype(RG)::value><<<grid, kBlock, 0, s>>>(rt);
+                CPAPR_LAUNCHED();
+                return {CPAPR_OK, ""};
+            });
+            if (e.code) return e;
+            continue;
+        }
+        for (int t = 0; t < kPqnrTrials; ++t) {  // R < 4: one pass per trial
             e = launch_fill(P->pq.T, n, 0.0, idle, s);
             if (e.code) return e;
             e = launch_delta(P, mode, B, P->pq.Dt, P->pq.status, fac, P->params.eps, P->pq.T, idle, s);
