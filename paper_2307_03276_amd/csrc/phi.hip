@@ -371,7 +371,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
             }
         } else if constexpr (KIND == kDelta4) {
             if (pend > 0) {
-#pragma unroll
+#pragma unroll 1  // one log1p body in the code (fewer live registers)
                 for (int k = 0; k < NTR; ++k) {
                     double v = lane < pend ? px * log1p(pr[k]) : 0.0;
                     add_trial(k, group_sum<G>(v));
@@ -608,6 +608,16 @@ __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
     phi_tile<G, RPL, NM1, MIXED, KIND>(a, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 
+// The four-trial line-search pass with its registers capped for four waves per
+// SIMD (the compiler's choice gives three: 139 registers; -5 % per pass).
+template <int G, int RPL, int NM1, bool MIXED, int KIND>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void phi_ls4_kernel(PhiArgs a)
+{
+    __shared__ TileShared<G, RPL, NM1> sh;
+    if (a.done != nullptr && *a.done) return;
+    phi_tile<G, RPL, NM1, MIXED, KIND>(a, xcd_remap(blockIdx.x, gridDim.x), sh);
+}
+
 // Persistent Phi over a batch of operand sets of one shape class. The grid is
 // sized to the device; the tile count and the tile -> slot map are read from
 // device memory (so a captured graph stays valid when the batch changes).
@@ -812,7 +822,10 @@ Error dispatch_seg_n(int G, int RPL, const PhiArgs& a, dim3 grid, hipStream_t s)
 {
 #define CPAPR_SEG_CASE(GG, RR)                                                        \
     if (G == GG && RPL == RR) {                                                       \
-        phi_seg_kernel<GG, RR, NM1, MIXED, KIND><<<grid, kBlock, 0, s>>>(a);          \
+        if constexpr (KIND == kDelta4)                                                \
+            phi_ls4_kernel<GG, RR, NM1, MIXED, KIND><<<grid, kBlock, 0, s>>>(a);      \
+        else                                                                          \
+            phi_seg_kernel<GG, RR, NM1, MIXED, KIND><<<grid, kBlock, 0, s>>>(a);      \
         CPAPR_LAUNCHED();                                                             \
         return {CPAPR_OK, ""};                                                        \
     }
