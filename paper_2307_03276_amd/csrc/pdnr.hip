@@ -7,13 +7,17 @@
 //   H = sum_k x_k / max(m_k, eps)^2  pi_k pi_k^T,   m_k = b . pi_k.
 //
 // One inner iteration for all rows of the mode, with no host round trip:
-//   pdnr_hess_kernel   -> Phi row and H of every active row (one pass over the
-//                         mode-sorted nonzeros; skipped once every row has converged)
-//   pdnr_begin_kernel  -> KKT test, held set, damped Newton direction (Cholesky of
-//                         the free block in LDS, one wave per row), first trial
-//   kPdnrTrials x { line-search pass (the Phi engine's line-search kind),
-//                   pdnr_accept_kernel: accept (damping from the ratio of actual to
-//                   predicted decrease), shorten the step, or take the MU step }
+//   pdnr_hess_kernel    -> Phi row and H of every active row (one pass over the
+//                          mode-sorted nonzeros on the matrix cores; skipped once
+//                          every row has converged)
+//   pdnr_begin_kernel   -> KKT test, held set, damped Newton direction (Cholesky of
+//                          the free block, one wave per row), first trial
+//   line-search pass    -> the Phi engine's four-trial kind: f(b + delta) - f(b)
+//                          for alpha = 1, 1/2, 1/4, 1/8 at once
+//   pdnr_accept4_kernel -> the first acceptable trial (damping from the ratio of
+//                          actual to predicted decrease) or the MU step
+// (R < 4: kPdnrTrials rounds of a one-trial pass and pdnr_accept_kernel, which
+// accepts, shortens the step or takes the MU step.)
 //
 // Row rules (the oracle documents the same ones): stop when tau > 0 and
 // max|min(b, g)| < tau; entries with g_r > 0 and b_r <= kPdnrHeld are held
@@ -28,7 +32,7 @@
 //
 // H and the Phi row live together in one accumulation row of R*R + R doubles
 // per matrix row. The Hessian pass adds into it (plain stores for rows that lie
-// inside one wave's tile, atomics for rows at tile ends); the row kernels clear
+// inside one wave's range, atomics for rows at range ends); the row kernels clear
 // it once the row's line search is over, so it is zero again for the next pass
 // (and stays zero for converged rows, whose nonzeros the pass skips).
 #include <algorithm>
@@ -447,6 +451,113 @@ __global__ __launch_bounds__(64 * begin_waves<RM>()) void pdnr_begin_kernel(RowA
     }
 }
 
+// max over aligned 16-lane segments (whole wave active)
+__device__ __forceinline__ double seg16_max(double v)
+{
+    v = fmax(v, dpp<0xB1>(v));
+    v = fmax(v, dpp<0x4E>(v));
+    v = fmax(v, dpp<0x141>(v));
+    return fmax(v, dpp<0x140>(v));
+}
+
+// R <= 16: four rows per wave, one per 16-lane segment, with the same steps
+// as pdnr_begin_kernel (lane s of a segment holds row s of its row's system).
+// Segments stay in step: a segment that has nothing left to do keeps
+// computing on neutral values and discards the result, so every shuffle and
+// segment reduction runs with the whole wave active.
+__global__ __launch_bounds__(64) void pdnr_begin16_kernel(RowArgs a)
+{
+    constexpr int RM = 16;
+    __shared__ double lcol_all[4][RM][RM + 1];  // per segment: lcol[k][j] = L[j][k]
+    const int lane = threadIdx.x;
+    const int q = lane >> 4, s = lane & 15, sb = lane & ~15;
+    auto& lcol = lcol_all[q];
+    const int64_t i = (int64_t)blockIdx.x * 4 + q;
+    const int R = a.R;
+    bool live = i < a.rows && a.d.status[i] != kConverged;
+    const bool on = live && s < R;
+    double* hp = a.d.HP + (live ? i : 0) * a.d.hp_stride;
+    double b = 0.0, g = 0.0;
+    if (on) {
+        b = a.B[i * R + s];
+        const double ph = hp[(int64_t)R * R + s];
+        g = 1.0 - ph;
+        a.phi[i * R + s] = ph;
+        a.d.G[i * R + s] = g;
+    }
+    const double viol = seg16_max(on ? fabs(b < g ? b : g) : 0.0);
+    if (live && s == 0) a.d.viol[i] = viol;
+    if (live && a.tau > 0.0 && viol < a.tau) {
+        if (s == 0) a.d.status[i] = kConverged;
+        for (int64_t e = s; e < a.d.hp_stride; e += 16) hp[e] = 0.0;
+        live = false;
+    }
+    if (live && s == 0) a.st->pq_all_done = 0;
+
+    const bool fre = live && s < R && !(g > 0.0 && b <= kPdnrHeld);
+    const unsigned fmask = (unsigned)((__ballot(fre) >> sb) & 0xFFFFull);
+    const int nf = __popc(fmask);
+    const double trace = seg_sum<16>(fre ? hp[(int64_t)s * R + s] : 0.0);
+    const bool chol = live && nf > 0 && trace > 0.0;
+    const double damp = chol ? a.d.mu[i] * (trace / nf) : 0.0;
+    double M[RM];
+#pragma unroll
+    for (int j = 0; j < RM; ++j) {
+        const bool fj = j < R && ((fmask >> j) & 1u);
+        M[j] = fre ? (fj ? hp[(int64_t)s * R + j] : 0.0) + (j == s ? damp : 0.0) : (j == s ? 1.0 : 0.0);
+    }
+    bool ok = chol;
+#pragma unroll
+    for (int k = 0; k < RM; ++k) {
+        const double piv = __shfl(M[k], sb + k);
+        ok = ok && piv > 0.0;
+        const double lkk = sqrt(piv > 0.0 ? piv : 1.0);
+        const double lik = s == k ? lkk : M[k] / lkk;
+        M[k] = lik;
+        lcol[k][s] = lik;
+        wave_sync();
+#pragma unroll
+        for (int j = k + 1; j < RM; ++j) M[j] = __builtin_fma(-lik, lcol[k][j], M[j]);
+    }
+    double z = fre ? -g : 0.0;
+#pragma unroll
+    for (int j = 0; j < RM; ++j) {
+        const double yj = __shfl(z, sb + j) / __shfl(M[j], sb + j);
+        if (s > j)
+            z = __builtin_fma(-M[j], yj, z);
+        else if (s == j)
+            z = yj;
+    }
+#pragma unroll
+    for (int j = RM - 1; j >= 0; --j) {
+        const double dj = __shfl(z, sb + j) / __shfl(M[j], sb + j);
+        if (s < j)
+            z = __builtin_fma(-lcol[s][j], dj, z);
+        else if (s == j)
+            z = dj;
+    }
+    double d = -g;  // held entries (and every entry when no entry is free)
+    if (ok && fre) d = z;
+    const bool newton0 = live && (nf == 0 || ok);
+    const bool newton = newton0 && seg_sum<16>(on ? g * d : 0.0) < 0.0;
+    if (!newton) d = -b * g;
+    double delta = 0.0;
+    if (on) {
+        a.d.Dd[i * R + s] = d;
+        const double nb = b + d;
+        delta = (nb > 0.0 ? nb : 0.0) - b;
+        a.d.Dt[i * R + s] = delta;
+    }
+    const double gd = seg_sum<16>(g * delta);
+    if (live && s == 0) {
+        a.d.alpha[i] = 1.0;
+        a.d.gdel[i] = gd;
+        a.d.trials[i] = 0;
+        a.d.status[i] = kSearching;
+        a.st->pq_idle = 0;
+    }
+}
+
 // End of a row's line search (one wave per row; lane r holds entry r): the
 // accepted step, or the MU step if none was; the damping update from the
 // ratio of actual to predicted decrease; the accumulation row cleared.
@@ -713,13 +824,18 @@ Error enqueue_pdnr_inner(cpapr_plan* P, int mode, double* B, const void* const* 
         if (e.code) return e;
         pdnr_flags_kernel<<<1, 64, 0, s>>>(st, 1);
         CPAPR_LAUNCHED();
-        e = by_tile(rm, [&](auto RM) -> Error {
-            constexpr int W = begin_waves<decltype(RM)::value>();
-            const dim3 bgrid((unsigned)std::max<int64_t>((rows + W - 1) / W, 1));
-            pdnr_begin_kernel<decltype(RM)::value><<<bgrid, 64 * W, 0, s>>>(ra);
+        if (rm <= 16) {
+            pdnr_begin16_kernel<<<dim3((unsigned)std::max<int64_t>((rows + 3) / 4, 1)), 64, 0, s>>>(ra);
             CPAPR_LAUNCHED();
-            return {CPAPR_OK, ""};
-        });
+        } else {
+            e = by_tile(rm, [&](auto RM) -> Error {
+                constexpr int W = begin_waves<decltype(RM)::value>();
+                const dim3 bgrid((unsigned)std::max<int64_t>((rows + W - 1) / W, 1));
+                pdnr_begin_kernel<decltype(RM)::value><<<bgrid, 64 * W, 0, s>>>(ra);
+                CPAPR_LAUNCHED();
+                return {CPAPR_OK, ""};
+            });
+        }
         if (e.code) return e;
         if (R >= kPdnrTrials) {  // all trials in one line-search pass
             e = launch_fill(P->pd.T, n, 0.0, idle, s);
