@@ -558,24 +558,37 @@ __global__ __launch_bounds__(64) void pdnr_begin16_kernel(RowArgs a)
     }
 }
 
-// End of a row's line search (one wave per row; lane r holds entry r): the
-// accepted step, or the MU step if none was; the damping update from the
-// ratio of actual to predicted decrease; the accumulation row cleared.
-__device__ __forceinline__ void finish_step(const RowArgs& a, int64_t i, int lane, bool accept, double b, double g,
-                                            double delta, double gdel, double df)
+// Value of lane src of v's SEG-lane segment (sb: the segment's first lane; the
+// whole wave active).
+template <int SEG>
+__device__ __forceinline__ double seg_value(double v, int sb, int src)
+{
+    if constexpr (SEG == 64)
+        return lane_value(v, src);
+    else
+        return __shfl(v, sb + src);
+}
+
+// End of a row's line search (lane s of the row's SEG-lane segment holds entry
+// s; `live`: the segment has a row that searched): the accepted step, or the
+// MU step if none was; the damping update from the ratio of actual to
+// predicted decrease; the accumulation row cleared.
+template <int SEG>
+__device__ __forceinline__ void finish_step(const RowArgs& a, int64_t i, int s, int sb, bool live, bool accept,
+                                            double b, double g, double delta, double gdel, double df)
 {
     const int R = a.R;
-    const bool on = lane < R;
-    double* hp = a.d.HP + i * a.d.hp_stride;
-    double mu = a.d.mu[i];
+    const bool on = live && s < R;
+    double* hp = a.d.HP + (live ? i : 0) * a.d.hp_stride;
+    double mu = live ? a.d.mu[i] : 0.0;
+    // predicted decrease of the quadratic model along the step (used if accepted)
+    double hd = 0.0;
+    for (int r = 0; r < R; ++r) {
+        const double dr = seg_value<SEG>(delta, sb, r);
+        if (on) hd = __builtin_fma(hp[(int64_t)r * R + s], dr, hd);
+    }
+    const double quad = seg_sum<SEG>(on ? delta * hd : 0.0);
     if (accept) {
-        // predicted decrease of the quadratic model along the accepted step
-        double hd = 0.0;
-        for (int r = 0; r < R; ++r) {
-            const double dr = lane_value(delta, r);
-            if (on) hd = __builtin_fma(hp[(int64_t)r * R + lane], dr, hd);
-        }
-        const double quad = wave_sum(on ? delta * hd : 0.0);
         const double pred = -(gdel + 0.5 * quad);
         const double rho = pred > 0.0 ? -df / pred : 0.0;
         if (rho < 0.25)
@@ -587,14 +600,16 @@ __device__ __forceinline__ void finish_step(const RowArgs& a, int64_t i, int lan
         mu = fmin(mu * kPdnrMuStep, kPdnrMuMax);
     }
     if (on) {
-        a.B[i * R + lane] = b + delta;
-        a.d.Dt[i * R + lane] = delta;
+        a.B[i * R + s] = b + delta;
+        a.d.Dt[i * R + s] = delta;
     }
-    clear_row(hp, a.d.hp_stride, lane);
-    if (lane == 0) {
-        a.d.mu[i] = mu;
-        a.d.steps[i] += 1;
-        a.d.status[i] = kActive;
+    if (live) {
+        for (int64_t e = s; e < a.d.hp_stride; e += SEG) hp[e] = 0.0;
+        if (s == 0) {
+            a.d.mu[i] = mu;
+            a.d.steps[i] += 1;
+            a.d.status[i] = kActive;
+        }
     }
 }
 
@@ -628,25 +643,30 @@ __global__ __launch_bounds__(kBlock) void pdnr_accept_kernel(RowArgs a)
         }
         return;
     }
-    finish_step(a, i, lane, accept, b, g, delta, gdel, df);
+    finish_step<64>(a, i, lane, 0, true, accept, b, g, delta, gdel, df);
 }
 
 // The same decision for all trials at once (R >= 4): the line-search pass has
 // summed the four trials alpha = 1, 1/2, 1/4, 1/8 into columns 0-3, and the
-// first acceptable one is taken, as the trial-by-trial rounds would.
-__global__ __launch_bounds__(kBlock) void pdnr_accept4_kernel(RowArgs a)
+// first acceptable one is taken, as the trial-by-trial rounds would. A row per
+// SEG-lane segment: SEG = 64 with four waves per workgroup, or SEG = 16 (R <= 16)
+// with four rows per wave.
+template <int SEG>
+__global__ __launch_bounds__(SEG == 64 ? kBlock : 64) void pdnr_accept4_kernel(RowArgs a)
 {
     static_assert(kPdnrTrials == 4, "the fused line-search pass evaluates four trials");
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (i >= a.rows || a.d.status[i] != kSearching) return;
+    const int s = lane & (SEG - 1), sb = lane & ~(SEG - 1);
+    const int64_t i = (int64_t)blockIdx.x * 4 + (SEG == 64 ? (threadIdx.x >> 6) : (lane >> 4));
+    const bool live = i < a.rows && a.d.status[i] == kSearching;
+    if (SEG == 64 && !live) return;  // a whole wave
     const int R = a.R;
-    const bool on = lane < R;
+    const bool on = live && s < R;
     double b = 0.0, g = 0.0, d = 0.0;
     if (on) {
-        b = a.B[i * R + lane];
-        g = a.d.G[i * R + lane];
-        d = a.d.Dd[i * R + lane];
+        b = a.B[i * R + s];
+        g = a.d.G[i * R + s];
+        d = a.d.Dd[i * R + s];
     }
     bool accept = false;
     double delta = 0.0, gdel = 0.0, df = 0.0;
@@ -658,16 +678,16 @@ __global__ __launch_bounds__(kBlock) void pdnr_accept4_kernel(RowArgs a)
             const double nb = b + alpha * d;
             dl = (nb > 0.0 ? nb : 0.0) - b;
         }
-        const double gd = wave_sum(g * dl);
-        const double dfk = wave_sum(dl) - a.d.T[i * R + k];
-        if (!accept && gd < 0.0 && dfk <= kPdnrSigma * gd) {
+        const double gd = seg_sum<SEG>(g * dl);
+        const double dfk = seg_sum<SEG>(dl) - (live ? a.d.T[i * R + k] : 0.0);
+        if (live && !accept && gd < 0.0 && dfk <= kPdnrSigma * gd) {
             accept = true;
             delta = dl;
             gdel = gd;
             df = dfk;
         }
     }
-    finish_step(a, i, lane, accept, b, g, delta, gdel, df);
+    finish_step<SEG>(a, i, s, sb, live, accept, b, g, delta, gdel, df);
 }
 
 // Per-mode results: most steps of a row, steps summed, largest last violation.
@@ -844,7 +864,10 @@ Error enqueue_pdnr_inner(cpapr_plan* P, int mode, double* B, const void* const* 
             if (e.code) return e;
             pdnr_flags_kernel<<<1, 64, 0, s>>>(st, 0);
             CPAPR_LAUNCHED();
-            pdnr_accept4_kernel<<<agrid, kBlock, 0, s>>>(ra);
+            if (R <= 16)
+                pdnr_accept4_kernel<16><<<dim3((unsigned)std::max<int64_t>((rows + 3) / 4, 1)), 64, 0, s>>>(ra);
+            else
+                pdnr_accept4_kernel<64><<<agrid, kBlock, 0, s>>>(ra);
             CPAPR_LAUNCHED();
             continue;
         }
