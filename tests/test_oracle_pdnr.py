@@ -49,6 +49,20 @@ def test_pdnr_kkt_at_convergence(oracle_lib):
         np.testing.assert_allclose(st["phi_last"], 1.0 - G, rtol=0, atol=1e-9)
 
 
+@pytest.mark.parametrize("dims,R,nnz", [((12, 10, 8, 6), 5, 1500), ((7, 6, 5, 4, 3), 3, 600)])
+def test_pdnr_kkt_at_convergence_more_modes(oracle_lib, dims, R, nnz):
+    """Four and five modes (pi from three and four other factors)."""
+    X = synth.random_tensor(21, dims, nnz)
+    M = synth.random_model(21, dims, R)
+    for n in range(len(dims)):
+        B0 = M.factors[n] * M.lam
+        Bd, st = oracle_lib.pdnr_inner(X, n, B0, M.factors, lmax=200, tau=1e-10)
+        assert np.all(Bd >= 0)
+        G = 1.0 - dense_ref.phi_dense(X, n, Bd, M.factors, 1e-10)
+        assert np.max(np.abs(np.minimum(Bd, G))) < 1e-10, n
+        assert np.all(G > -1e-10)
+
+
 def test_pdnr_rank_one_closed_form(oracle_lib):
     """R = 1: the row optimum is the row's total count (normalised factors)."""
     X = synth.random_tensor(5, (7, 6, 5), 120)
