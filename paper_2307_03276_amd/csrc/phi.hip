@@ -609,7 +609,10 @@ __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
 }
 
 // The four-trial line-search pass with its registers capped for four waves per
-// SIMD (the compiler's choice gives three: 139 registers; -5 % per pass).
+// SIMD, used for up to two rank columns per lane (at 8 lanes x 2 columns the
+// compiler's choice gives three waves with 139 registers; capped, -5 % per
+// pass). With four columns per lane the cap spills 130-220 bytes per lane and
+// costs 1.6x, so those shapes keep the plain kernel.
 template <int G, int RPL, int NM1, bool MIXED, int KIND>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void phi_ls4_kernel(PhiArgs a)
 {
@@ -822,7 +825,7 @@ Error dispatch_seg_n(int G, int RPL, const PhiArgs& a, dim3 grid, hipStream_t s)
 {
 #define CPAPR_SEG_CASE(GG, RR)                                                        \
     if (G == GG && RPL == RR) {                                                       \
-        if constexpr (KIND == kDelta4)                                                \
+        if constexpr (KIND == kDelta4 && RR <= 2)                                     \
             phi_ls4_kernel<GG, RR, NM1, MIXED, KIND><<<grid, kBlock, 0, s>>>(a);      \
         else                                                                          \
             phi_seg_kernel<GG, RR, NM1, MIXED, KIND><<<grid, kBlock, 0, s>>>(a);      \
