@@ -996,10 +996,11 @@ int model_chunk(const cpapr_plan* P, int group)
 }
 
 // Deterministic mode: attach the plan's tile-end buffers to a single-plan launch.
-Error attach_det(const cpapr_plan* P, PhiArgs& a)
+// G: lanes per nonzero of the launch (the plan's unless a pass picks its own).
+Error attach_det(const cpapr_plan* P, PhiArgs& a, int G = 0)
 {
     if (P->det_part == nullptr) return {CPAPR_OK, ""};
-    const int64_t tiles = cdiv(a.nnz, (int64_t)(kBlock / P->group) * a.L);
+    const int64_t tiles = cdiv(a.nnz, (int64_t)(kBlock / (G ? G : P->group)) * a.L);
     if (tiles > P->det_tiles) return {CPAPR_EUNSUPPORTED, "deterministic mode: tiles smaller than 128 nonzeros"};
     a.det_part = P->det_part;
     a.det_rows = P->det_rows;
@@ -1007,10 +1008,11 @@ Error attach_det(const cpapr_plan* P, PhiArgs& a)
     return {CPAPR_OK, ""};
 }
 
-Error launch_det_fixup(const cpapr_plan* P, int mode, const PhiArgs& a, double* out, const int* done, hipStream_t s)
+Error launch_det_fixup(const cpapr_plan* P, int mode, const PhiArgs& a, double* out, const int* done, hipStream_t s,
+                       int G = 0)
 {
     if (a.det_part == nullptr) return {CPAPR_OK, ""};
-    const int64_t tile_nnz = (int64_t)(kBlock / P->group) * a.L;
+    const int64_t tile_nnz = (int64_t)(kBlock / (G ? G : P->group)) * a.L;
     const int64_t tiles = cdiv(a.nnz, tile_nnz);
     if (tiles <= 0) return {CPAPR_OK, ""};
     det_fixup_kernel<<<(unsigned)tiles, kBlock, 0, s>>>(P->mode[mode].rows, a.nnz, tile_nnz, tiles, P->R, a.det_part,
@@ -1060,16 +1062,23 @@ Error launch_delta4(const cpapr_plan* P, int mode, const double* B, const double
                     const void* const* fac, double eps, double* out, const int* skip, hipStream_t s)
 {
     if (P->R < kTrials4) return {CPAPR_EUNSUPPORTED, "the four-trial line-search pass needs R >= 4"};
-    const int G = P->group;
-    const int RPL = rank_block(P->R, G);
+    int G = P->group;
+    int RPL = rank_block(P->R, G);
     PhiArgs a = make_args(P, mode, B, fac, eps, out, skip);
+    // Four rank columns per lane hold 16 trial-step words per lane: such shapes
+    // take twice the lanes per nonzero for this pass, on the same tiles.
+    if (RPL == 4 && G <= 32 && phi_shape_supported(2 * G, rank_block(P->R, 2 * G), P->N - 1)) {
+        G *= 2;
+        RPL = rank_block(P->R, G);
+        a.L *= 2;
+    }
     a.D = D;
     a.live = live;
-    Error e = attach_det(P, a);
+    Error e = attach_det(P, a, G);
     if (e.code) return e;
     e = dispatch_seg<false, kDelta4>(G, RPL, a, s);
     if (e.code) return e;
-    return launch_det_fixup(P, mode, a, out, skip, s);
+    return launch_det_fixup(P, mode, a, out, skip, s, G);
 }
 
 Error launch_mttkrp(const cpapr_plan* P, int mode, const double* const* A, double* M, hipStream_t s)

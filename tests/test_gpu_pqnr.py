@@ -151,3 +151,29 @@ def test_pqnr_rejects_mu_plan_and_mixed():
     with pytest.raises(cpapr.CpaprError) as ei:
         _plan(X, 10, precision=cpapr.CPAPR_MIXED)
     assert ei.value.code == -6
+
+
+@pytest.mark.parametrize("deterministic", [0, 1])
+def test_pqnr_four_column_shapes(deterministic):
+    """R = 24 runs Phi at 8 lanes x 4 columns; the four-trial line-search pass
+    takes 16 x 2 on the same tiles (also in the deterministic mode, whose
+    tile-end partials must line up with them): lockstep with the oracle, and
+    bit-for-bit repeats when deterministic."""
+    X = synth.random_tensor(17, (400, 300, 200), 40_000, zipf=(1.3, None, None))
+    M = synth.random_model(17, X.dims, 24)
+    P = _plan(X, 24, lmax=2, tol=0.0, deterministic=deterministic)
+    assert P.shape()[0] == 8
+    A = [dev(a) for a in M.factors]
+    for n in range(3):
+        Bh = M.factors[n] * M.lam
+        runs = []
+        for _ in range(2 if deterministic else 1):
+            B = dev(Bh)
+            st = P.pqnr_inner(n, B, A)
+            runs.append(host(B))
+        Bo, ost = oracle.pqnr_inner(X, n, Bh, M.factors, lmax=2, tau=0.0)
+        assert st["row_steps"] == ost["row_steps"]
+        assert np.max(np.abs(runs[0] - Bo)) <= 1e-12 * np.max(np.abs(Bo)), f"mode {n}"
+        if deterministic:
+            assert np.array_equal(runs[0], runs[1]), f"mode {n} differs between runs"
+    P.close()
