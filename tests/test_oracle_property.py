@@ -57,3 +57,31 @@ def test_loglik_equals_dense_definition(oracle_lib, dims, R, seed):
     M = synth.random_model(seed, dims, R)
     ref = dense_ref.loglik_dense(X, M.lam, M.factors)
     assert abs(oracle_lib.loglik(X, M) - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def _row_objective(X, n, B, factors, eps=1e-10):
+    """Sum over rows of f_i(b) = sum(b) - sum_k x_k log(max(b . pi_k, eps)), in NumPy."""
+    pi = np.ones((X.nnz, B.shape[1]))
+    for m in range(X.nmodes):
+        if m != n:
+            pi *= factors[m][X.idx[m]]
+    mk = np.einsum("kr,kr->k", B[X.idx[n]], pi)
+    return float(B.sum() - np.sum(X.vals * np.log(np.maximum(mk, eps))))
+
+
+@cfg
+@given(dims=shapes, R=st.integers(1, 5), seed=st.integers(0, 10_000), lmax=st.integers(1, 6))
+def test_row_solvers_descend_and_stay_feasible(oracle_lib, dims, R, seed, lmax):
+    """PQNR and PDNR never increase the row objectives, keep B >= 0 and report
+    the steps they took (lmax per row on a fixed schedule)."""
+    dims = tuple(dims)
+    X = synth.random_tensor(seed, dims, max(1, math.prod(dims) // 2))
+    M = synth.random_model(seed, dims, R)
+    for n in range(len(dims)):
+        B0 = M.factors[n] * M.lam
+        f0 = _row_objective(X, n, B0, M.factors)
+        for solve in (oracle_lib.pqnr_inner, oracle_lib.pdnr_inner):
+            B, st_ = solve(X, n, B0, M.factors, lmax=lmax, tau=0.0)
+            assert np.all(B >= 0)
+            assert _row_objective(X, n, B, M.factors) <= f0 + 1e-12 * abs(f0)
+            assert st_["n_updates"] == lmax and st_["row_steps"] == lmax * X.dims[n]
