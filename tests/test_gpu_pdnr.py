@@ -69,10 +69,11 @@ def test_pdnr_short_schedule_lockstep(lmax):
 
 
 @pytest.mark.parametrize("dims,R,nnz", [((6, 5, 4, 3, 5, 4, 3, 2), 3, 500), ((40, 30, 20, 10), 4, 3000),
-                                        ((30, 20, 10), 64, 4000), ((50, 40, 30), 33, 6000)])
+                                        ((30, 20, 10), 64, 4000), ((50, 40, 30), 33, 6000),
+                                        ((120, 90), 8, 3000)])
 def test_pdnr_unusual_shapes_lockstep(dims, R, nnz):
     """Eight modes; the largest rank (a full 64-lane system); a rank one past a
-    power of two (padded system)."""
+    power of two (padded system); a matrix (pi from one other factor)."""
     X = synth.random_tensor(41, dims, nnz)
     M = synth.random_model(41, dims, R)
     _lockstep(X, M, R, 2)
