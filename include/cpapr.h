@@ -180,7 +180,8 @@ int64_t cpapr_plan_segments(const cpapr_plan* plan, int32_t mode);
  *   eps divisor floor, > 0.
  *   Phi device [I_n x R], overwritten (rows without nonzeros become 0).
  * In CPAPR_MIXED the other factors are first rounded to FP32 copies in the
- * workspace; products and sums run in FP32 with compensation, Phi is FP64.
+ * workspace and gathered from there (half the bytes); they are widened to FP64
+ * as they are loaded, so products, sums and Phi are FP64.
  * Stream-ordered; does not wait. */
 int cpapr_phi(cpapr_plan* plan, int32_t mode, const double* B, const double* const* A, double eps,
               double* Phi, void* stream);

@@ -22,14 +22,16 @@
 //  * Tiles are mapped XCD-aware: consecutive tiles (which share B and Phi rows)
 //    are given to the same XCD so their rows stay in one L2.
 //
-// Mixed precision: factors and pi are FP32; products and sums carry an FP32
-// error term (TwoProd by FMA, Knuth TwoSum), and Phi partials leave registers
-// as FP64 hi + lo.
+// Mixed precision: the other factors are stored (and gathered) as FP32, which
+// halves the gathered bytes, and widened to FP64 as they are loaded; products,
+// sums and Phi are FP64. (Compensated FP32 arithmetic was the earlier design:
+// it made the kernel issue-bound and slower than FP64; widening runs at the
+// FP64 kernel's speed at R = 16 and 19-29 % faster at R = 32.)
 //
-// The same tile code serves four kinds of pass over the nonzeros: Phi, MTTKRP
-// (Eqs. 10-12: x_k pi_k scattered), the log-likelihood terms (summed per tile)
-// and the line-search sums of the PQNR row solves (per-row changes of the
-// likelihood along trial steps).
+// The same tile code serves several kinds of pass over the nonzeros: Phi,
+// MTTKRP (Eqs. 10-12: x_k pi_k scattered), the log-likelihood terms (summed
+// per tile) and the line-search sums of the row solves (per-row changes of
+// the likelihood along one or four trial steps).
 #include <algorithm>
 #include <type_traits>
 
@@ -53,12 +55,6 @@ __device__ __forceinline__ double dpp_f64(double v)
     return __hiloint2double(hi, lo);
 }
 
-template <int CTRL>
-__device__ __forceinline__ float dpp_f32(float v)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-
 // lane ^ 16 inside each 32-lane half (ds_swizzle bitmask mode: and 0x1f, xor 0x10)
 __device__ __forceinline__ double xor16_f64(double v)
 {
@@ -66,21 +62,12 @@ __device__ __forceinline__ double xor16_f64(double v)
     int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
     return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ float xor16_f32(float v)
-{
-    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
-}
 __device__ __forceinline__ double xor32_f64(double v)
 {
     const int addr = ((int)(threadIdx.x & 63) ^ 32) << 2;
     int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
     int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
     return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ float xor32_f32(float v)
-{
-    const int addr = ((int)(threadIdx.x & 63) ^ 32) << 2;
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
 }
 
 // DPP controls: quad_perm [1,0,3,2] = 0xB1, quad_perm [2,3,0,1] = 0x4E,
@@ -97,64 +84,14 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
-#pragma clang fp contract(off)
-// Knuth TwoSum: s + e == a + b exactly.
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e)
-{
-    s = a + b;
-    const float bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
 
-__device__ __forceinline__ void pair_add(float& hi, float& lo, float ohi, float olo)
-{
-    float s, e;
-    two_sum(hi, ohi, s, e);
-    hi = s;
-    lo = (lo + olo) + e;
-}
-
-template <int G>
-__device__ __forceinline__ void group_sum_pair(float& hi, float& lo)
-{
-    if constexpr (G >= 2) pair_add(hi, lo, dpp_f32<0xB1>(hi), dpp_f32<0xB1>(lo));
-    if constexpr (G >= 4) pair_add(hi, lo, dpp_f32<0x4E>(hi), dpp_f32<0x4E>(lo));
-    if constexpr (G >= 8) pair_add(hi, lo, dpp_f32<0x141>(hi), dpp_f32<0x141>(lo));
-    if constexpr (G >= 16) pair_add(hi, lo, dpp_f32<0x140>(hi), dpp_f32<0x140>(lo));
-    if constexpr (G >= 32) pair_add(hi, lo, xor16_f32(hi), xor16_f32(lo));
-    if constexpr (G >= 64) pair_add(hi, lo, xor32_f32(hi), xor32_f32(lo));
-}
-
-// Compensated accumulate of a*b into (hi, lo): TwoProd via FMA, then TwoSum.
-__device__ __forceinline__ void acc_prod(float& hi, float& lo, float a, float b)
-{
-    const float p = a * b;
-    const float pe = __builtin_fmaf(a, b, -p);
-    float s, e;
-    two_sum(hi, p, s, e);
-    hi = s;
-    lo = lo + (e + pe);
-}
-#pragma clang fp contract(fast)
-
-// Per-lane accumulator of one Phi row slice: FP64, or FP32 hi + lo.
-template <bool MIXED>
-struct Acc;
-
-template <>
-struct Acc<false> {
+// Per-lane accumulator of one Phi row slice (FP64 in both precisions: FP32-stored
+// factors are widened as they are loaded).
+struct Acc {
     double v;
     __device__ void zero() { v = 0.0; }
     __device__ void add(double s, double pi) { v = __builtin_fma(s, pi, v); }
     __device__ double value() const { return v; }
-};
-
-template <>
-struct Acc<true> {
-    float hi, lo;
-    __device__ void zero() { hi = lo = 0.f; }
-    __device__ void add(float s, float pi) { acc_prod(hi, lo, s, pi); }
-    __device__ double value() const { return (double)hi + (double)lo; }
 };
 
 // q = x / m for normal, finite m > 0 (m is clamped to eps > 0 before): the
@@ -169,14 +106,6 @@ __device__ __forceinline__ double div_pos(double x, double m)
     r = __builtin_fma(r, __builtin_fma(-m, r, 1.0), r);
     const double q = x * r;
     return __builtin_fma(r, __builtin_fma(-m, q, x), q);
-}
-
-__device__ __forceinline__ float div_pos(float x, float m)
-{
-    float r = __builtin_amdgcn_rcpf(m);
-    r = __builtin_fmaf(r, __builtin_fmaf(-m, r, 1.f), r);
-    const float q = x * r;
-    return __builtin_fmaf(r, __builtin_fmaf(-m, q, x), q);
 }
 
 // What the segmented kernel computes per nonzero and where it goes.
@@ -218,26 +147,18 @@ __device__ __forceinline__ bool delta_ratio(const double (&b)[RPL], const double
 
 // One nonzero's dot product and scale: s_k for Phi, x_k for MTTKRP, the
 // likelihood term for Loglik.
-template <int G, int RPL, bool MIXED, int KIND, typename T>
-__device__ __forceinline__ T nonzero_scale(const T (&b)[RPL], const T (&pi)[RPL], double x, double eps)
+template <int G, int RPL, int KIND>
+__device__ __forceinline__ double nonzero_scale(const double (&b)[RPL], const double (&pi)[RPL], double x, double eps)
 {
     if constexpr (KIND == kMttkrp) {
-        return (T)x;
-    } else if constexpr (!MIXED) {
+        return x;
+    } else {
         double d = 0.0;
 #pragma unroll
         for (int c = 0; c < RPL; ++c) d = __builtin_fma(b[c], pi[c], d);
         d = group_sum<G>(d);
         if constexpr (KIND == kLoglik) return x * log(d > eps ? d : eps);
         return div_pos(x, d > eps ? d : eps);
-    } else {
-        float hi = 0.f, lo = 0.f;
-#pragma unroll
-        for (int c = 0; c < RPL; ++c) acc_prod(hi, lo, b[c], pi[c]);
-        group_sum_pair<G>(hi, lo);
-        const float m = hi + lo;
-        const float e = (float)eps;
-        return div_pos((float)x, m > e ? m : e);
     }
 }
 
@@ -275,7 +196,8 @@ struct TileShared {
 template <int G, int RPL, int NM1, bool MIXED, int KIND>
 __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileShared<G, RPL, NM1>& sh)
 {
-    using T = typename std::conditional<MIXED, float, double>::type;
+    using T = double;  // arithmetic: FP64 in both precisions
+    using L = typename std::conditional<MIXED, float, double>::type;  // the factors as stored
     constexpr int NG = kBlock / G;
     constexpr int W = G * RPL;
     constexpr int U = gather_depth<NM1, RPL>();
@@ -314,7 +236,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
     int cur = -1;
     int nseg = 0;
     double ll = 0.0;  // likelihood terms of this lane group (Loglik)
-    Acc<MIXED> acc[RPL];
+    Acc acc[RPL];
     T b[RPL];
     constexpr bool LS = KIND == kDelta || KIND == kDelta4;  // a line-search pass
     constexpr int NTR = KIND == kDelta4 ? kTrials4 : 1;      // trial steps it evaluates
@@ -381,9 +303,9 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
         }
     };
 
-    const T* fac[NM1];
+    const L* fac[NM1];
 #pragma unroll
-    for (int m = 0; m < NM1; ++m) fac[m] = (const T*)a.fac[m];
+    for (int m = 0; m < NM1; ++m) fac[m] = (const L*)a.fac[m];
     Staged<NM1>* my = stage + g * BATCH;
 
     // Metadata of the next round is loaded into registers while the current
@@ -420,7 +342,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
         for (int q0 = 0; q0 < cnt; q0 += U) {
             int rowu[U];
             double xu[U];
-            T fu[U][NM1][RPL];
+            L fu[U][NM1][RPL];
             bool liveu[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -433,7 +355,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
                     if (liveu[u]) {
 #pragma unroll
                         for (int m = 0; m < NM1; ++m) {
-                            const T* f = fac[m] + (uint64_t)e.c[m] + colbase;
+                            const L* f = fac[m] + (uint64_t)e.c[m] + colbase;
 #pragma unroll
                             for (int c = 0; c < RPL; ++c) fu[u][m][c] = f[c];
                         }
@@ -527,7 +449,7 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
                         }
                         if (++pend == G) drain();
                     } else {
-                        const T s = nonzero_scale<G, RPL, MIXED, KIND, T>(b, pi, xu[u], a.eps);
+                        const double s = nonzero_scale<G, RPL, KIND>(b, pi, xu[u], a.eps);
                         if constexpr (KIND == kLoglik) {
                             ll += s;
                         } else {
@@ -758,7 +680,7 @@ __global__ __launch_bounds__(kBlock) void phi_atomic_kernel(PhiArgs a)
         const double* brow = a.B + (int64_t)row * R + lane * RPL;
 #pragma unroll
         for (int c = 0; c < RPL; ++c) b[c] = valid[c] ? brow[c] : 0.0;
-        const double s = nonzero_scale<G, RPL, false, false, double>(b, pi, x, a.eps);
+        const double s = nonzero_scale<G, RPL, kPhi>(b, pi, x, a.eps);
         double* dst = a.Phi + (int64_t)row * R + lane * RPL;
 #pragma unroll
         for (int c = 0; c < RPL; ++c)
