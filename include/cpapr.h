@@ -57,6 +57,10 @@ enum {
     CPAPR_EUNSUPPORTED = -6 /* size outside the documented limits */
 };
 
+/* Precision. FP64: factors gathered as stored. MIXED: Phi's gathers read FP32
+ * copies of the other factors (half the gathered bytes), widened to FP64 as
+ * they are loaded; every product, sum, B, Phi, lambda and the KKT test stay
+ * FP64. */
 enum { CPAPR_FP64 = 0, CPAPR_MIXED = 1 };
 
 /* Phi kernel variants. SEGMENTED: mode-sorted nonzeros, in-register and
