@@ -48,6 +48,18 @@ MUTATIONS = [
      ["pqnr:test_pqnr_objective_decreases_every_step", "pqnr:test_pqnr_converges_faster_than_mu"]),
     ("pqnr-two-loop-sign", "if (fr[r]) q[r] += (a[c] - beta) * P.s[j][r];", "if (fr[r]) q[r] -= (a[c] - beta) * P.s[j][r];",
      ["pqnr:test_pqnr_converges_faster_than_mu", "pqnr:test_pqnr_matches_independent_lbfgsb"]),
+    ("pqnr-five-trials", "#define PQNR_TRIALS 4", "#define PQNR_TRIALS 5",
+     ["pqnr:test_pqnr_line_search_four_trials_then_mu_step"]),
+    ("pqnr-three-trials", "#define PQNR_TRIALS 4", "#define PQNR_TRIALS 3",
+     ["pqnr:test_pqnr_line_search_four_trials_then_mu_step"]),
+    ("pqnr-fallback-keeps-pairs", "if (!accepted) P.count = 0;", "if (!accepted) (void)0;",
+     ["pqnr:test_pqnr_line_search_four_trials_then_mu_step"]),
+    ("pqnr-fallback-no-step", "for (int r = 0; r < R; ++r) delta[r] = -b[r] * g[r];",
+     "for (int r = 0; r < R; ++r) delta[r] = 0.0;",
+     ["pqnr:test_pqnr_line_search_four_trials_then_mu_step"]),
+    ("pqnr-fallback-last-trial", "        if (!accepted) /* the MU step b .* phi, written as b + (-b .* g) */\n"
+     "            for (int r = 0; r < R; ++r) delta[r] = -b[r] * g[r];\n", "",
+     ["pqnr:test_pqnr_line_search_four_trials_then_mu_step"]),
     ("pdnr-hessian-drops-m", "const double w = sc / mm;", "const double w = sc;",
      ["pdnr:test_pdnr_first_step_is_damped_newton", "pdnr:test_pdnr_converges_in_few_steps"]),
     ("pdnr-hessian-no-cross-terms", "w * pi[r] * pi[c]", "w * pi[r] * pi[r]",
@@ -76,6 +88,10 @@ PARAMS = {
 def _run_pin(name):
     if name.startswith("pqnr:"):
         from tests import test_oracle_pqnr as pq
+        if name[5:] == "test_pqnr_line_search_four_trials_then_mu_step":
+            for case in pq.CRAFTED:
+                pq.test_pqnr_line_search_four_trials_then_mu_step(oracle, *case)
+            return
         getattr(pq, name[5:])(oracle)
         return
     if name.startswith("pdnr:"):

@@ -121,3 +121,55 @@ def test_pqnr_solve_mass_normalisation_and_fit(oracle_lib):
     assert abs(out.lam.sum() - X.vals.sum()) <= 1e-7 * X.vals.sum()
     mu, _ = oracle_lib.solve(X, M, kmax=8, lmax=10, tau=0.0)
     assert oracle_lib.loglik(X, out) >= oracle_lib.loglik(X, mu)
+
+
+# Two one-row subproblems found by a seeded search (a 1 x J x K tensor with
+# Zipf(1.1) coordinates): (seed, J, K, nonzeros, R, the first trial whose
+# sufficient-decrease test passes at the third step, 0-based). Along that step's
+# quasi-Newton direction the first passes at alpha = 1/8 (the fourth and last
+# trial of the reading) and at alpha = 1/16 (a fifth trial the reading does not
+# make).
+CRAFTED = [(100, 13, 10, 50, 2, 3), (571, 15, 9, 42, 3, 4)]
+
+
+@pytest.mark.parametrize("seed,J,K,nnz,R,first_pass", CRAFTED)
+def test_pqnr_line_search_four_trials_then_mu_step(oracle_lib, seed, J, K, nnz, R, first_pass):
+    """The trial count and the fallback of the PQNR reading: four backtracking
+    trials (alpha = 1 .. 1/8), then the MU step b * phi with the curvature
+    pairs dropped. The third step of each crafted row is a quasi-Newton step
+    (two pairs, a descent direction): where the fourth trial passes, the
+    oracle takes it; where only a fifth would pass, the oracle takes the MU
+    step, and the steps after it differ from those keeping the pairs gives."""
+    from tests import rowsolve_ref as ref
+    X = synth.random_tensor(seed, (1, J, K), nnz, zipf=(None, 1.1, 1.1))
+    M = synth.random_model(seed, X.dims, R)
+    xs = X.vals
+    P = M.factors[1][X.idx[1]] * M.factors[2][X.idx[2]]
+    B0 = M.factors[0] * M.lam
+    b0 = B0[0]
+    orc = [b0] + [oracle_lib.pqnr_inner(X, 0, B0, M.factors, lmax=k, tau=0.0)[0][0] for k in range(1, 7)]
+    log = []
+    its = ref.pqnr_row(xs, P, b0, 6, log=log)
+    for k in range(7):  # the oracle takes the reading's steps
+        assert np.max(np.abs(orc[k] - its[k])) <= 1e-13 * np.max(np.abs(its[k])), k
+    e = log[2]
+    b, g, d = e["b"], e["g"], e["d"]
+    assert e["npairs"] == 2 and np.dot(g, d) < 0.0 and not np.allclose(d, -b * g)
+    passes = []
+    for alpha in (1.0, 0.5, 0.25, 0.125, 0.0625):
+        delta = np.maximum(b + alpha * d, 0.0) - b
+        gd = float(np.dot(g, delta))
+        assert gd < 0.0
+        passes.append(ref.objective_change(b, delta, xs, P) <= 1e-4 * gd)
+    assert passes.index(True) == first_pass, passes
+    phi = (xs / (P @ b)) @ P  # the MU step, from Phi's definition
+    if first_pass < 4:
+        taken = b + (np.maximum(b + 0.5 ** first_pass * d, 0.0) - b)
+        np.testing.assert_allclose(orc[3], taken, rtol=1e-13, atol=0)
+        assert np.max(np.abs(orc[3] - b * phi)) > 1e-3 * np.max(np.abs(b * phi))
+    else:
+        np.testing.assert_allclose(orc[3], b * phi, rtol=1e-13, atol=0)
+        fifth = b + (np.maximum(b + 0.0625 * d, 0.0) - b)
+        assert np.max(np.abs(orc[3] - fifth)) > 1e-3 * np.max(np.abs(fifth))
+        kept = ref.pqnr_row(xs, P, b0, 6, keep_pairs_on_fail=True)
+        assert max(np.max(np.abs(orc[k] - kept[k])) / np.max(np.abs(kept[k])) for k in range(4, 7)) > 1e-6
