@@ -66,8 +66,12 @@ enum { CPAPR_FP64 = 0, CPAPR_MIXED = 1 };
 /* Phi kernel variants. SEGMENTED: mode-sorted nonzeros, in-register and
  * in-workgroup segmented reduction, atomics only for rows that cross a tile
  * boundary. ATOMIC: the per-nonzero atomic scatter of the paper's GPU kernel
- * (Algorithm 3), kept for comparison. AUTO picks SEGMENTED. */
-enum { CPAPR_VARIANT_AUTO = 0, CPAPR_VARIANT_SEGMENTED = 1, CPAPR_VARIANT_ATOMIC = 2 };
+ * (Algorithm 3), kept for comparison. XR: SEGMENTED with the per-nonzero dot
+ * products reduced across the lane group by a reduce-scatter through LDS
+ * (one sum and one division per nonzero in one lane), for 8 or 16 lanes per
+ * nonzero and up to 8 gathered words per lane; other shapes run SEGMENTED.
+ * AUTO picks SEGMENTED. */
+enum { CPAPR_VARIANT_AUTO = 0, CPAPR_VARIANT_SEGMENTED = 1, CPAPR_VARIANT_ATOMIC = 2, CPAPR_VARIANT_XR = 3 };
 
 /* Order of the nonzeros inside a row of the mode-n sorted copy (Phi's sum over
  * a row is order-free). ROW: input order (a stable sort by i_n). ROW_COL: by
@@ -190,6 +194,26 @@ int64_t cpapr_plan_segments(const cpapr_plan* plan, int32_t mode);
 int cpapr_phi(cpapr_plan* plan, int32_t mode, const double* B, const double* const* A, double eps,
               double* Phi, void* stream);
 
+/* Transient Phi(n) (Algorithm 2) of a COO tensor without a plan, for a caller
+ * that needs Phi once. The nonzeros of mode `mode` are checked (coordinates in
+ * range, values finite and > 0), sorted by their mode-n coordinate into the
+ * caller's workspace (Section 3.1's sort by mode, for this mode only) and
+ * reduced by the plan path's Phi kernel with its default launch shape.
+ *   X   the tensor (device idx / vals, host dims), nnz >= 0.
+ *   R   rank, 1..CPAPR_MAX_RANK.
+ *   B   device [I_mode x R], nonnegative.
+ *   A   host array of N device pointers to A(m) [I_m x R]; A[mode] is unused.
+ *   eps divisor floor, > 0.
+ *   Phi device [I_mode x R], overwritten (rows without nonzeros become 0).
+ *   ws  device, 256-byte aligned, ws_bytes >= cpapr_phi_coo_workspace_size;
+ *       its contents are scratch.
+ * FP64 only. Waits for `stream` before returning, so ws may be reused or freed
+ * at once. Errors: CPAPR_EINDEX / CPAPR_EVALUE for bad entries,
+ * CPAPR_EWORKSPACE for a missing, misaligned or small workspace. */
+int cpapr_phi_coo_workspace_size(const cpapr_coo* X, int32_t mode, int32_t R, size_t* bytes);
+int cpapr_phi_coo(const cpapr_coo* X, int32_t mode, int32_t R, const double* B, const double* const* A, double eps,
+                  double* Phi, void* ws, size_t ws_bytes, void* stream);
+
 /* MU inner loop of Algorithm 1 for one mode, params lmax / tol / eps of the plan:
  * for l < lmax: Phi = phi(B); viol = max|min(B, 1 - Phi)|; stop if tol > 0 and
  * viol < tol; else B <- B .* Phi.
@@ -226,6 +250,15 @@ int cpapr_pqnr_inner(cpapr_plan* plan, int32_t mode, double* B, const double* co
  * MU plan's. */
 int cpapr_pdnr_inner(cpapr_plan* plan, int32_t mode, double* B, const double* const* A, cpapr_stats* out,
                      void* stream);
+
+/* Per-row outcome of the last cpapr_pqnr_inner / cpapr_pdnr_inner call on this
+ * plan, which must have been for `mode` (the row state is that of the mode
+ * solved last): steps (device [I_mode] int32, may be NULL) receives the steps
+ * each row took; viol (device [I_mode] doubles, may be NULL) the violation
+ * max_r |min(b_r, 1 - phi_r)| of its last KKT test, which for a row that
+ * stopped is the value found below tol. Stream-ordered device-to-device
+ * copies. CPAPR_EINVAL for an MU plan. */
+int cpapr_row_stats(cpapr_plan* plan, int32_t mode, int32_t* steps, double* viol, void* stream);
 
 /* Full CP-APR MU (Algorithm 1) with the plan's parameters.
  *   lambda device [R], in/out.  A host array of N device pointers, in/out.

@@ -24,12 +24,20 @@ CPAPR_MIXED = 1
 CPAPR_VARIANT_AUTO = 0
 CPAPR_VARIANT_SEGMENTED = 1
 CPAPR_VARIANT_ATOMIC = 2
+CPAPR_VARIANT_XR = 3
 CPAPR_SORT_ROW = 0
 CPAPR_SORT_ROW_COL = 1
 CPAPR_METHOD_MU = 0
 CPAPR_METHOD_PQNR = 1
 CPAPR_METHOD_PDNR = 2
 MAX_MODES = 8
+CPAPR_OK = 0
+CPAPR_EINVAL = -1
+CPAPR_EINDEX = -2
+CPAPR_EVALUE = -3
+CPAPR_EWORKSPACE = -4
+CPAPR_EHIP = -5
+CPAPR_EUNSUPPORTED = -6
 
 
 class CpaprError(RuntimeError):
@@ -81,9 +89,12 @@ def load():
         "cpapr_plan_set_shape": (C.c_int, [vp, i32, i32]),
         "cpapr_plan_shape": (C.c_int, [vp, P(i32), P(i32)]),
         "cpapr_phi": (C.c_int, [vp, i32, vp, P(vp), dbl, vp, vp]),
+        "cpapr_phi_coo_workspace_size": (C.c_int, [P(cpapr_coo), i32, i32, P(C.c_size_t)]),
+        "cpapr_phi_coo": (C.c_int, [P(cpapr_coo), i32, i32, vp, P(vp), dbl, vp, vp, C.c_size_t, vp]),
         "cpapr_mu_inner": (C.c_int, [vp, i32, vp, P(vp), vp, P(cpapr_stats), vp]),
         "cpapr_pqnr_inner": (C.c_int, [vp, i32, vp, P(vp), P(cpapr_stats), vp]),
         "cpapr_pdnr_inner": (C.c_int, [vp, i32, vp, P(vp), P(cpapr_stats), vp]),
+        "cpapr_row_stats": (C.c_int, [vp, i32, vp, vp, vp]),
         "cpapr_solve": (C.c_int, [vp, vp, P(vp), P(cpapr_stats), vp]),
         "cpapr_loglik": (C.c_int, [vp, vp, P(vp), dbl, P(dbl), vp]),
         "cpapr_mttkrp": (C.c_int, [vp, i32, P(vp), vp, vp]),
@@ -116,8 +127,9 @@ def load():
 
 
 EXPORTED = ("cpapr_params_default", "cpapr_plan_workspace_size", "cpapr_plan_create", "cpapr_plan_destroy",
-            "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_plan_shape", "cpapr_phi", "cpapr_mu_inner", "cpapr_pqnr_inner",
-            "cpapr_pdnr_inner", "cpapr_solve", "cpapr_loglik",
+            "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_plan_shape", "cpapr_phi", "cpapr_phi_coo_workspace_size",
+            "cpapr_phi_coo", "cpapr_mu_inner", "cpapr_pqnr_inner",
+            "cpapr_pdnr_inner", "cpapr_row_stats", "cpapr_solve", "cpapr_loglik",
             "cpapr_mttkrp", "cpapr_batch_workspace_size", "cpapr_batch_tiles", "cpapr_batch_create", "cpapr_batch_create2",
             "cpapr_batch_destroy", "cpapr_batch_set", "cpapr_batch_clear", "cpapr_batch_commit", "cpapr_batch_run",
             "cpapr_batch_mu", "cpapr_batch_inner", "cpapr_batch_status", "cpapr_mode_begin", "cpapr_mode_end", "cpapr_plan_sync_f32",
@@ -208,6 +220,34 @@ def cpapr_phi(h, mode, B, A, eps, Phi, stream=None):
     return _check(load().cpapr_phi(h, mode, B.data_ptr(), _ptr_array(A), eps, Phi.data_ptr(), _stream(stream)))
 
 
+def cpapr_phi_coo_workspace_size(coo: cpapr_coo, mode: int, R: int) -> int:
+    n = C.c_size_t(0)
+    _check(load().cpapr_phi_coo_workspace_size(C.byref(coo), mode, R, C.byref(n)))
+    return int(n.value)
+
+
+def cpapr_phi_coo(coo, mode, R, B, A, eps, Phi, ws, stream=None):
+    """Transient Phi of a COO tensor (no plan); ws: a device uint8 tensor of at least the queried size."""
+    import torch
+    _need_cuda(B, "B", torch.float64)
+    _need_cuda(Phi, "Phi", torch.float64)
+    _need_cuda(ws, "ws")
+    _check(load().cpapr_phi_coo(C.byref(coo), mode, R, B.data_ptr(), _ptr_array(A), eps, Phi.data_ptr(),
+                                ws.data_ptr(), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def phi_coo(dims, idx, vals, mode, R, B, A, eps=1e-10, out=None, stream=None):
+    """Transient Phi(mode) of device COO arrays (idx int32 [N, nnz], vals float64 [nnz])."""
+    import torch
+    coo = make_coo(dims, idx, vals)
+    nbytes = cpapr_phi_coo_workspace_size(coo, mode, R)
+    ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=B.device)
+    if out is None:
+        out = torch.empty((int(dims[mode]), R), dtype=torch.float64, device=B.device)
+    cpapr_phi_coo(coo, mode, R, B, A, eps, out, ws, stream)
+    return out
+
+
 def cpapr_mu_inner(h, mode, B, A, Phi_last, stream=None) -> dict:
     st = cpapr_stats()
     _check(load().cpapr_mu_inner(h, mode, B.data_ptr(), _ptr_array(A), Phi_last.data_ptr(), C.byref(st),
@@ -225,6 +265,16 @@ def cpapr_pdnr_inner(h, mode, B, A, stream=None) -> dict:
     st = cpapr_stats()
     _check(load().cpapr_pdnr_inner(h, mode, B.data_ptr(), _ptr_array(A), C.byref(st), _stream(stream)))
     return st.as_dict()
+
+
+def cpapr_row_stats(h, mode, steps, viol, stream=None):
+    """Per-row steps (int32) and last KKT violation (float64) of the last row-solve call, into device tensors."""
+    if steps is not None:
+        _need_cuda(steps, "steps")
+    if viol is not None:
+        _need_cuda(viol, "viol")
+    _check(load().cpapr_row_stats(h, mode, steps.data_ptr() if steps is not None else None,
+                                  viol.data_ptr() if viol is not None else None, _stream(stream)))
 
 
 def cpapr_solve(h, lam, A, stream=None) -> dict:
@@ -439,6 +489,15 @@ class Plan:
     def pdnr_inner(self, mode, B, A, stream=None):
         """PDNR row solves of one mode (plan created with method=CPAPR_METHOD_PDNR); B in/out."""
         return cpapr_pdnr_inner(self.handle, mode, B, A, stream)
+
+    def row_stats(self, mode, stream=None):
+        """(steps, viol) per row of `mode` after its last row-solve call, as host arrays."""
+        import torch
+        steps = torch.empty(self.dims[mode], dtype=torch.int32, device="cuda")
+        viol = torch.empty(self.dims[mode], dtype=torch.float64, device="cuda")
+        cpapr_row_stats(self.handle, mode, steps, viol, stream)
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        return steps.cpu().numpy(), viol.cpu().numpy()
 
     def solve(self, lam, A, stream=None):
         return cpapr_solve(self.handle, lam, A, stream)

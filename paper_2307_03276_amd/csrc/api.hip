@@ -63,7 +63,7 @@ Error check_params(const cpapr_params* p, int32_t R, int nmodes)
     if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return {CPAPR_EINVAL, "eps must be finite and > 0"};
     if (!(p->kappa >= 0.0) || !(p->kappa_tol >= 0.0)) return {CPAPR_EINVAL, "kappa and kappa_tol must be >= 0"};
     if (p->precision != CPAPR_FP64 && p->precision != CPAPR_MIXED) return {CPAPR_EINVAL, "unknown precision"};
-    if (p->variant < CPAPR_VARIANT_AUTO || p->variant > CPAPR_VARIANT_ATOMIC) return {CPAPR_EINVAL, "unknown variant"};
+    if (p->variant < CPAPR_VARIANT_AUTO || p->variant > CPAPR_VARIANT_XR) return {CPAPR_EINVAL, "unknown variant"};
     if (p->variant == CPAPR_VARIANT_ATOMIC && p->precision == CPAPR_MIXED)
         return {CPAPR_EUNSUPPORTED, "the atomic variant is FP64 only"};
     const int g = cpapr::resolve_group(R, p->group, nmodes - 1);
@@ -249,6 +249,79 @@ void prof_end(hipStream_t s)
     if (hipEventRecord(g_prof.stop[g_prof.count], s) == hipSuccess) g_prof.count++;
 }
 
+// Workspace of a transient Phi (no plan): the sorted copy of the one mode,
+// then the scratch of its sort.
+struct TransientLayout {
+    size_t rows, cidx, vals, scratch, total;
+};
+
+TransientLayout transient_layout(int N, int64_t nnz)
+{
+    TransientLayout L{};
+    size_t off = 0;
+    L.rows = off;
+    off += align256((size_t)nnz * 4);
+    L.cidx = off;
+    off += align256((size_t)nnz * 4 * (N - 1));
+    L.vals = off;
+    off += align256((size_t)nnz * 8);
+    L.scratch = off;
+    off += (size_t)cpapr::sort_scratch_bytes(nnz, N);
+    L.total = off;
+    return L;
+}
+
+size_t transient_bytes(int N, int64_t nnz) { return transient_layout(N, nnz).total; }
+
+Error check_transient(const cpapr_coo* X, int32_t mode, int32_t R, bool need_data)
+{
+    Error e = check_coo(X, R, need_data);
+    if (e.code) return e;
+    if (mode < 0 || mode >= X->nmodes) return {CPAPR_EINVAL, "mode out of range"};
+    return {CPAPR_OK, ""};
+}
+
+// Transient Phi of mode `mode` of X: validate and sort the mode's nonzeros
+// into `ws` (a one-mode plan kept on the host stack), then the plan's Phi
+// launch. Waits for the stream.
+Error phi_transient(const cpapr_coo* X, int32_t mode, int32_t R, const double* B, const double* const* A,
+                    double eps, double* Phi, char* ws, size_t ws_bytes, hipStream_t s)
+{
+    Error e = check_transient(X, mode, R, true);
+    if (e.code) return e;
+    if (!B || !Phi || !A) return {CPAPR_EINVAL, "B, A or Phi is NULL"};
+    for (int m = 0; m < X->nmodes; ++m)
+        if (m != mode && !A[m]) return {CPAPR_EINVAL, "a factor pointer is NULL"};
+    if (!(eps > 0.0) || !std::isfinite(eps)) return {CPAPR_EINVAL, "eps must be finite and > 0"};
+    const TransientLayout L = transient_layout(X->nmodes, X->nnz);
+    if (!ws) return {CPAPR_EWORKSPACE, "workspace is NULL"};
+    if (((uintptr_t)ws & 255) != 0) return {CPAPR_EWORKSPACE, "workspace must be 256-byte aligned"};
+    if (ws_bytes < L.total) return {CPAPR_EWORKSPACE, "workspace too small"};
+    cpapr_plan P{};
+    P.N = X->nmodes;
+    P.nnz = X->nnz;
+    P.R = R;
+    for (int m = 0; m < P.N; ++m) P.dims[m] = X->dims[m];
+    cpapr_params_default(&P.params);
+    P.ws = ws;
+    P.ws_bytes = ws_bytes;
+    P.group = cpapr::resolve_group(R, 0, P.N - 1);
+    P.mode[mode].rows = (int32_t*)(ws + L.rows);
+    P.mode[mode].cofs = (uint32_t*)(ws + L.cidx);
+    P.mode[mode].vals = (double*)(ws + L.vals);
+    e = cpapr::build_sorted(&P, X, ws + L.scratch, s, mode);
+    if (e.code) return e;
+    P.chunk = cpapr::model_chunk(&P, P.group);
+    const void* fac[CPAPR_MAX_MODES];
+    for (int m = 0; m < P.N; ++m) fac[m] = A[m];
+    e = cpapr::launch_fill(Phi, X->dims[mode] * (int64_t)R, 0.0, nullptr, s);
+    if (e.code) return e;
+    e = cpapr::launch_phi(&P, mode, B, fac, false, eps, Phi, nullptr, s);
+    if (e.code) return e;
+    CPAPR_HIP(hipStreamSynchronize(s));
+    return {CPAPR_OK, ""};
+}
+
 }  // namespace cpapr
 
 extern "C" {
@@ -425,6 +498,29 @@ int cpapr_phi(cpapr_plan* plan, int32_t mode, const double* B, const double* con
     }
 }
 
+int cpapr_phi_coo_workspace_size(const cpapr_coo* X, int32_t mode, int32_t R, size_t* bytes)
+{
+    try {
+        Error e = cpapr::check_transient(X, mode, R, false);
+        if (e.code) return report(e);
+        if (!bytes) return fail(CPAPR_EINVAL, "bytes is NULL");
+        *bytes = cpapr::transient_layout(X->nmodes, X->nnz).total;
+        return CPAPR_OK;
+    } catch (...) {
+        return fail(CPAPR_EINVAL, "unexpected exception");
+    }
+}
+
+int cpapr_phi_coo(const cpapr_coo* X, int32_t mode, int32_t R, const double* B, const double* const* A, double eps,
+                  double* Phi, void* ws, size_t ws_bytes, void* stream)
+{
+    try {
+        return report(cpapr::phi_transient(X, mode, R, B, A, eps, Phi, (char*)ws, ws_bytes, (hipStream_t)stream));
+    } catch (...) {
+        return fail(CPAPR_EINVAL, "unexpected exception");
+    }
+}
+
 int cpapr_mu_inner(cpapr_plan* plan, int32_t mode, double* B, const double* const* A, double* Phi_last,
                    cpapr_stats* out, void* stream)
 {
@@ -516,6 +612,36 @@ int cpapr_pdnr_inner(cpapr_plan* plan, int32_t mode, double* B, const double* co
                      void* stream)
 {
     return rows_inner(plan, CPAPR_METHOD_PDNR, mode, B, A, out, stream);
+}
+
+int cpapr_row_stats(cpapr_plan* plan, int32_t mode, int32_t* steps, double* viol, void* stream)
+{
+    try {
+        Error e = check_plan_call(plan, mode);
+        if (e.code) return report(e);
+        const int32_t* s_src = nullptr;
+        const double* v_src = nullptr;
+        if (plan->params.method == CPAPR_METHOD_PQNR) {
+            s_src = plan->pq.steps;
+            v_src = plan->pq.viol;
+        } else if (plan->params.method == CPAPR_METHOD_PDNR) {
+            s_src = plan->pd.steps;
+            v_src = plan->pd.viol;
+        } else {
+            return fail(CPAPR_EINVAL, "the plan was not created for row solves (PQNR or PDNR)");
+        }
+        const int64_t rows = plan->dims[mode];
+        hipStream_t s = (hipStream_t)stream;
+        if (steps && rows > 0)
+            if (hipMemcpyAsync(steps, s_src, (size_t)rows * sizeof(int32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return fail(CPAPR_EHIP, "hipMemcpyAsync of the row steps failed");
+        if (viol && rows > 0)
+            if (hipMemcpyAsync(viol, v_src, (size_t)rows * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return fail(CPAPR_EHIP, "hipMemcpyAsync of the row violations failed");
+        return CPAPR_OK;
+    } catch (...) {
+        return fail(CPAPR_EINVAL, "unexpected exception");
+    }
 }
 
 int cpapr_solve(cpapr_plan* plan, double* lambda, double* const* A, cpapr_stats* out, void* stream)

@@ -195,8 +195,9 @@ constexpr int kPartials = 512;   // blocks of the two-level deterministic column
 
 // ---- plan construction (sort.hip) ----
 int64_t sort_scratch_bytes(int64_t nnz, int N);
-// Validates coordinates/values, then builds the sorted copies of every mode.
-Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t s);
+// Validates coordinates/values, then builds the sorted copies of every mode
+// (only >= 0: of that mode alone).
+Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t s, int only = -1);
 
 // ---- Phi (phi.hip) ----
 // Whether a Phi kernel exists for this lane group, rank block and mode count.
@@ -283,6 +284,15 @@ Error launch_loglik(const cpapr_plan* P, const double* lam, const double* const*
 Error launch_loglik_terms(const cpapr_plan* P, const double* B, const double* const* A, double eps, double* partial,
                           int* nparts, hipStream_t s);
 int64_t loglik_partials(int64_t nnz);
+
+// ---- transient Phi without a plan (api.hip) ----
+// Workspace bytes of a transient Phi for N modes and nnz nonzeros.
+size_t transient_bytes(int N, int64_t nnz);
+// Validate X and `mode`, sort the mode into `ws`, run Phi; waits for the stream.
+Error phi_transient(const cpapr_coo* X, int32_t mode, int32_t R, const double* B, const double* const* A,
+                    double eps, double* Phi, char* ws, size_t ws_bytes, hipStream_t s);
+// Argument checks of a transient Phi that touch no device memory.
+Error check_transient(const cpapr_coo* X, int32_t mode, int32_t R, bool need_data);
 
 // ---- error message of the last failing entry point (api.hip, thread-local) ----
 void set_last_error(const std::string& msg);

@@ -191,6 +191,61 @@ struct TileShared {
     Staged<NM1> stage[NG * BATCH];
 };
 
+// Ordered merge of the head/tail partial rows a tile's lane groups left in
+// LDS; rows crossing the tile boundary go out with atomics (or, in the
+// deterministic mode, as kept partials), all others with plain stores. Called
+// by every thread of the workgroup after a barrier.
+template <int G, int RPL>
+__device__ __forceinline__ void tile_merge(const PhiArgs& a, int64_t tile, int64_t tile_start, int64_t tile_end,
+                                           const double (*part)[G * RPL], const int* prow)
+{
+    constexpr int NG = kBlock / G;
+    constexpr int W = G * RPL;
+    const int t = threadIdx.x;
+    const int R = a.R;
+    const int64_t nnz = a.nnz;
+    if (t < R && t < W) {
+        const int prev_row = tile_start > 0 ? a.rows[tile_start - 1] : -1;
+        const int next_row = tile_end < nnz ? a.rows[tile_end] : -1;
+        int run = -1;
+        double v = 0.0;
+        // Deterministic mode: the tile-end rows' partials are kept (head: the row
+        // continuing from the previous tile; tail: a row starting here and
+        // continuing) and summed in tile order by det_fixup_kernel.
+        double* det = a.det_part;
+        if (det != nullptr && t == 0) {
+            a.det_rows[2 * tile] = -1;
+            a.det_rows[2 * tile + 1] = -1;
+        }
+        auto emit = [&](int row, double val) {
+            double* dst = a.Phi + (int64_t)row * R + t;
+            if (row == prev_row || row == next_row) {
+                if (det == nullptr) {
+                    unsafeAtomicAdd(dst, val);
+                } else {
+                    const int side = row == prev_row ? 0 : 1;
+                    det[((int64_t)side * a.det_tiles + tile) * R + t] = val;
+                    if (t == 0) a.det_rows[2 * tile + side] = row;
+                }
+            } else {
+                *dst = val;
+            }
+        };
+        for (int e = 0; e < 2 * NG; ++e) {
+            const int re = prow[e];
+            if (re < 0) continue;
+            if (re == run) {
+                v += part[e][t];
+            } else {
+                if (run >= 0) emit(run, v);
+                run = re;
+                v = part[e][t];
+            }
+        }
+        if (run >= 0) emit(run, v);
+    }
+}
+
 // One workgroup tile of consecutive sorted nonzeros (tile index `tile` of the
 // operand set `a`).
 template <int G, int RPL, int NM1, bool MIXED, int KIND>
@@ -199,7 +254,6 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
     using T = double;  // arithmetic: FP64 in both precisions
     using L = typename std::conditional<MIXED, float, double>::type;  // the factors as stored
     constexpr int NG = kBlock / G;
-    constexpr int W = G * RPL;
     constexpr int U = gather_depth<NM1, RPL>();
     constexpr int BATCH = TileShared<G, RPL, NM1>::BATCH;
     constexpr int EPL = BATCH / G;  // staged entries loaded by each lane
@@ -478,48 +532,217 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
     if (cur >= 0) flush(cur, nseg == 1 ? 0 : 1);
     __syncthreads();
 
-    // Ordered merge of the head/tail partials; rows crossing the tile boundary
-    // go out with atomics, all others with plain stores.
-    if (t < R && t < W) {
-        const int prev_row = tile_start > 0 ? a.rows[tile_start - 1] : -1;
-        const int next_row = tile_end < nnz ? a.rows[tile_end] : -1;
-        int run = -1;
-        double v = 0.0;
-        // Deterministic mode: the tile-end rows' partials are kept (head: the row
-        // continuing from the previous tile; tail: a row starting here and
-        // continuing) and summed in tile order by det_fixup_kernel.
-        double* det = a.det_part;
-        if (det != nullptr && t == 0) {
-            a.det_rows[2 * tile] = -1;
-            a.det_rows[2 * tile + 1] = -1;
-        }
-        auto emit = [&](int row, double val) {
-            double* dst = a.Phi + (int64_t)row * R + t;
-            if (row == prev_row || row == next_row) {
-                if (det == nullptr) {
-                    unsafeAtomicAdd(dst, val);
-                } else {
-                    const int side = row == prev_row ? 0 : 1;
-                    det[((int64_t)side * a.det_tiles + tile) * R + t] = val;
-                    if (t == 0) a.det_rows[2 * tile + side] = row;
-                }
-            } else {
-                *dst = val;
-            }
-        };
-        for (int e = 0; e < 2 * NG; ++e) {
-            const int re = prow[e];
-            if (re < 0) continue;
-            if (re == run) {
-                v += part[e][t];
-            } else {
-                if (run >= 0) emit(run, v);
-                run = re;
-                v = part[e][t];
-            }
-        }
-        if (run >= 0) emit(run, v);
+    tile_merge<G, RPL>(a, tile, tile_start, tile_end, part, prow);
+}
+
+// Nonzeros per lane group per round of the reduce-scatter Phi tile.
+#ifndef CPAPR_XR_Q
+#define CPAPR_XR_Q 4
+#endif
+
+// LDS of one reduce-scatter tile: the merge rows and staged nonzeros of the
+// plain tile, plus per lane group the Q x G partial dot products of a round
+// (padded by two words so that rows of different groups start on different
+// banks) and the round's Q scales.
+template <int G, int RPL, int NM1, int Q>
+struct XrShared {
+    static constexpr int NG = kBlock / G;
+    static constexpr int BATCH = G;  // nonzeros staged per lane group per batch
+    static constexpr int RSTR = Q * G + 2;
+    double part[2 * NG][G * RPL];
+    int prow[2 * NG];
+    Staged<NM1> stage[NG * BATCH];
+    double red[NG * RSTR];
+    double sv[NG * Q];
+};
+
+// Phi over one tile, the dot products reduced across the lane group by a
+// reduce-scatter instead of an all-reduce per nonzero. A lane group takes Q
+// consecutive nonzeros of its sub-chunk per round: every lane gathers its rank
+// slice of the Q pi rows and forms its Q partial dot products; the partials go
+// to LDS, where lane q of the group sums the G partials of nonzero q (a fixed
+// order) and forms the one scale s_q = x_q / max(m_q, eps) for it; the Q scales
+// are read back by every lane and scattered into the register Phi row as in
+// the plain tile. Per round that is one sum of G terms and one division per
+// nonzero in one lane instead of a log2(G)-step all-reduce and a division in
+// all G lanes, and Q nonzeros' gathers in flight per lane group.
+template <int G, int RPL, int NM1, bool MIXED, int Q>
+__device__ __forceinline__ void phi_tile_xr(const PhiArgs& a, int64_t tile, XrShared<G, RPL, NM1, Q>& sh)
+{
+    using L = typename std::conditional<MIXED, float, double>::type;
+    constexpr int NG = kBlock / G;
+    constexpr int BATCH = XrShared<G, RPL, NM1, Q>::BATCH;
+    constexpr int RSTR = XrShared<G, RPL, NM1, Q>::RSTR;
+    static_assert(BATCH % Q == 0 && Q <= G, "a batch holds whole rounds; one divider lane per nonzero");
+    auto& part = sh.part;
+    auto& prow = sh.prow;
+
+    const int t = threadIdx.x;
+    const int g = t / G;
+    const int lane = t % G;
+    const int R = a.R;
+    const int64_t nnz = a.nnz;
+    const int64_t tile_start = (int64_t)tile * NG * a.L;
+    const int64_t tile_end = min(tile_start + (int64_t)NG * a.L, nnz);
+    const int64_t p0 = tile_start + (int64_t)g * a.L;
+    const int64_t p1 = min(p0 + (int64_t)a.L, nnz);
+    double* red = sh.red + g * RSTR;
+    double* sv = sh.sv + g * Q;
+    Staged<NM1>* my = sh.stage + g * BATCH;
+
+    if (lane == 0) {
+        prow[2 * g] = -1;
+        prow[2 * g + 1] = -1;
     }
+    const int colbase = min(lane * RPL, R - RPL);
+    bool own[RPL];
+#pragma unroll
+    for (int c = 0; c < RPL; ++c) own[c] = colbase + c >= lane * RPL && colbase + c < R;
+
+    int cur = -1;
+    int nseg = 0;
+    double acc[RPL], bcur[RPL];
+#pragma unroll
+    for (int c = 0; c < RPL; ++c) acc[c] = bcur[c] = 0.0;
+
+    auto flush = [&](int row, int kind) {
+        if (kind == 2) {
+            double* dst = a.Phi + (int64_t)row * R + colbase;
+#pragma unroll
+            for (int c = 0; c < RPL; ++c)
+                if (own[c]) dst[c] = acc[c];
+        } else {
+            const int e = 2 * g + kind;
+#pragma unroll
+            for (int c = 0; c < RPL; ++c)
+                if (own[c]) part[e][colbase + c] = acc[c];
+            if (lane == 0) prow[e] = row;
+        }
+    };
+
+    const L* fac[NM1];
+#pragma unroll
+    for (int m = 0; m < NM1; ++m) fac[m] = (const L*)a.fac[m];
+
+    // metadata of the next batch in registers while the current one is processed
+    Staged<NM1> pre;
+    auto load_meta = [&](int64_t base) {
+        const int64_t p = base + lane;
+        if (p < p1) {
+            pre.row = a.rows[p];
+#pragma unroll
+            for (int m = 0; m < NM1; ++m) pre.c[m] = a.cofs[(int64_t)m * nnz + p];
+            pre.x = a.vals[p];
+        }
+    };
+    if (p0 < p1) load_meta(p0);
+
+    for (int64_t base = p0; base < p1; base += BATCH) {
+        const int cnt = (int)min((int64_t)BATCH, p1 - base);
+        if (lane < cnt) my[lane] = pre;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (base + BATCH < p1) load_meta(base + BATCH);
+
+        for (int q0 = 0; q0 < cnt; q0 += Q) {
+            const int nq = min(Q, cnt - q0);
+            // gathers of the round's pi rows, and the B rows of rows starting here
+            L fu[Q][NM1][RPL];
+            double bq[Q][RPL];
+            int rowq[Q];
+            bool newr[Q];
+            int prev = cur;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                newr[q] = false;
+                rowq[q] = prev;
+                if (q < nq) {
+                    const Staged<NM1> e = my[q0 + q];
+                    rowq[q] = e.row;
+                    newr[q] = e.row != prev;
+                    prev = e.row;
+#pragma unroll
+                    for (int m = 0; m < NM1; ++m) {
+                        const L* f = fac[m] + (uint64_t)e.c[m] + colbase;
+#pragma unroll
+                        for (int c = 0; c < RPL; ++c) fu[q][m][c] = f[c];
+                    }
+                    if (newr[q]) {
+                        const double* brow = a.B + (int64_t)e.row * R + colbase;
+#pragma unroll
+                        for (int c = 0; c < RPL; ++c) bq[q][c] = own[c] ? brow[c] : 0.0;
+                    }
+                }
+            }
+            // pi rows and this lane's partial dot products
+            double pi[Q][RPL];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                if (newr[q]) {
+#pragma unroll
+                    for (int c = 0; c < RPL; ++c) bcur[c] = bq[q][c];
+                }
+                if (q < nq) {
+                    double d = 0.0;
+#pragma unroll
+                    for (int c = 0; c < RPL; ++c) {
+                        double v = (double)fu[q][0][c];
+#pragma unroll
+                        for (int m = 1; m < NM1; ++m) v *= (double)fu[q][m][c];
+                        pi[q][c] = v;
+                        d = __builtin_fma(bcur[c], v, d);
+                    }
+                    red[q * G + lane] = d;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // lane q: the whole dot product of nonzero q and its scale
+            if (lane < nq) {
+                double m = 0.0;
+#pragma unroll
+                for (int j = 0; j < G; ++j) m += red[lane * G + j];
+                sv[lane] = div_pos(my[q0 + lane].x, m > a.eps ? m : a.eps);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            double s[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) s[q] = sv[q];
+            // scatter into the register Phi row; a row change flushes the previous row
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                if (q < nq) {
+                    if (newr[q]) {
+                        if (cur >= 0) flush(cur, nseg == 1 ? 0 : 2);
+                        cur = rowq[q];
+                        ++nseg;
+#pragma unroll
+                        for (int c = 0; c < RPL; ++c) acc[c] = 0.0;
+                    }
+#pragma unroll
+                    for (int c = 0; c < RPL; ++c) acc[c] = __builtin_fma(s[q], pi[q][c], acc[c]);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    if (cur >= 0) flush(cur, nseg == 1 ? 0 : 1);
+    __syncthreads();
+    tile_merge<G, RPL>(a, tile, tile_start, tile_end, part, prow);
+}
+
+template <int G, int RPL, int NM1, bool MIXED>
+__global__ __launch_bounds__(kBlock) void phi_xr_kernel(PhiArgs a)
+{
+    __shared__ XrShared<G, RPL, NM1, CPAPR_XR_Q> sh;
+    if (a.done != nullptr && *a.done) return;
+    phi_tile_xr<G, RPL, NM1, MIXED, CPAPR_XR_Q>(a, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 
 template <int G, int RPL, int NM1, bool MIXED, int KIND>
@@ -777,6 +1000,40 @@ Error dispatch_seg_n(int G, int RPL, const PhiArgs& a, dim3 grid, hipStream_t s)
     return {CPAPR_EUNSUPPORTED, "no Phi kernel for this lane-group / rank-block shape and mode count"};
 }
 
+// Shapes the reduce-scatter tile is built for: 8 or 16 lanes per nonzero, up
+// to 8 gathered words per lane and nonzero (its Q rounds keep them in
+// registers).
+bool xr_shape_supported(int G, int RPL, int NM1) { return (G == 8 || G == 16) && NM1 * RPL <= 8; }
+
+template <bool MIXED>
+Error dispatch_xr(int G, int RPL, const PhiArgs& a, hipStream_t s)
+{
+    const int NG = kBlock / G;
+    const int64_t tiles = cdiv(a.nnz, (int64_t)NG * a.L);
+    if (tiles <= 0) return {CPAPR_OK, ""};
+    if (tiles > 0x7fffffff) return {CPAPR_EUNSUPPORTED, "too many tiles"};
+    const dim3 grid((unsigned)tiles);
+#define CPAPR_XR_CASE(GG, RR, NN)                                                     \
+    if (G == GG && RPL == RR && a.NM1 == NN) {                                        \
+        phi_xr_kernel<GG, RR, NN, MIXED><<<grid, kBlock, 0, s>>>(a);                  \
+        CPAPR_LAUNCHED();                                                             \
+        return {CPAPR_OK, ""};                                                        \
+    }
+#define CPAPR_XR_N(GG, RR) CPAPR_XR_CASE(GG, RR, 1) CPAPR_XR_CASE(GG, RR, 2) CPAPR_XR_CASE(GG, RR, 3) \
+    CPAPR_XR_CASE(GG, RR, 4)
+    CPAPR_XR_N(8, 1)
+    CPAPR_XR_N(8, 2)
+    CPAPR_XR_N(16, 1)
+    CPAPR_XR_N(16, 2)
+    CPAPR_XR_CASE(8, 4, 1)
+    CPAPR_XR_CASE(8, 4, 2)
+    CPAPR_XR_CASE(16, 4, 1)
+    CPAPR_XR_CASE(16, 4, 2)
+#undef CPAPR_XR_N
+#undef CPAPR_XR_CASE
+    return {CPAPR_EUNSUPPORTED, "no reduce-scatter Phi kernel for this shape"};
+}
+
 template <bool MIXED, int KIND>
 Error dispatch_seg(int G, int RPL, const PhiArgs& a, hipStream_t s)
 {
@@ -959,7 +1216,10 @@ Error launch_phi(const cpapr_plan* P, int mode, const double* B, const void* con
     Error e = attach_det(P, a);
     if (e.code) return e;
     prof_begin(mode, s);
-    e = mixed ? dispatch_seg<true, kPhi>(G, RPL, a, s) : dispatch_seg<false, kPhi>(G, RPL, a, s);
+    if (P->params.variant == CPAPR_VARIANT_XR && xr_shape_supported(G, RPL, a.NM1))
+        e = mixed ? dispatch_xr<true>(G, RPL, a, s) : dispatch_xr<false>(G, RPL, a, s);
+    else
+        e = mixed ? dispatch_seg<true, kPhi>(G, RPL, a, s) : dispatch_seg<false, kPhi>(G, RPL, a, s);
     prof_end(s);
     if (e.code) return e;
     return launch_det_fixup(P, mode, a, Phi, done, s);

@@ -333,7 +333,7 @@ int64_t sort_scratch_bytes(int64_t nnz, int N)
     return (int64_t)b;
 }
 
-Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t s)
+Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t s, int only)
 {
     const int64_t nnz = P->nnz;
     const int N = P->N;
@@ -377,6 +377,7 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
     if (hflags & 2) return {CPAPR_EVALUE, "a tensor value is not finite and positive"};
 
     for (int n = 0; n < N; ++n) {
+        if (only >= 0 && n != only) continue;
         PlanMode& pm = P->mode[n];
         if (nnz == 0) {
             pm.segments = 0;
@@ -455,7 +456,8 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
     unsigned long long hseg[CPAPR_MAX_MODES] = {};
     CPAPR_HIP(hipMemcpyAsync(hseg, segc, sizeof(unsigned long long) * N, hipMemcpyDeviceToHost, s));
     CPAPR_HIP(hipStreamSynchronize(s));
-    for (int n = 0; n < N; ++n) P->mode[n].segments = (int64_t)hseg[n];
+    for (int n = 0; n < N; ++n)
+        if (only < 0 || n == only) P->mode[n].segments = (int64_t)hseg[n];
     return {CPAPR_OK, ""};
 }
 

@@ -171,3 +171,22 @@ def test_calls_reject_null_plan(lib):
     assert lib.cpapr_plan_segments(None, 0) == -1
     g = C.c_int32(0)
     assert lib.cpapr_plan_shape(None, C.byref(g), C.byref(g)) == -1
+
+
+def test_phi_coo_workspace_size(lib):
+    """Transient Phi's workspace: one mode's sorted copy plus its sort's
+    scratch; grows with nnz; rejects a bad mode or rank (host checks only)."""
+    import ctypes as C
+    def size(dims, nnz, mode, R):
+        d = (C.c_int64 * len(dims))(*dims)
+        coo = cpapr.cpapr_coo(len(dims), C.cast(d, C.POINTER(C.c_int64)), nnz, None, None)
+        n = C.c_size_t(0)
+        rc = lib.cpapr_phi_coo_workspace_size(C.byref(coo), mode, R, C.byref(n))
+        return rc, n.value
+    rc1, a = size([40, 30, 20], 1000, 0, 8)
+    rc2, b = size([40, 30, 20], 100_000, 0, 8)
+    assert rc1 == rc2 == 0 and 0 < a < b
+    assert b >= 100_000 * (4 + 8 + 8)  # at least the sorted copy of one mode
+    assert size([40, 30, 20], 1000, 3, 8)[0] == cpapr.CPAPR_EINVAL
+    assert size([40, 30, 20], 1000, -1, 8)[0] == cpapr.CPAPR_EINVAL
+    assert size([40, 30, 20], 1000, 0, 0)[0] == cpapr.CPAPR_EUNSUPPORTED

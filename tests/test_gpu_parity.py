@@ -2,8 +2,10 @@
 element on the same seeded inputs.
 
 Gate (FP64): normwise and elementwise relative error <= 1e-12, and exact zeros
-where the oracle has exact zeros (rows without nonzeros). Mixed precision
-(FP32-stored factors, compensated FP32 sums): <= 1e-5. Sizes span many tiles
+where the oracle has exact zeros (rows without nonzeros); factor matrices of
+whole solves are held column-wise (every entry against its column's largest,
+see assert_iterate_parity). Mixed precision (FP32-stored factors widened to
+FP64 as they are gathered): <= 1e-5. Sizes span many tiles
 and a ragged tail; the edge cases cover empty and single-entry tensors, empty
 rows, clamped divisors, duplicates, one row spanning the whole tensor, every
 supported lane-group / rank-block shape, and N from 2 to 8."""
@@ -12,7 +14,7 @@ import pytest
 
 import oracle
 from paper_2307_03276_amd import cpapr, synth
-from tests.gpu_util import assert_parity, dev, host
+from tests.gpu_util import assert_iterate_parity, assert_parity, dev, host
 
 pytestmark = pytest.mark.gpu
 
@@ -286,9 +288,12 @@ def _solve_case(X, M, kmax, lmax, tau, tol, elementwise=True, **kw):
     assert bool(st["converged"]) == ost["converged"]
     assert_parity(host(lam), out.lam, tol, "lambda")
     for n in range(X.nmodes):
-        assert_parity(host(A[n]), out.factors[n], tol, f"A{n}", elementwise=elementwise)
+        if elementwise:
+            assert_iterate_parity(host(A[n]), out.factors[n], tol, f"A{n}")
+        else:
+            assert_parity(host(A[n]), out.factors[n], tol, f"A{n}", elementwise=False)
     ll = oracle.loglik(X, out)
-    assert abs(st["loglik"] - ll) <= max(tol, 1e-12) * abs(ll) * 10
+    assert abs(st["loglik"] - ll) <= max(tol, 1e-12) * abs(ll)
     P.close()
     return st, ost
 
@@ -302,7 +307,7 @@ def test_solve_to_kkt_tolerance_with_shift():
     X = synth.random_tensor(21, (60, 50, 40, 8), 12_000, zipf=(1.2, 1.2, None, None))
     M = synth.random_model(21, X.dims, 6)
     M.factors[0][3, 2] = 0.0  # an inadmissible zero for the S shift to lift
-    st, ost = _solve_case(X, M, 30, 10, 1e-4, 1e-10)
+    st, ost = _solve_case(X, M, 30, 10, 1e-4, TOL64)
 
 
 @pytest.mark.parametrize("dims,R,nnz,seed", [
@@ -315,7 +320,7 @@ def test_solve_unusual_shapes(dims, R, nnz, seed):
     """Full fixed-schedule solves at the edges of the supported shapes."""
     X = synth.random_tensor(seed, dims, nnz)
     M = synth.random_model(seed, dims, R)
-    _solve_case(X, M, 3, 4, 0.0, 1e-11)
+    _solve_case(X, M, 3, 4, 0.0, TOL64)
 
 
 def test_solve_all_duplicates():
@@ -325,7 +330,7 @@ def test_solve_all_duplicates():
     idx = np.tile(np.array([[3], [2], [4]], dtype=np.int32), (1, 500))
     X = synth.SparseTensor(dims, idx, np.full(500, 2.0))
     M = synth.random_model(35, dims, 4)
-    _solve_case(X, M, 3, 5, 0.0, 1e-11)
+    _solve_case(X, M, 3, 5, 0.0, TOL64)
 
 
 def test_solve_mixed_precision_fixed_schedule():
@@ -341,7 +346,7 @@ def test_loglik_matches_oracle():
     P = cpapr.Plan.from_tensor(X, 16)
     got = P.loglik(dev(M.lam), [dev(a) for a in M.factors])
     ref = oracle.loglik(X, M)
-    assert abs(got - ref) <= 1e-12 * abs(ref) * 10
+    assert abs(got - ref) <= TOL64 * abs(ref)
     P.close()
 
 
@@ -386,3 +391,60 @@ def test_phi_and_inner_loop_random_sweep():
         Bo, _, _, _ = oracle.mu_inner(X, n, Bh, M.factors, lmax=3)
         assert_parity(host(B), Bo, tol, f"case {case} inner loop", elementwise=not mixed)
         P.close()
+
+
+@pytest.mark.parametrize("dims,R,nnz,zipf", [
+    ((100, 80, 60), 10, 10_000, None),
+    ((300, 200, 50), 16, 30_001, (1.1, None, 1.2)),
+    ((50, 60), 5, 4_000, (1.1, 1.1)),
+    ((9, 8, 7, 6, 5), 33, 6_000, None),
+    ((40, 30, 20), 8, 0, None),
+])
+def test_phi_coo_transient_matches_oracle(dims, R, nnz, zipf):
+    """Phi of a COO tensor without a plan (the one mode sorted into a caller
+    workspace): every mode against the oracle; an empty tensor gives Phi = 0."""
+    import torch
+    X = synth.random_tensor(61, dims, nnz, zipf=zipf or ())
+    M = synth.random_model(61, dims, R)
+    idx, vals = dev(X.idx), dev(X.vals)
+    A = [dev(a) for a in M.factors]
+    for n in range(len(dims)):
+        Bh = M.factors[n] * M.lam
+        out = torch.full((dims[n], R), 7.0, dtype=torch.float64, device="cuda")  # overwritten
+        cpapr.phi_coo(X.dims, idx, vals, n, R, dev(Bh), A, out=out)
+        assert_parity(host(out), oracle.phi(X, n, Bh, M.factors), TOL64, f"mode {n}")
+
+
+def test_phi_coo_rejects_bad_input_and_workspace():
+    import torch
+    X = synth.random_tensor(62, (30, 20, 10), 500)
+    M = synth.random_model(62, X.dims, 4)
+    idx, vals = dev(X.idx), dev(X.vals)
+    A = [dev(a) for a in M.factors]
+    B = dev(M.factors[0] * M.lam)
+    out = torch.empty((30, 4), dtype=torch.float64, device="cuda")
+    coo = cpapr.make_coo(X.dims, idx, vals)
+    need = cpapr.cpapr_phi_coo_workspace_size(coo, 0, 4)
+    small = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(cpapr.CpaprError) as ei:
+        cpapr.cpapr_phi_coo(coo, 0, 4, B, A, 1e-10, out, small)
+    assert ei.value.code == cpapr.CPAPR_EWORKSPACE
+    bad = X.idx.copy()
+    bad[1, 17] = 20  # outside mode 1
+    with pytest.raises(cpapr.CpaprError) as ei:
+        cpapr.phi_coo(X.dims, dev(bad), vals, 0, 4, B, A, out=out)
+    assert ei.value.code == cpapr.CPAPR_EINDEX
+    with pytest.raises(cpapr.CpaprError) as ei:
+        cpapr.phi_coo(X.dims, idx, vals, 3, 4, B, A, out=out)
+    assert ei.value.code == cpapr.CPAPR_EINVAL
+
+
+@pytest.mark.parametrize("dims,R", [((300, 200, 50), 8), ((300, 200, 50), 16), ((300, 200, 50), 30),
+                                    ((60, 50), 16), ((40, 30, 20, 10), 10)])
+def test_phi_xr_variant_matches_oracle(dims, R):
+    """The reduce-scatter tile (CPAPR_VARIANT_XR) on the shapes it is built
+    for (8 lanes x 1, 2 or 4 columns; N = 2..4), in both precisions."""
+    X = synth.random_tensor(81, dims, 25_000, zipf=(1.1,) * len(dims))
+    M = synth.random_model(81, dims, R)
+    _phi_case(X, M, variant=cpapr.CPAPR_VARIANT_XR)
+    _phi_case(X, M, variant=cpapr.CPAPR_VARIANT_XR, precision=cpapr.CPAPR_MIXED, tol=TOLMIX)

@@ -49,9 +49,31 @@ def test_pqnr_short_schedule_lockstep(lmax):
     P.close()
 
 
+def _oracle_counts_near(X, n, Bh, factors, row, tau, lmax):
+    """Step counts the oracle takes for `row` from starting points within the
+    parity gate of the given one: the row of Bh scaled entrywise by 1 + a*xi,
+    xi ~ U(-1, 1) seeded, a = 1e-13 and 1e-12, 16 draws each."""
+    counts = set()
+    for amp in (1e-13, 1e-12):
+        for seed in range(16):
+            xi = np.random.default_rng(seed).uniform(-1.0, 1.0, Bh.shape[1])
+            Bp = Bh.copy()
+            Bp[row] *= 1.0 + amp * xi
+            _, o = oracle.pqnr_inner(X, n, Bp, factors, lmax=lmax, tau=tau, rows=[row])
+            counts.add(int(o["steps"][row]))
+    return counts
+
+
 @pytest.mark.parametrize("dims,R,nnz", [((100, 80, 60), 10, 10_000), ((40, 30, 20, 10), 4, 3000),
                                         ((60, 50, 40), 32, 8000), ((30, 25, 20), 70, 4000)])
 def test_pqnr_converged_rows_match_oracle(dims, R, nnz):
+    """Rows stop at their first KKT test below tau; the step count of every row
+    is compared. Near a row's optimum the quasi-Newton decisions (which pair
+    to keep, whether a trial decreases the objective enough) are taken on
+    differences at the rounding level, so some rows' counts move when their
+    starting point moves within the parity gate, in the oracle itself. A row's
+    GPU count must equal the oracle's, or be a count the oracle also takes
+    from a starting point within the gate (1e-13 or 1e-12 relative)."""
     X = synth.random_tensor(11, dims, nnz, zipf=(1.1,) + (None,) * (len(dims) - 1))
     M = synth.random_model(11, dims, R)
     tau = 1e-9
@@ -61,11 +83,17 @@ def test_pqnr_converged_rows_match_oracle(dims, R, nnz):
         Bh = M.factors[n] * M.lam
         B = dev(Bh)
         st = P.pqnr_inner(n, B, A)
+        steps_g, viol_g = P.row_stats(n)
         Bo, ost = oracle.pqnr_inner(X, n, Bh, M.factors, lmax=200, tau=tau)
         assert st["kkt_violation"] < tau and ost["last_viol"] < tau
-        # a row whose violation lands within rounding of tau may stop one step
-        # earlier or later on either side (the GPU's atomic summation order varies)
-        assert abs(st["row_steps"] - ost["row_steps"]) <= max(4, ost["row_steps"] // 50)
+        assert np.all(viol_g < tau)
+        steps_o = ost["steps"]
+        assert int(steps_g.sum()) == st["row_steps"] and int(steps_o.sum()) == ost["row_steps"]
+        for i in np.flatnonzero(steps_g != steps_o):
+            near = _oracle_counts_near(X, n, Bh, M.factors, i, tau, 200)
+            print(f"mode {n} row {i}: steps gpu {steps_g[i]} oracle {steps_o[i]}; oracle from starts within the gate: "
+                  f"{sorted(near)}", flush=True)
+            assert steps_g[i] in near, f"mode {n} row {i}"
         # both within tau of KKT at the same row optimum
         assert_parity(host(B), Bo, 1e-6, f"converged B mode {n}", elementwise=False)
     P.close()
