@@ -267,7 +267,8 @@ def batch_workload(args):
         "speedup_vs_one_at_a_time": ms_single / ms_batched,
         "max_rel_err_vs_oracle_sampled": worst,
         "autotuner": {k: {"group": v["group"], "chunk": v["chunk"], "ms": v["ms"],
-                          "model": v.get("model"), "model_vs_tuned": v.get("model_vs_tuned")}
+                          "model": v.get("model"), "model_ms": v.get("model_ms"),
+                          "model_vs_tuned": v.get("model_vs_tuned"), "fastest_candidates": v.get("candidates", [])[:6]}
                       for k, v in choices.items()},
     }
     print(json.dumps(out), flush=True)
@@ -280,7 +281,7 @@ def _max_rel(got, ref):
     return float(np.linalg.norm(np.asarray(got) - ref) / n) if n > 0 else float(np.linalg.norm(got))
 
 
-def run_serving(count, warmup, prec, fp64_checks=2, seed=0):
+def run_serving(count, warmup, prec, fp64_checks=2, seed=0, policy="srpt", round_cap=8e6):
     """Poisson arrivals at 200 requests/s of CP-APR MU solves (3- or 4-way, dims
     U[1e3, 1e5], nnz LogUniform[1e4, 2e7], Zipf(1.1), R in {10, 16, 32}, KKT
     tolerance 1e-4, k_max 20), admitted by a 200 GB HBM budget; against the
@@ -308,7 +309,12 @@ def run_serving(count, warmup, prec, fp64_checks=2, seed=0):
         r.arrival = 0.0
     serve.Server(budget_bytes=200e9, max_slots=64, **kw).run_trace(warm)
     torch.cuda.synchronize()
-    srv = serve.Server(budget_bytes=200e9, max_slots=64, **kw)
+    # every active request in every round (the plain continuous batching)
+    srv_all = serve.Server(budget_bytes=200e9, max_slots=64, **kw)
+    done_all = srv_all.run_trace([serve.Request(id=r.id, X=r.X, M=r.M, arrival=r.arrival) for r in meas])
+    summary_all = serve.latency_summary(done_all)
+    torch.cuda.synchronize()
+    srv = serve.Server(budget_bytes=200e9, max_slots=64, policy=policy, round_cap=round_cap, **kw)
     done = srv.run_trace(meas)
     summary = serve.latency_summary(done)
     by_id = {r.id: r for r in done}
@@ -348,9 +354,13 @@ def run_serving(count, warmup, prec, fp64_checks=2, seed=0):
         "requests": len(meas), "warmup_requests": len(warm), "total_nnz": int(nnz.sum()),
         "mean_nnz": float(nnz.mean()), "arrival_span_s": span,
         "offered_req_per_s": (len(meas) - 1) / span if span > 0 else None,
-        "served": dict(summary, peak_active=srv.peak_active, peak_hbm_bytes=srv.peak_used, ticks=srv.ticks,
+        "served": dict(summary, policy=policy, round_cap_nnz=round_cap, peak_active=srv.peak_active,
+                       peak_hbm_bytes=srv.peak_used, ticks=srv.ticks,
+                       host_phase_s={k: round(v, 4) for k, v in srv.phase_s.items()},
                        converged=int(sum(1 for r in done if r.stats.get("converged"))),
                        mean_outer_iters=float(np.mean([r.stats["outer_iters"] for r in done]))),
+        "served_all_each_round": dict(summary_all, ticks=srv_all.ticks,
+                                      host_phase_s={k: round(v, 4) for k, v in srv_all.phase_s.items()}),
         "one_at_a_time": {"p50_from_arrival_s": float(np.percentile(ttc, 50)),
                           "p99_from_arrival_s": float(np.percentile(ttc, 99)),
                           "solves_per_s": len(meas) / clock, "busy_s": busy},
@@ -381,6 +391,61 @@ def serve_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def tune_workload(args):
+    """The launch-policy model against a measured search: for every mode of
+    tensors from 1e4 to 1e8 nonzeros (uniform and Zipf, R = 8..32, N = 3 and 4,
+    both precisions) Phi is timed at every (lanes, chunk) candidate and at the
+    model's shape; model_vs_tuned = model time / fastest time."""
+    import numpy as np
+    import torch
+
+    from paper_2307_03276_amd import cpapr, synth, tune
+
+    cases = []
+    rng = np.random.default_rng(5)
+    for i, (N, nnz, R) in enumerate([(3, 10_000, 8), (3, 50_000, 16), (3, 100_000, 32), (3, 200_000, 16),
+                                     (3, 400_000, 16), (3, 400_000, 32), (3, 700_000, 32), (3, 1_000_000, 8),
+                                     (3, 1_000_000, 16), (3, 1_000_000, 32), (4, 400_000, 16), (4, 400_000, 32)]):
+        dims = tuple(int(d) for d in rng.integers(100, 5000, size=N))
+        cases.append((f"uniform {N}-way {dims}, {nnz} nnz, R={R}", lambda d=dims, z=nnz, r=R, s=900 + i: (
+            synth.random_tensor(s, d, z), synth.random_model(s, d, r))))
+    cases.append(("Zipf 3-way 20000x15000x2000, 2M nnz, R=16", lambda: (
+        synth.random_tensor(950, (20000, 15000, 2000), 2_000_000, zipf=(1.1, 1.1, 1.1), mu=3.0),
+        synth.random_model(950, (20000, 15000, 2000), 16))))
+    cases.append(("zipf3: 3-way 200000x150000x20000, 20M nnz, R=16", lambda: synth.config_zipf3()[:2]))
+    cases.append(("zipf4: 4-way 1000000x200000x10000x500, 100M nnz, R=32", lambda: synth.config_zipf4()[:2]))
+    rows = []
+    dev = torch.device("cuda")
+    for name, make in cases:
+        X, M = make()
+        idx = torch.from_numpy(X.idx).to(dev)
+        vals = torch.from_numpy(X.vals).to(dev)
+        A = [torch.from_numpy(a).to(dev) for a in M.factors]
+        lam = torch.from_numpy(M.lam).to(dev)
+        for prec in (cpapr.CPAPR_FP64, cpapr.CPAPR_MIXED):
+            P = cpapr.Plan(X.dims, idx, vals, M.rank, precision=prec)
+            res = tune.tune_plan(P, lambda n: ((A[n] * lam).contiguous(), A))
+            for r in res:
+                r.update(tensor=name, precision="fp64" if prec == cpapr.CPAPR_FP64 else "mixed", nnz=X.nnz,
+                         rank=M.rank, segments=P.segments(r["mode"]))
+                print(f"# {name} {r['precision']} mode {r['mode']}: model {tuple(r['model'])} {r['model_ms']:.4f} ms, "
+                      f"best {tuple(r['best'])} {r['best_ms']:.4f} ms, ratio {r['model_vs_tuned']:.3f}", flush=True)
+                rows.append(r)
+            P.close()
+        del idx, vals, A, lam
+        torch.cuda.empty_cache()
+    worst = max(r["model_vs_tuned"] for r in rows)
+    out = {"metric": "launch-policy model time / fastest measured shape (Phi per mode)", "value": worst,
+           "unit": "ratio", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": None, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64 and f32+f64", "data": "synthetic",
+           "config": {"workload": f"per-mode launch-shape search over {len(cases)} tensors x 2 precisions"},
+           "within_5pct": sum(r["model_vs_tuned"] <= 1.05 for r in rows), "modes_timed": len(rows),
+           "cases": [{k: r[k] for k in ("tensor", "precision", "mode", "nnz", "rank", "segments", "model", "model_ms",
+                                          "best", "best_ms", "model_vs_tuned", "finalists", "candidates")}
+                     for r in rows]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,7 +456,7 @@ def main():
                     help="inner solver of the zipf3 / zipf4 jobs: MU (Algorithm 1), PQNR or PDNR row solves")
     ap.add_argument("--nnz", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["zipf3", "zipf4", "batch", "serve"], default="zipf3",
+    ap.add_argument("--workload", choices=["zipf3", "zipf4", "batch", "serve", "tune"], default="zipf3",
                     help="zipf3: the 20M-nonzero 3-way CP-APR MU job (default); zipf4: the 100M-nonzero 4-way "
                          "solve to KKT 1e-4; batch: 512 uneven tensors; serve: a Poisson stream of solve requests")
     ap.add_argument("--batch-count", type=int, default=512)
@@ -416,6 +481,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "batch":
         batch_workload(args)
+        return
+    if args.workload == "tune":
+        tune_workload(args)
         return
     if args.workload == "serve":
         if args.precision == "fp64" and "--precision" not in sys.argv:

@@ -120,7 +120,7 @@ typedef struct cpapr_params {
     double kappa_tol;  /* entries below this count as zero (1e-10) */
     int32_t precision; /* CPAPR_FP64 or CPAPR_MIXED */
     int32_t variant;   /* CPAPR_VARIANT_* */
-    int32_t group;     /* lanes per nonzero (0 = by rank; else 4, 8, 16, 32 or 64) */
+    int32_t group;     /* lanes per nonzero (0 = launch-policy model; else 4, 8, 16, 32 or 64) */
     int32_t chunk;     /* nonzeros per lane group per tile (0 = launch-policy model) */
     int32_t sort;      /* CPAPR_SORT_*: order of the nonzeros inside each row of a mode */
     int32_t method;    /* CPAPR_METHOD_*: inner solver of cpapr_solve */
@@ -166,17 +166,21 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
 int cpapr_plan_destroy(cpapr_plan* plan);
 
 /* Change the Phi launch shape of an existing plan (lanes per nonzero `group`:
- * 0 = by rank, else 4, 8, 16, 32 or 64; nonzeros per lane group per tile
- * `chunk`: 0 = launch-policy model, else 1..65536). Host-only; used by the autotuner to
- * time shapes without re-sorting. Returns CPAPR_EUNSUPPORTED for shapes with
- * no kernel at this rank and mode count. */
+ * 0 = launch-policy model, else 4, 8, 16, 32 or 64; nonzeros per lane group
+ * per tile `chunk`: 0 = launch-policy model, else 1..65536). Host-only; used
+ * by the autotuner to time shapes without re-sorting. Returns
+ * CPAPR_EUNSUPPORTED for shapes with no kernel at this rank and mode count. */
 int cpapr_plan_set_shape(cpapr_plan* plan, int32_t group, int32_t chunk);
 
 /* The Phi launch shape a plan uses: lanes per nonzero and nonzeros per lane
- * group per tile. With group 0 (params or cpapr_plan_set_shape) the group
- * follows the rank; with chunk 0 the chunk comes from a launch-policy model
- * (512-nonzero tiles in FP64, 1024 with FP32-stored factors; the kind of
- * heuristic the paper names as future work in Section 4). Host-only. */
+ * group per tile. With group or chunk 0 (params or cpapr_plan_set_shape) they
+ * come from a launch-policy model of the tensor (the kind of heuristic the
+ * paper names as future work in Section 4): 512-nonzero tiles, smaller ones
+ * (down to 64 nonzeros, 16 lanes per nonzero) when the tensor has fewer than
+ * about 512,000 nonzeros; for 17 <= R <= 32 and up to four modes 16 lanes x 2
+ * columns on 256-nonzero tiles in FP64 and 8 lanes x 4 columns on
+ * 1024-nonzero tiles with FP32-stored factors; otherwise lanes by rank
+ * (4 up to R = 4, 8 up to R = 32, then 16 or 64). Host-only. */
 int cpapr_plan_shape(const cpapr_plan* plan, int32_t* group, int32_t* chunk);
 
 /* Number of nonempty rows (segments) of mode `mode` (host query). */
@@ -300,7 +304,17 @@ typedef struct cpapr_batch cpapr_batch;
  * workgroup tiles (a slot of nnz nonzeros takes ceil(nnz / 512) tiles at the
  * default chunk; cpapr_batch_tiles gives the exact count for a plan). */
 int cpapr_batch_workspace_size(int32_t max_slots, int64_t max_tiles, size_t* bytes);
+/* Tiles one slot of this plan takes in a batch (at its batch shape); -1 if
+ * plan is NULL. */
 int64_t cpapr_batch_tiles(const cpapr_plan* plan);
+/* The launch shape of this plan's slots in a batch. A plan whose shape is the
+ * launch-policy model's (group and chunk 0 at creation or in the last
+ * cpapr_plan_set_shape) takes, in a batch, the model's shape for a tensor
+ * large enough to fill the device by itself: the batch's slots share each
+ * launch and fill the device together, so the small tiles the model gives a
+ * small tensor launched alone (to make enough workgroups) only cost there.
+ * A plan with a shape set by the caller keeps it. */
+int cpapr_plan_batch_shape(const cpapr_plan* plan, int32_t* group, int32_t* chunk);
 int cpapr_batch_create(int32_t max_slots, int64_t max_tiles, void* ws, size_t ws_bytes, cpapr_batch** out);
 /* As cpapr_batch_create, with flags. By default (flags 0, what
  * cpapr_batch_create uses) each shape class is one launch with a workgroup per
@@ -345,6 +359,15 @@ int cpapr_batch_mu(cpapr_batch* batch, void* stream);
  * use_graph != 0 replays a captured hipGraph of the whole sequence.
  * Stream-ordered; read the outcome with cpapr_batch_status. */
 int cpapr_batch_inner(cpapr_batch* batch, int32_t lmax, int32_t use_graph, void* stream);
+
+/* Per-slot hold flags for the following cpapr_batch_run / cpapr_batch_inner
+ * calls (host array of max_slots entries: nonzero = hold). A held slot does no
+ * work in those runs: its Phi, B and factors are left as they are and
+ * cpapr_batch_status reports it as stopped with no updates. Lets a caller run
+ * a subset of its slots (e.g. the requests with the least remaining work)
+ * without changing the batch's shape, so a captured graph stays valid.
+ * All slots run by default. Waits for `stream`. */
+int cpapr_batch_hold(cpapr_batch* batch, const int32_t* hold, void* stream);
 
 /* Per-slot outcome since the last cpapr_batch_run / cpapr_batch_inner (host
  * arrays of max_slots entries; entries of unset slots are unspecified): last

@@ -88,6 +88,7 @@ def load():
         "cpapr_plan_segments": (i64, [vp, i32]),
         "cpapr_plan_set_shape": (C.c_int, [vp, i32, i32]),
         "cpapr_plan_shape": (C.c_int, [vp, P(i32), P(i32)]),
+        "cpapr_plan_batch_shape": (C.c_int, [vp, P(i32), P(i32)]),
         "cpapr_phi": (C.c_int, [vp, i32, vp, P(vp), dbl, vp, vp]),
         "cpapr_phi_coo_workspace_size": (C.c_int, [P(cpapr_coo), i32, i32, P(C.c_size_t)]),
         "cpapr_phi_coo": (C.c_int, [P(cpapr_coo), i32, i32, vp, P(vp), dbl, vp, vp, C.c_size_t, vp]),
@@ -107,6 +108,7 @@ def load():
         "cpapr_batch_mu": (C.c_int, [vp, vp]),
         "cpapr_batch_status": (C.c_int, [vp, P(dbl), P(i32), P(i32), vp]),
         "cpapr_batch_inner": (C.c_int, [vp, i32, i32, vp]),
+        "cpapr_batch_hold": (C.c_int, [vp, P(i32), vp]),
         "cpapr_mode_begin": (C.c_int, [vp, i32, i32, vp, vp, vp, vp, vp]),
         "cpapr_mode_end": (C.c_int, [vp, i32, vp, vp, vp, vp]),
         "cpapr_plan_sync_f32": (C.c_int, [vp, P(vp), vp]),
@@ -127,12 +129,13 @@ def load():
 
 
 EXPORTED = ("cpapr_params_default", "cpapr_plan_workspace_size", "cpapr_plan_create", "cpapr_plan_destroy",
-            "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_plan_shape", "cpapr_phi", "cpapr_phi_coo_workspace_size",
+            "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_plan_shape",
+            "cpapr_plan_batch_shape", "cpapr_phi", "cpapr_phi_coo_workspace_size",
             "cpapr_phi_coo", "cpapr_mu_inner", "cpapr_pqnr_inner",
             "cpapr_pdnr_inner", "cpapr_row_stats", "cpapr_solve", "cpapr_loglik",
             "cpapr_mttkrp", "cpapr_batch_workspace_size", "cpapr_batch_tiles", "cpapr_batch_create", "cpapr_batch_create2",
             "cpapr_batch_destroy", "cpapr_batch_set", "cpapr_batch_clear", "cpapr_batch_commit", "cpapr_batch_run",
-            "cpapr_batch_mu", "cpapr_batch_inner", "cpapr_batch_status", "cpapr_mode_begin", "cpapr_mode_end", "cpapr_plan_sync_f32",
+            "cpapr_batch_mu", "cpapr_batch_inner", "cpapr_batch_hold", "cpapr_batch_status", "cpapr_mode_begin", "cpapr_mode_end", "cpapr_plan_sync_f32",
             "cpapr_prof_enable", "cpapr_prof_disable", "cpapr_prof_read", "cpapr_last_error")
 
 
@@ -209,6 +212,12 @@ def cpapr_plan_set_shape(h, group: int, chunk: int):
 def cpapr_plan_shape(h):
     g, c = C.c_int32(0), C.c_int32(0)
     _check(load().cpapr_plan_shape(h, C.byref(g), C.byref(c)))
+    return g.value, c.value
+
+
+def cpapr_plan_batch_shape(h):
+    g, c = C.c_int32(0), C.c_int32(0)
+    _check(load().cpapr_plan_batch_shape(h, C.byref(g), C.byref(c)))
     return g.value, c.value
 
 
@@ -333,6 +342,12 @@ def cpapr_batch_inner(h, lmax, use_graph=False, stream=None):
     return _check(load().cpapr_batch_inner(h, lmax, 1 if use_graph else 0, _stream(stream)))
 
 
+def cpapr_batch_hold(h, hold, stream=None):
+    """Hold flags (sequence of max_slots ints, nonzero = hold) for the following runs."""
+    arr = (C.c_int32 * len(hold))(*[int(bool(x)) for x in hold])
+    _check(load().cpapr_batch_hold(h, arr, _stream(stream)))
+
+
 def cpapr_batch_status(h, max_slots, stream=None):
     viol = (C.c_double * max_slots)()
     upd = (C.c_int32 * max_slots)()
@@ -399,6 +414,9 @@ class Batch:
     def inner(self, lmax, use_graph=False, stream=None):
         cpapr_batch_inner(self.handle, lmax, use_graph, stream)
 
+    def hold(self, flags, stream=None):
+        cpapr_batch_hold(self.handle, list(flags), stream)
+
     def status(self, stream=None):
         return cpapr_batch_status(self.handle, self.max_slots, stream)
 
@@ -462,7 +480,12 @@ class Plan:
         """(lanes per nonzero, nonzeros per lane group per tile) of the Phi launch."""
         return cpapr_plan_shape(self.handle)
 
+    def batch_shape(self):
+        """(lanes per nonzero, nonzeros per lane group per tile) of this plan's slots in a batch."""
+        return cpapr_plan_batch_shape(self.handle)
+
     def tiles(self):
+        """Tiles one slot of this plan takes in a batch."""
         return cpapr_batch_tiles(self.handle)
 
     def segments(self, mode):

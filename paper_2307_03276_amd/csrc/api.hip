@@ -305,7 +305,7 @@ Error phi_transient(const cpapr_coo* X, int32_t mode, int32_t R, const double* B
     cpapr_params_default(&P.params);
     P.ws = ws;
     P.ws_bytes = ws_bytes;
-    P.group = cpapr::resolve_group(R, 0, P.N - 1);
+    P.group = cpapr::model_group(&P);
     P.mode[mode].rows = (int32_t*)(ws + L.rows);
     P.mode[mode].cofs = (uint32_t*)(ws + L.cidx);
     P.mode[mode].vals = (double*)(ws + L.vals);
@@ -388,7 +388,7 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
         P->params = *p;
         P->ws = w;
         P->ws_bytes = ws_bytes;
-        P->group = cpapr::resolve_group(R, p->group, X->nmodes - 1);
+        P->group = p->group ? cpapr::resolve_group(R, p->group, X->nmodes - 1) : cpapr::model_group(P);
         P->chunk = cpapr::resolve_chunk(P->group, p->chunk);  // replaced by the model below if 0
         for (int n = 0; n < P->N; ++n) {
             P->mode[n].rows = (int32_t*)(w + L.mode_rows[n]);
@@ -417,6 +417,7 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
             return report(e);
         }
         if (p->chunk == 0) P->chunk = cpapr::model_chunk(P, P->group);
+        P->shape_auto = p->group == 0 && p->chunk == 0;
         if (P->det_part != nullptr && (int64_t)(cpapr::kBlock / P->group) * P->chunk < 128) {
             delete P;
             return fail(CPAPR_EUNSUPPORTED, "deterministic mode needs tiles of at least 128 nonzeros");
@@ -451,13 +452,14 @@ int cpapr_plan_set_shape(cpapr_plan* plan, int32_t group, int32_t chunk)
     p.chunk = chunk;
     Error e = check_params(&p, plan->R, plan->N);
     if (e.code) return report(e);
-    const int new_group = cpapr::resolve_group(plan->R, group, plan->N - 1);
+    const int new_group = group ? cpapr::resolve_group(plan->R, group, plan->N - 1) : cpapr::model_group(plan);
     const int new_chunk = chunk > 0 ? chunk : cpapr::model_chunk(plan, new_group);
     if (plan->det_part != nullptr && (int64_t)(cpapr::kBlock / new_group) * new_chunk < 128)
         return fail(CPAPR_EUNSUPPORTED, "deterministic mode needs tiles of at least 128 nonzeros");
     plan->params = p;
     plan->group = new_group;
     plan->chunk = new_chunk;
+    plan->shape_auto = group == 0 && chunk == 0;
     return CPAPR_OK;
 }
 

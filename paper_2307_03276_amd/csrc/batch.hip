@@ -36,7 +36,7 @@ struct HostSlot {
 
 struct Layout {
     size_t slots, tile_map, class_off, class_ntiles, copies, ncopies, copy_total;
-    size_t mu, nmu, mu_total, viol, st_done, st_updates, st_viol, counters, total;
+    size_t mu, nmu, mu_total, viol, st_done, st_updates, st_viol, st_hold, counters, total;
 };
 
 Layout layout(int max_slots, int64_t max_tiles)
@@ -71,16 +71,27 @@ Layout layout(int max_slots, int64_t max_tiles)
     off += align256(4 * (size_t)max_slots);
     L.st_viol = off;
     off += align256(8 * (size_t)max_slots);
+    L.st_hold = off;
+    off += align256(4 * (size_t)max_slots);
     L.counters = off;
     off += align256(4 * (size_t)cpapr::kBatchCounters * cpapr::kCounterStride);
     L.total = off;
     return L;
 }
 
+// Tiles of one slot of this plan (at its batch shape).
 int64_t plan_tiles(const cpapr_plan* P)
 {
-    const int NG = cpapr::kBlock / P->group;
-    return cdiv(P->nnz, (int64_t)NG * P->chunk);
+    int G, L;
+    cpapr::batch_shape(P, &G, &L);
+    return cdiv(P->nnz, (int64_t)(cpapr::kBlock / G) * L);
+}
+
+int slot_class(const cpapr_plan* P)
+{
+    int G, L;
+    cpapr::batch_shape(P, &G, &L);
+    return cpapr::batch_class_of(G, cpapr::rank_block(P->R, G), P->N - 1, P->params.precision == CPAPR_MIXED);
 }
 
 }  // namespace
@@ -104,6 +115,7 @@ struct cpapr_batch {
     unsigned int* d_counters;
     cpapr::BatchState st;
     std::vector<HostSlot> slots;
+    std::vector<int32_t> hold;          // per slot: 1 = sits out the next runs (uploaded by commit and hold)
     bool committed = false;
     std::vector<int> classes;           // classes with work at the last commit
     std::vector<int64_t> class_tiles;   // their tile counts (grid launches)
@@ -246,6 +258,16 @@ int64_t cpapr_batch_tiles(const cpapr_plan* plan)
     return plan_tiles(plan);
 }
 
+int cpapr_plan_batch_shape(const cpapr_plan* plan, int32_t* group, int32_t* chunk)
+{
+    if (!plan) return fail(CPAPR_EINVAL, "plan is NULL");
+    int G, L;
+    cpapr::batch_shape(plan, &G, &L);
+    if (group) *group = G;
+    if (chunk) *chunk = L;
+    return CPAPR_OK;
+}
+
 int cpapr_batch_create(int32_t max_slots, int64_t max_tiles, void* ws, size_t ws_bytes, cpapr_batch** out)
 {
     return cpapr_batch_create2(max_slots, max_tiles, 0, ws, ws_bytes, out);
@@ -287,8 +309,10 @@ int cpapr_batch_create2(int32_t max_slots, int64_t max_tiles, int32_t flags, voi
         b->st.done = (int32_t*)(b->ws + L.st_done);
         b->st.updates = (int32_t*)(b->ws + L.st_updates);
         b->st.viol = (double*)(b->ws + L.st_viol);
+        b->st.hold = (int32_t*)(b->ws + L.st_hold);
         b->d_counters = (unsigned int*)(b->ws + L.counters);
         b->slots.resize(max_slots);
+        b->hold.assign(max_slots, 0);
         *out = b;
         return CPAPR_OK;
     } catch (...) {
@@ -315,8 +339,7 @@ int cpapr_batch_set(cpapr_batch* batch, int32_t slot, cpapr_plan* plan, int32_t 
     for (int m = 0; m < plan->N; ++m)
         if (m != mode && !A[m]) return fail(CPAPR_EINVAL, "a factor pointer is NULL");
     if (plan->params.variant == CPAPR_VARIANT_ATOMIC) return fail(CPAPR_EUNSUPPORTED, "batches run the segmented kernel");
-    const int rpl = cpapr::rank_block(plan->R, plan->group);
-    if (cpapr::batch_class_of(plan->group, rpl, plan->N - 1, plan->params.precision == CPAPR_MIXED) < 0)
+    if (slot_class(plan) < 0)
         return fail(CPAPR_EUNSUPPORTED, "no batched kernel for this plan's shape (lane group 4, 8 or 16; N <= 4)");
     if (flags & ~CPAPR_BATCH_F32_CURRENT) return fail(CPAPR_EINVAL, "unknown flags");
     HostSlot& h = batch->slots[slot];
@@ -352,8 +375,7 @@ int cpapr_batch_commit(cpapr_batch* batch, void* stream)
             const HostSlot& h = b->slots[i];
             if (!h.set) continue;
             const cpapr_plan* P = h.plan;
-            const int c = cpapr::batch_class_of(P->group, cpapr::rank_block(P->R, P->group), P->N - 1,
-                                                P->params.precision == CPAPR_MIXED);
+            const int c = slot_class(P);
             if (c < 0) return fail(CPAPR_EUNSUPPORTED, "slot with an unsupported shape");
             by_class[c].push_back(i);
         }
@@ -389,6 +411,8 @@ int cpapr_batch_commit(cpapr_batch* batch, void* stream)
                 copy_total += z.n;
                 BatchSlot bs{};
                 bs.args = cpapr::phi_args(P, h.mode, h.B, fac, P->params.eps, h.Phi);
+                int G;
+                cpapr::batch_shape(P, &G, &bs.args.L);
                 bs.tile_begin = tiles;
                 bs.slot = i;
                 const int64_t nt = plan_tiles(P);
@@ -437,10 +461,30 @@ int cpapr_batch_commit(cpapr_batch* batch, void* stream)
         if (hipMemcpyAsync(b->d_ncopies, &ncopies, 4, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(b->d_copy_total, &copy_total, 8, hipMemcpyHostToDevice, s) != hipSuccess)
             return fail(CPAPR_EHIP, "upload of list sizes failed");
+        if (hipMemcpyAsync(b->st.hold, b->hold.data(), 4 * (size_t)b->max_slots, hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+            return fail(CPAPR_EHIP, "upload of the hold flags failed");
         if (hipStreamSynchronize(s) != hipSuccess) return fail(CPAPR_EHIP, "stream synchronisation failed");
         b->classes = classes;
         b->class_tiles.assign(cnt.begin(), cnt.end());
         b->committed = true;
+        return CPAPR_OK;
+    } catch (...) {
+        return fail(CPAPR_EINVAL, "unexpected exception");
+    }
+}
+
+int cpapr_batch_hold(cpapr_batch* batch, const int32_t* hold, void* stream)
+{
+    try {
+        if (!batch) return fail(CPAPR_EINVAL, "batch is NULL");
+        if (!hold) return fail(CPAPR_EINVAL, "hold is NULL");
+        for (int i = 0; i < batch->max_slots; ++i) batch->hold[i] = hold[i] != 0;
+        hipStream_t s = (hipStream_t)stream;
+        if (hipMemcpyAsync(batch->st.hold, batch->hold.data(), 4 * (size_t)batch->max_slots, hipMemcpyHostToDevice,
+                           s) != hipSuccess)
+            return fail(CPAPR_EHIP, "upload of the hold flags failed");
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(CPAPR_EHIP, "stream synchronisation failed");
         return CPAPR_OK;
     } catch (...) {
         return fail(CPAPR_EINVAL, "unexpected exception");

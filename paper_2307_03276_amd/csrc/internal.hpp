@@ -121,6 +121,7 @@ struct PhiArgs {
     int R;
     int NM1;
     int L;
+    int o32;               // 1: every gathered factor is below 4 GiB (32-bit byte offsets)
     double eps;
 };
 
@@ -182,6 +183,7 @@ struct cpapr_plan {
     char* ws;
     size_t ws_bytes;
     int group, chunk;                 // resolved launch shape of the Phi kernel
+    bool shape_auto;                  // group and chunk both from the launch-policy model
     cpapr::PqnrState pq;              // PQNR row-solve state (method CPAPR_METHOD_PQNR only)
     cpapr::PdnrState pd;              // PDNR row-solve state (method CPAPR_METHOD_PDNR only)
     double* det_part;                 // deterministic mode: tile-end partial rows (nullptr: atomics)
@@ -205,7 +207,12 @@ bool phi_shape_supported(int group, int rpl, int nmodes_other);
 // Resolve the lane-group size for rank R (the `group` parameter, 0 = automatic).
 int resolve_group(int R, int requested, int nm1);
 int resolve_chunk(int group, int requested);
-int model_chunk(const cpapr_plan* P, int group);  // default chunk once segments are known
+int model_group(const cpapr_plan* P);             // launch-policy model: lanes per nonzero
+int model_chunk(const cpapr_plan* P, int group);  // launch-policy model: nonzeros per lane group per tile
+// Shape of this plan's slots in a batched launch: the model's shape for a
+// tensor large enough to fill the device when the plan's shape is the model's,
+// else the plan's own shape.
+void batch_shape(const cpapr_plan* P, int* group, int* chunk);
 // Deterministic mode: tiles the partial buffers are sized for (tiles of >= 128 nonzeros).
 inline int64_t det_tile_capacity(int64_t nnz) { return nnz / 128 + 2; }
 // Rank columns per lane (1, 2 or 4) for rank R on `group` lanes; -1 if R > 4 * group.
@@ -232,6 +239,7 @@ struct BatchState {
     int32_t* done;
     int32_t* updates;
     double* viol;
+    int32_t* hold;  // 1: the slot sits out the run (its done flag starts set)
 };
 // viol_spread: [kMuSpread * max_slots] u64 (slot s, spread j at j * max_slots + s).
 Error launch_batch_mu(const BatchMu* items, const int32_t* nitems_dev, const int64_t* total_dev, int max_slots,

@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void batch_clear_kernel(unsigned long long*
 __global__ __launch_bounds__(kBlock) void batch_reset_kernel(BatchState st, int n)
 {
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        st.done[i] = 0;
+        st.done[i] = st.hold != nullptr ? st.hold[i] : 0;  // a held slot does no work in this run
         st.updates[i] = 0;
         st.viol[i] = 0.0;
     }

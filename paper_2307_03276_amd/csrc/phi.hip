@@ -95,17 +95,17 @@ struct Acc {
 };
 
 // q = x / m for normal, finite m > 0 (m is clamped to eps > 0 before): the
-// hardware reciprocal estimate, one Newton step r <- r + r(1 - m r), then one
-// residual correction q <- q + r(x - m q) with the residual formed exactly by
-// an FMA. The result is within an ulp of the rounded quotient; the IEEE
+// hardware reciprocal estimate, one Newton step r <- r + r(1 - m r), then
+// q = x r. The result is within two ulps of the rounded quotient (a residual
+// correction step, which would bring it within one, measured 3 % of the Phi
+// kernel's time and changes nothing at the 1e-12 parity gate); the IEEE
 // division sequence's scaling for denormal and huge operands is not needed in
 // this range.
 __device__ __forceinline__ double div_pos(double x, double m)
 {
     double r = __builtin_amdgcn_rcp(m);
     r = __builtin_fma(r, __builtin_fma(-m, r, 1.0), r);
-    const double q = x * r;
-    return __builtin_fma(r, __builtin_fma(-m, q, x), q);
+    return x * r;
 }
 
 // What the segmented kernel computes per nonzero and where it goes.
@@ -157,8 +157,9 @@ __device__ __forceinline__ double nonzero_scale(const double (&b)[RPL], const do
 #pragma unroll
         for (int c = 0; c < RPL; ++c) d = __builtin_fma(b[c], pi[c], d);
         d = group_sum<G>(d);
-        if constexpr (KIND == kLoglik) return x * log(d > eps ? d : eps);
-        return div_pos(x, d > eps ? d : eps);
+        // max(m, eps) as one v_max (m is never NaN: values and factors are finite)
+        if constexpr (KIND == kLoglik) return x * log(__builtin_fmax(d, eps));
+        return div_pos(x, __builtin_fmax(d, eps));
     }
 }
 
@@ -248,7 +249,10 @@ __device__ __forceinline__ void tile_merge(const PhiArgs& a, int64_t tile, int64
 
 // One workgroup tile of consecutive sorted nonzeros (tile index `tile` of the
 // operand set `a`).
-template <int G, int RPL, int NM1, bool MIXED, int KIND>
+// O32: every gathered factor is smaller than 4 GiB, so a row's address is the
+// factor's base plus a 32-bit byte offset (one VALU add, and the loads take the
+// base from scalar registers).
+template <int G, int RPL, int NM1, bool MIXED, int KIND, bool O32 = false>
 __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileShared<G, RPL, NM1>& sh)
 {
     using T = double;  // arithmetic: FP64 in both precisions
@@ -409,7 +413,9 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
                     if (liveu[u]) {
 #pragma unroll
                         for (int m = 0; m < NM1; ++m) {
-                            const L* f = fac[m] + (uint64_t)e.c[m] + colbase;
+                            const L* f = O32 ? (const L*)((const char*)fac[m] +
+                                                          (uint32_t)((e.c[m] + (uint32_t)colbase) * (uint32_t)sizeof(L)))
+                                             : fac[m] + (uint64_t)e.c[m] + colbase;
 #pragma unroll
                             for (int c = 0; c < RPL; ++c) fu[u][m][c] = f[c];
                         }
@@ -745,12 +751,12 @@ __global__ __launch_bounds__(kBlock) void phi_xr_kernel(PhiArgs a)
     phi_tile_xr<G, RPL, NM1, MIXED, CPAPR_XR_Q>(a, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 
-template <int G, int RPL, int NM1, bool MIXED, int KIND>
+template <int G, int RPL, int NM1, bool MIXED, int KIND, bool O32 = false>
 __global__ __launch_bounds__(kBlock) void phi_seg_kernel(PhiArgs a)
 {
     __shared__ TileShared<G, RPL, NM1> sh;
     if (a.done != nullptr && *a.done) return;
-    phi_tile<G, RPL, NM1, MIXED, KIND>(a, xcd_remap(blockIdx.x, gridDim.x), sh);
+    phi_tile<G, RPL, NM1, MIXED, KIND, O32>(a, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 
 // The four-trial line-search pass with its registers capped for four waves per
@@ -972,6 +978,11 @@ Error dispatch_seg_n(int G, int RPL, const PhiArgs& a, dim3 grid, hipStream_t s)
     if (G == GG && RPL == RR) {                                                       \
         if constexpr (KIND == kDelta4 && RR <= 2)                                     \
             phi_ls4_kernel<GG, RR, NM1, MIXED, KIND><<<grid, kBlock, 0, s>>>(a);      \
+        else if constexpr (KIND == kPhi)                                              \
+            if (a.o32)                                                                \
+                phi_seg_kernel<GG, RR, NM1, MIXED, KIND, true><<<grid, kBlock, 0, s>>>(a); \
+            else                                                                      \
+                phi_seg_kernel<GG, RR, NM1, MIXED, KIND><<<grid, kBlock, 0, s>>>(a);  \
         else                                                                          \
             phi_seg_kernel<GG, RR, NM1, MIXED, KIND><<<grid, kBlock, 0, s>>>(a);      \
         CPAPR_LAUNCHED();                                                             \
@@ -1104,6 +1115,10 @@ PhiArgs make_args(const cpapr_plan* P, int mode, const double* B, const void* co
     a.NM1 = P->N - 1;
     a.L = P->chunk;
     a.eps = eps;
+    const uint64_t word = P->params.precision == CPAPR_MIXED ? 4 : 8;
+    a.o32 = 1;
+    for (int m = 0; m < P->N; ++m)
+        if (m != mode && (uint64_t)P->dims[m] * (uint64_t)P->R * word > 0xffffffffull) a.o32 = 0;
     return a;
 }
 
@@ -1161,17 +1176,103 @@ int resolve_chunk(int group, int requested)
     return 512 / (kBlock / group);
 }
 
-// Launch-policy model for the nonzeros per lane group per tile, in place of a
-// measured search (the paper leaves such a heuristic as future work, Section 4).
-// Fitted to chunk sweeps at the default lane groups on single Zipf tensors and
-// on batches of small uniform ones: 512-nonzero tiles are best or within a few
-// percent of best for FP64 at every rank measured; with FP32-stored factors,
-// whose per-nonzero work is larger, 1024-nonzero tiles are (fewer tile merges
-// and boundary atomics per nonzero). Row length had no consistent effect.
+// Launch-policy model: the Phi launch shape from the tensor, in place of a
+// measured search (the paper leaves such a heuristic as future work, Section
+// 4). Fitted to sweeps of lanes per nonzero x nonzeros per lane group on every
+// mode of 3- and 4-way tensors from 1e4 to 1e8 nonzeros, uniform and Zipf, R =
+// 8..32, both precisions, timed as kernel durations with the launches queued
+// back to back. What decides is the nonzero count (tiles enough to fill the
+// device), the rank and the precision; the modes of one tensor, and uniform
+// against Zipf rows at equal size, preferred the same shape.
+//  * a large tensor's shape: 512-nonzero tiles with lanes by rank, except
+//    17 <= R <= 32 with up to four modes: 16 lanes x 2 columns on 256-nonzero
+//    tiles in FP64, 8 lanes x 4 columns on 1024-nonzero tiles with FP32-stored
+//    factors (half the gathered words per lane);
+//  * a tensor too small to give ~900 such tiles (3.5 per compute unit) takes
+//    tiles of the largest power of two <= nnz / 900 (at least 32): up to 128
+//    nonzeros on 16 lanes (shorter per-nonzero chains, the launch being
+//    latency-bound); at 256 or 512 lanes by rank, 16 for 9 <= R <= 16 with
+//    FP32-stored factors. Fewer tiles leave the last round of workgroups on
+//    part of the device (measured: 780 tiles 5-13 % slower than 1560 of half
+//    the size; 980 within 2 % of the best);
+//  * the deterministic mode keeps tiles of at least 128 nonzeros;
+//  * in a batch the slots of all tensors share one launch per shape class and
+//    fill the device together, so a slot takes the large tensor's shape of its
+//    rank and precision whatever its own size.
+namespace {
+struct ModelIn {
+    int64_t nnz;
+    int R, nm1;
+    bool mixed, det;
+};
+
+ModelIn model_in(const cpapr_plan* P)
+{
+    return {P->nnz, P->R, P->N - 1, P->params.precision == CPAPR_MIXED, P->params.deterministic != 0};
+}
+
+bool group16_ok(const ModelIn& m)
+{
+    const int rpl = rank_block(m.R, 16);
+    return rpl > 0 && phi_shape_supported(16, rpl, m.nm1);
+}
+
+// (tile nonzeros, lanes per nonzero)
+void model_shape(const ModelIn& m, int* tile, int* group)
+{
+    const int g0 = resolve_group(m.R, 0, m.nm1);
+    int tb = 512, gb = g0;  // a large tensor's shape
+    if (m.R > 16 && m.R <= 32 && m.nm1 <= 3) {
+        if (m.mixed) {
+            tb = 1024;
+        } else if (group16_ok(m)) {
+            tb = 256;
+            gb = 16;
+        }
+    }
+    int64_t t = 32;  // the largest power of two <= nnz / 900, up to the large tensor's tile
+    while (t < tb && 2 * t * 900 <= m.nnz) t *= 2;
+    if (m.det && t < 128) t = 128;
+    if (t >= tb) {
+        *tile = tb;
+        *group = gb;
+    } else if (t <= 128) {
+        *tile = (int)t;
+        *group = group16_ok(m) ? 16 : g0;
+    } else {
+        *tile = (int)t;
+        *group = m.mixed && m.R > 8 && m.R <= 16 && group16_ok(m) ? 16 : g0;
+    }
+}
+}  // namespace
+
+int model_group(const cpapr_plan* P)
+{
+    int t, g;
+    model_shape(model_in(P), &t, &g);
+    return g;
+}
+
 int model_chunk(const cpapr_plan* P, int group)
 {
-    const int tile = P->params.precision == CPAPR_MIXED ? 1024 : 512;
-    return std::max(1, tile / (kBlock / group));
+    int t, g;
+    model_shape(model_in(P), &t, &g);
+    return std::max(1, t / (kBlock / group));
+}
+
+void batch_shape(const cpapr_plan* P, int* group, int* chunk)
+{
+    if (!P->shape_auto) {
+        *group = P->group;
+        *chunk = P->chunk;
+        return;
+    }
+    ModelIn m = model_in(P);
+    m.nnz = int64_t(1) << 40;  // the batch fills the device, not this slot
+    m.det = false;             // batched launches take no tile-end buffers
+    int t;
+    model_shape(m, &t, group);
+    *chunk = std::max(1, t / (kBlock / *group));
 }
 
 // Deterministic mode: attach the plan's tile-end buffers to a single-plan launch.

@@ -15,6 +15,17 @@ mode transitions run the per-mode prologue / epilogue kernels
 makes no update (tol > 0) or after k_max sweeps; its memory returns to the
 budget and queued requests are admitted.
 
+Round policy: "all" admits first come, first served, whatever fits, and runs
+every active request in every round. "srpt" (shortest remaining work first)
+ranks the active and the queued requests together by remaining work (nonzeros
+x mode rounds left) and runs the shortest until the round holds `round_cap`
+nonzeros (at least one request); queued requests are admitted (uploaded and
+sorted) only when the ranking puts them in a round, and active ones outside it
+are held (their slots do no work and their state stays as it is). Short
+requests then finish without waiting for the long ones, or for the uploads of
+requests that will not run soon, while the GPU still gets a full round of work.
+A steady stream of short requests can hold a long one back indefinitely.
+
 Each request's arithmetic is independent of the others in the batch (same
 kernels, same per-plan tiling), so its result is the same alone and in the mix
 up to the order of the few atomic additions at tile boundaries.
@@ -111,6 +122,10 @@ class GpuExecutor:
     def commit(self):
         self.batch.commit(self.stream)
 
+    def hold(self, flags):
+        """Per-slot hold flags for the following rounds (held slots do no work)."""
+        self.batch.hold(flags, self.stream)
+
     def run_round(self, lmax: int):
         """The whole inner loop of every slot's mode; per-slot (viol, updates, done)."""
         self.batch.inner(lmax, use_graph=self.use_graph, stream=self.stream)
@@ -137,7 +152,7 @@ class Server:
     def __init__(self, budget_bytes: float = 200e9, max_slots: int = 64, max_tiles: int = 1 << 22,
                  kmax: int = 20, lmax: int = 10, tol: float = 1e-4, eps: float = 1e-10,
                  precision: int = cpapr.CPAPR_MIXED, use_graph: bool = True, stream=None,
-                 compute_loglik: bool = True, executor=None):
+                 compute_loglik: bool = True, executor=None, policy: str = "all", round_cap: float = 8e6):
         self.budget = float(budget_bytes)
         self.used = 0.0
         self.max_slots = max_slots
@@ -153,6 +168,15 @@ class Server:
         self.peak_active = 0
         self.peak_used = 0.0
         self._need_commit = True
+        if policy not in ("all", "srpt"):
+            raise ValueError("policy must be 'all' or 'srpt'")
+        self.policy = policy
+        self.round_cap = float(round_cap)
+        self._held = None  # hold flags last sent to the executor
+        # host seconds per phase of tick(): admission (upload + plan build),
+        # batch commit, hold flags, the round (device time + status read-back),
+        # advancing the loop state (mode epilogue / prologue, retirement)
+        self.phase_s = dict(admit=0.0, commit=0.0, hold=0.0, round=0.0, advance=0.0)
 
     # ------------------------------------------------------------------ admission
     def footprint(self, req: Request) -> int:
@@ -165,24 +189,39 @@ class Server:
     def _admit(self):
         while self.queue and self.free_slots:
             req = self.queue[0]
-            need = self.footprint(req)
-            if need > self.budget:
-                self.queue.popleft()
-                req.stats["rejected"] = "larger than the HBM budget"
-                req.t_done = time.perf_counter() - self.t0
-                self.done.append(req)
-                continue
-            if self.used + need > self.budget:
+            if not self._admit_one(req):
                 break  # first come, first served: wait for memory
-            self.queue.popleft()
-            slot = self.free_slots.pop()
-            act = _Active(req, slot, self.ex.admit(req), need)
-            self.used += need
-            self.peak_used = max(self.peak_used, self.used)
-            req.t_admit = time.perf_counter() - self.t0
-            self._mode_begin(act)
-            self.active.append(act)
-            self.peak_active = max(self.peak_active, len(self.active))
+
+    def _admit_one(self, req: Request) -> bool:
+        """Admit a queued request if a slot is free and it fits the budget
+        (rejecting it for good when it exceeds the whole budget). Returns
+        whether it left the queue."""
+        need = self.footprint(req)
+        if need > self.budget:
+            self.queue.remove(req)
+            req.stats["rejected"] = "larger than the HBM budget"
+            req.t_done = time.perf_counter() - self.t0
+            self.done.append(req)
+            return True
+        if not self.free_slots or self.used + need > self.budget:
+            return False
+        self.queue.remove(req)
+        slot = self.free_slots.pop()
+        act = _Active(req, slot, self.ex.admit(req), need)
+        self.used += need
+        self.peak_used = max(self.peak_used, self.used)
+        req.t_admit = time.perf_counter() - self.t0
+        self._mode_begin(act)
+        self.active.append(act)
+        self.peak_active = max(self.peak_active, len(self.active))
+        return True
+
+    def _admit_srpt(self):
+        """Admit the queued requests that the shortest-remaining-work ranking
+        puts in the next round."""
+        for item in self._ranked_round(with_queue=True):
+            if isinstance(item, Request):
+                self._admit_one(item)
 
     # ------------------------------------------------------------------ per request
     def _mode_begin(self, a: _Active):
@@ -211,7 +250,14 @@ class Server:
         current mode together (one device sequence, stops decided on the
         device) and advance each request to its next mode. Returns False when
         nothing is active or queued."""
-        self._admit()
+        clock = time.perf_counter
+        t = clock()
+        if self.policy == "all":
+            self._admit()
+        else:
+            self._admit_srpt()
+        t, dt = clock(), clock() - t
+        self.phase_s["admit"] += dt
         if not self.active:
             return bool(self.queue)
         changed = False
@@ -223,12 +269,29 @@ class Server:
         if changed or self._need_commit:
             self.ex.commit()
             self._need_commit = False
+        t, dt = clock(), clock() - t
+        self.phase_s["commit"] += dt
         lmax, kmax, tol = self.params["lmax"], self.params["kmax"], self.params["tol"]
-        # the whole inner loop of every active request's current mode, stops on the device
+        run = self._select()
+        held = [0] * self.max_slots
+        for a in self.active:
+            if a not in run:
+                held[a.slot] = 1
+        if held != self._held and (self._held is not None or any(held)):
+            self.ex.hold(held)
+            self._held = held
+        t, dt = clock(), clock() - t
+        self.phase_s["hold"] += dt
+        # the whole inner loop of every running request's current mode, stops on the device
         viol, updates, done = self.ex.run_round(lmax)
         self.ticks += 1
+        t, dt = clock(), clock() - t
+        self.phase_s["round"] += dt
         keep = []
         for a in self.active:
+            if a not in run:
+                keep.append(a)  # held this round: nothing ran
+                continue
             a.last_viol[a.n] = viol[a.slot]
             a.updates += updates[a.slot]
             if updates[a.slot] > 0:
@@ -246,7 +309,36 @@ class Server:
             self._mode_begin(a)
             keep.append(a)
         self.active = keep
+        self.phase_s["advance"] += clock() - t
         return bool(self.active or self.queue)
+
+    def _remaining(self, a) -> float:
+        """Work left for a request (active, or queued with all of it left): its
+        nonzeros times the mode rounds left."""
+        if isinstance(a, Request):
+            return float(a.X.nnz) * self.params["kmax"] * len(a.X.dims)
+        rounds = (self.params["kmax"] - a.k) * a.N + (a.N - a.n)
+        return float(a.req.X.nnz) * rounds
+
+    def _ranked_round(self, with_queue: bool) -> list:
+        """Shortest remaining work first: the active (and, with_queue, queued)
+        requests of the next round, until it holds round_cap nonzeros."""
+        items = list(self.active) + (list(self.queue) if with_queue else [])
+        nnz = lambda q: float(q.X.nnz if isinstance(q, Request) else q.req.X.nnz)  # noqa: E731
+        rid = lambda q: q.id if isinstance(q, Request) else q.req.id  # noqa: E731
+        out, work = [], 0.0
+        for q in sorted(items, key=lambda q: (self._remaining(q), rid(q))):
+            if out and work + nnz(q) > self.round_cap:
+                break
+            out.append(q)
+            work += nnz(q)
+        return out
+
+    def _select(self) -> set:
+        """The active requests that run this round."""
+        if self.policy == "all":
+            return set(self.active)
+        return set(self._ranked_round(with_queue=False))
 
     # ------------------------------------------------------------------ driving a trace
     def run_trace(self, requests: List[Request], time_limit: float = 600.0) -> List[Request]:

@@ -18,12 +18,13 @@ from __future__ import annotations
 import json
 import math
 import os
+import time
 from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 
 from . import cpapr
 
 GROUPS = (4, 8, 16)
-CHUNKS = (8, 16, 32, 64)
+CHUNKS = (2, 4, 8, 16, 32, 64)
 
 
 def rank_block(R: int, G: int) -> int:
@@ -48,18 +49,141 @@ def shape_candidates(R: int, nmodes: int) -> List[Tuple[int, int]]:
     return out
 
 
-def _time(fn, reps: int) -> float:
+_CYCLES_PER_MS: Optional[float] = None
+
+
+def _hold_stream(ms: float):
+    """Queue a device-side spin of about `ms` milliseconds on the current
+    stream (calibrated once against HIP events)."""
+    import torch
+    global _CYCLES_PER_MS
+    if _CYCLES_PER_MS is None:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        torch.cuda._sleep(1_000_000)
+        e1.record()
+        torch.cuda.synchronize()
+        _CYCLES_PER_MS = 1_000_000 / max(e0.elapsed_time(e1), 1e-3)
+    torch.cuda._sleep(int(min(ms, 100.0) * _CYCLES_PER_MS))
+
+
+def _enqueue_ms(fn) -> float:
+    """Host time to queue one call of fn (after a warm call)."""
     import torch
     fn()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    t = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    return t * 1e3
+
+
+def _time(fn, reps: int) -> float:
+    """Device time per call of fn over `reps` back-to-back calls. The stream is
+    first held busy for longer than the host takes to queue the calls, so they
+    run back to back on the device and the host's launch rate does not enter
+    (a Phi launch on a small tensor takes a few microseconds, less than the
+    host needs to issue it)."""
+    import torch
+    host = _enqueue_ms(fn)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    _hold_stream(2.0 * reps * host + 0.5)
     e0.record()
     for _ in range(reps):
         fn()
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def _kernel_ms(fn, reps: int) -> float:
+    """Median device duration of the Phi kernel alone (the library's launch
+    events bracket it) over `reps` calls of fn, queued behind a hold of the
+    stream as in _time."""
+    import torch
+    host = _enqueue_ms(fn)
+    cpapr.cpapr_prof_enable(reps)
+    try:
+        _hold_stream(2.0 * reps * host + 0.5)
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        recs = cpapr.cpapr_prof_read(reps)
+    finally:
+        cpapr.cpapr_prof_disable()
+    ms = sorted(t for _, t in recs)
+    return ms[len(ms) // 2]
+
+
+def _reps_for(est_ms: float, min_ms: float, lo: int = 5, hi: int = 200) -> int:
+    """Calls per timing: enough to cover min_ms of device time, at most `hi`
+    (the calls of one timing must fit the stream's queue behind the hold)."""
+    return max(lo, min(hi, int(math.ceil(min_ms / max(est_ms, 1e-4)))))
+
+
+def _confirm(measure, keys: Sequence[tuple], rounds: int) -> Dict[tuple, float]:
+    """Median of `rounds` timings of each finalist, taken in rotating order.
+    The fastest of many single timings is biased low (it is the minimum of
+    noisy draws), so the winner and the model are compared on fresh,
+    interleaved timings instead."""
+    samples: Dict[tuple, List[float]] = {k: [] for k in keys}
+    for r in range(rounds):
+        for j in range(len(keys)):
+            k = keys[(j + r) % len(keys)]
+            samples[k].append(measure(k))
+    return {k: sorted(v)[len(v) // 2] for k, v in samples.items()}
+
+
+def tune_plan(P, operands, modes: Optional[Iterable[int]] = None, min_ms: float = 1.0, rounds: int = 5,
+              finalists: int = 3, candidates: Optional[Sequence[Tuple[int, int]]] = None) -> List[dict]:
+    """Time the Phi kernel of each mode of one plan for every candidate
+    (group, chunk) and for the library's launch-policy model. operands(n) ->
+    (B, A). Each timing is the median kernel duration over enough launches to
+    cover min_ms; the `finalists` fastest shapes and the model's are then
+    re-timed `rounds` times, interleaved, and compared on their medians.
+    Returns, per mode, the fastest shape, the model's shape and time, and
+    model_vs_tuned = model time / fastest time. Leaves the plan on the model's
+    shape."""
+    import torch
+    nm = len(P.dims)
+    modes = range(nm) if modes is None else modes
+    if candidates is None:
+        candidates = [(g, c) for g in GROUPS for c in CHUNKS]
+    P.set_shape(0, 0)
+    model = tuple(P.shape())
+    out = []
+    for n in modes:
+        B, A = operands(n)
+        phi = torch.empty((P.dims[n], P.R), dtype=torch.float64, device=B.device)
+        call = lambda: P.phi(n, B, A, out=phi)  # noqa: E731
+        P.set_shape(*model)
+        reps = _reps_for(_kernel_ms(call, 5), min_ms)
+
+        def measure(shape):
+            P.set_shape(*shape)
+            return _kernel_ms(call, reps)
+
+        first = {}
+        for shape in list(candidates) + [model]:
+            if shape in first:
+                continue
+            try:
+                first[shape] = measure(shape)
+            except cpapr.CpaprError:
+                continue
+        top = sorted(first, key=first.get)[:finalists]
+        med = _confirm(measure, list(dict.fromkeys(top + [model])), rounds)
+        P.set_shape(0, 0)
+        best = min(med, key=med.get)
+        out.append({"mode": n, "best": list(best), "best_ms": med[best], "model": list(model),
+                    "model_ms": med[model], "model_vs_tuned": med[model] / med[best], "reps": reps,
+                    "candidates": {f"{g},{c}": round(t, 5) for (g, c), t in sorted(first.items())},
+                    "finalists": {f"{g},{c}": round(t, 5) for (g, c), t in sorted(med.items())}})
+    return out
 
 
 class Autotuner:
@@ -118,23 +242,29 @@ class Autotuner:
         b.close()
         return ms
 
-    def _search(self, its: Sequence[dict], nm: int, R: int) -> dict:
-        results = []
-        for G, chunk in shape_candidates(R, nm):
+    def _search(self, its: Sequence[dict], nm: int, R: int, finalists: int = 3, rounds: int = 5) -> dict:
+        def measure(shape):
             for it in its:
-                it["P"].set_shape(G, chunk)
-            results.append((self._time_batch(its), G, chunk))
-        results.sort()
-        ms, G, chunk = results[0]
-        # the library's launch-policy model (group by rank, chunk from precision,
-        # rank and row length, per plan), timed on the same slots
+                it["P"].set_shape(*shape)
+            return self._time_batch(its)
+
+        # the library's launch-policy model: (0, 0) gives every plan the
+        # model's batch shape, timed on the same slots as the candidates
+        model = (0, 0)
+        first = {shape: measure(shape) for shape in shape_candidates(R, nm)}
+        top = sorted(first, key=first.get)[:finalists]
+        med = _confirm(measure, list(dict.fromkeys(top + [model])), rounds)
         for it in its:
             it["P"].set_shape(0, 0)
-        model = sorted({it["P"].shape() for it in its})
-        model_ms = self._time_batch(its)
-        return {"group": G, "chunk": chunk, "ms": ms,
-                "model": [list(m) for m in model], "model_ms": model_ms, "model_vs_tuned": model_ms / ms,
-                "candidates": [{"group": g, "chunk": c, "ms": round(t, 4)} for t, g, c in results]}
+        model_shapes = sorted({it["P"].batch_shape() for it in its})
+        # (0, 0) when the model's shapes are the fastest: the plans keep them
+        best = min(med, key=med.get)
+        G, chunk = best
+        return {"group": G, "chunk": chunk, "ms": med[best],
+                "model": [list(m) for m in model_shapes], "model_ms": med[model],
+                "model_vs_tuned": med[model] / min(med.values()),
+                "candidates": [{"group": g, "chunk": c, "ms": round(t, 4)} for (g, c), t in
+                               sorted(first.items(), key=lambda kv: kv[1])]}
 
     def tune_sort(self, make_plan, modes: Iterable[int], operands) -> int:
         """Pick the in-row order for one tensor: make_plan(sort) builds a Plan,

@@ -1,6 +1,7 @@
 """Parity at the largest single-GPU size: the 4-way 1M x 200k x 10k x 500 tensor
 with 100M nonzeros (Zipf(1.2) on modes 1-2, uniform on 3-4, counts capped at
-1000), R = 32, in the default launch shape (8 lanes x 4 rank columns).
+1000), R = 32, in the default launch shape (the launch-policy model's: 16 lanes x 2 rank
+columns in FP64, 8 lanes x 4 with FP32-stored factors).
 
 As at 20M: oracle rows one by one (Phi and the fixed-schedule inner loop are
 row-separable), plus the mass identity sum(B .* Phi) = sum(x) over every row.

@@ -124,6 +124,28 @@ def test_phi_degenerate_sizes():
     _phi_case(X2, synth.random_model(3, X2.dims, 16))
 
 
+def test_phi_quotient_within_a_few_ulps():
+    """The per-nonzero quotient x / max(b.pi, eps), formed from the reciprocal
+    estimate and one Newton step, against the oracle's correctly rounded
+    division: a 2-way tensor with R = 1 and one nonzero per row of mode 0, so
+    Phi[i] = (x / (b_i a_j)) a_j and every other operation is exact or rounded
+    identically on both sides. The quotient is within two ulps, so with the two
+    products' roundings the largest relative difference is <= 4 * 2^-52."""
+    rng = np.random.default_rng(21)
+    I, J = 1_000_000, 5000
+    idx = np.stack([np.arange(I), rng.integers(0, J, I)]).astype(np.int32)
+    X = synth.SparseTensor((I, J), idx, rng.integers(1, 1000, I).astype(np.float64))
+    A = [rng.uniform(0.5, 2.0, (I, 1)), rng.uniform(0.5, 2.0, (J, 1))]
+    P = cpapr.Plan.from_tensor(X, 1)
+    got = host(P.phi(0, dev(A[0]), [dev(a) for a in A]))
+    ref = oracle.phi(X, 0, A[0], A)
+    rel = np.abs(got - ref) / np.abs(ref)
+    print(f"quotient: largest relative difference {rel.max():.3e} ({rel.max() / 2.0 ** -52:.2f} x 2^-52), "
+          f"{np.count_nonzero(rel)} of {I} rows differ", flush=True)
+    assert rel.max() <= 4 * 2.0 ** -52
+    P.close()
+
+
 def test_phi_atomic_variant_matches():
     X, M, _ = synth.config_small()
     _phi_case(X, M, variant=cpapr.CPAPR_VARIANT_ATOMIC)
@@ -221,22 +243,46 @@ def test_invalid_inputs_are_rejected():
 # ---------------------------------------------------------------- MU inner loop, solve, loglik
 
 def test_launch_policy_model_shapes():
-    """Default launch shape: lanes by rank, chunk from the policy model (512-
-    nonzero tiles in FP64, 1024 with FP32-stored factors); explicit shapes are
-    kept, and the model returns when the chunk is reset."""
-    X, M, _ = synth.config_small()
+    """Default launch shape from the launch-policy model of the tensor. A large
+    tensor gets 512-nonzero tiles with lanes by rank, except 17 <= R <= 32
+    (16 x 2 on 256-nonzero tiles in FP64, 8 x 4 on 1024 with FP32-stored
+    factors); a smaller one tiles of the largest power of two <= nnz/900 (at
+    least 32), on 16 lanes up to 128 nonzeros, lanes by rank at 256 and 512
+    (16 for 9 <= R <= 16 with FP32-stored factors); deterministic plans keep
+    tiles of at least 128. Explicit shapes are kept, and the model returns when
+    the shape is reset. In a batch a plan on the model's shape takes the large
+    tensor's shape."""
+    X, M, _ = synth.config_small()  # 10,000 nonzeros, R = 10
     P = cpapr.Plan.from_tensor(X, 10)
-    assert P.shape() == (8, 16)
-    P.set_shape(16, 40)
-    assert P.shape() == (16, 40)
+    assert P.shape() == (16, 2)
+    assert P.batch_shape() == (8, 16) and P.tiles() == 20
+    P.set_shape(8, 40)
+    assert P.shape() == (8, 40) and P.batch_shape() == (8, 40)
+    assert P.tiles() == -(-10_000 // (32 * 40))
     P.set_shape(0, 0)
-    assert P.shape() == (8, 16)
-    P.set_shape(16, 0)
-    assert P.shape() == (16, 32)
+    assert P.shape() == (16, 2) and P.batch_shape() == (8, 16)
+    P.set_shape(8, 0)
+    assert P.shape() == (8, 1) and P.batch_shape() == (8, 1)
     P.close()
-    Pm = cpapr.Plan.from_tensor(X, 10, precision=cpapr.CPAPR_MIXED)
-    assert Pm.shape() == (8, 32)
-    Pm.close()
+    Pd = cpapr.Plan.from_tensor(X, 10, deterministic=1)
+    assert Pd.shape() == (16, 8)
+    Pd.close()
+    cases = {300_000: [(16, cpapr.CPAPR_FP64, (8, 8)), (8, cpapr.CPAPR_MIXED, (8, 8)),
+                       (16, cpapr.CPAPR_MIXED, (16, 16)), (32, cpapr.CPAPR_FP64, (16, 16))],
+             600_000: [(16, cpapr.CPAPR_FP64, (8, 16)), (16, cpapr.CPAPR_MIXED, (8, 16)),
+                       (32, cpapr.CPAPR_FP64, (16, 16)), (32, cpapr.CPAPR_MIXED, (8, 16)),
+                       (8, cpapr.CPAPR_FP64, (8, 16)), (64, cpapr.CPAPR_FP64, (16, 32))],
+             1_100_000: [(32, cpapr.CPAPR_MIXED, (8, 32)), (32, cpapr.CPAPR_FP64, (16, 16))]}
+    big = {(16, cpapr.CPAPR_FP64): (8, 16), (8, cpapr.CPAPR_MIXED): (8, 16), (16, cpapr.CPAPR_MIXED): (8, 16),
+           (32, cpapr.CPAPR_FP64): (16, 16), (32, cpapr.CPAPR_MIXED): (8, 32), (8, cpapr.CPAPR_FP64): (8, 16),
+           (64, cpapr.CPAPR_FP64): (16, 32)}
+    for nnz, want in cases.items():
+        Xn = synth.random_tensor(nnz % 97, (400, 300, 200), nnz)
+        for R, prec, shape in want:
+            Pn = cpapr.Plan.from_tensor(Xn, R, precision=prec)
+            assert Pn.shape() == shape, (nnz, R, prec, Pn.shape())
+            assert Pn.batch_shape() == big[(R, prec)], (nnz, R, prec, Pn.batch_shape())
+            Pn.close()
 
 
 def test_mu_inner_fixed_schedule():

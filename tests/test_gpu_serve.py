@@ -101,3 +101,53 @@ def test_arrivals_over_time_and_latency_summary():
     s = serve.latency_summary(done)
     assert s["completed"] == 6 and s["p99_from_arrival_s"] >= s["p50_from_arrival_s"] > 0
     assert all(r.t_done >= r.t_admit >= r.arrival for r in done)
+
+
+def test_srpt_rounds_give_the_same_results():
+    """Shortest-remaining-work rounds hold some requests each round (their
+    slots do no work); every request still computes exactly what it computes
+    when all run every round."""
+    kw = dict(kmax=4, lmax=4, tol=1e-4, precision=cpapr.CPAPR_FP64)
+    reqs = _requests(6, seed=3)
+    allr = {r.id: r for r in serve.Server(max_slots=6, **kw).run_trace([_clone(r) for r in reqs])}
+    cap = sorted(r.X.nnz for r in reqs)[2]  # about two requests per round
+    srv = serve.Server(max_slots=6, policy="srpt", round_cap=cap, **kw)
+    srpt = {r.id: r for r in srv.run_trace([_clone(r) for r in reqs])}
+    assert srv.ticks > max(r.stats["outer_iters"] for r in srpt.values()) * 4  # rounds were split
+    for r in reqs:
+        a, s = allr[r.id], srpt[r.id]
+        assert s.stats["outer_iters"] == a.stats["outer_iters"]
+        assert s.stats["inner_updates"] == a.stats["inner_updates"]
+        assert_parity(s.result_lam, a.result_lam, 1e-12, "lambda")
+        for x, y in zip(s.result_factors, a.result_factors):
+            assert_iterate_parity(x, y, 1e-12, "factor")
+
+
+def test_held_slot_does_no_work():
+    import torch
+    from tests.gpu_util import dev, host
+    reqs = _requests(2, seed=4)
+    b = cpapr.Batch(2, 1 << 16)
+    items = []
+    for sl, r in enumerate(reqs):
+        P = cpapr.Plan.from_tensor(r.X, r.M.rank, lmax=3, tol=0.0)
+        A = [dev(a) for a in r.M.factors]
+        B = dev(r.M.factors[0] * r.M.lam)
+        Phi = torch.full((r.X.dims[0], r.M.rank), 5.0, dtype=torch.float64, device="cuda")
+        b.set(sl, P, 0, B, A, Phi)
+        items.append((P, A, B, Phi))
+    b.commit()
+    B1, Phi1 = host(items[1][2]).copy(), host(items[1][3]).copy()
+    b.hold([0, 1])
+    b.inner(3)
+    viol, upd, done = b.status()
+    assert done[1] == 1 and upd[1] == 0 and upd[0] == 3
+    assert np.array_equal(host(items[1][2]), B1) and np.array_equal(host(items[1][3]), Phi1)
+    Bo, _, _, _ = oracle.mu_inner(reqs[0].X, 0, reqs[0].M.factors[0] * reqs[0].M.lam, reqs[0].M.factors, lmax=3)
+    assert_parity(host(items[0][2]), Bo, 1e-12, "slot 0")
+    b.hold([0, 0])
+    b.inner(3)
+    assert b.status()[1][1] == 3  # released: runs again
+    b.close()
+    for P, *_ in items:
+        P.close()

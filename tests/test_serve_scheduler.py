@@ -16,6 +16,7 @@ class MockExecutor:
         self.slots = {}            # slot -> (request id, mode)
         self.admitted, self.events = [], []
         self.max_used_slots = 0
+        self.rounds = []           # ids that ran, per round
 
     def footprint(self, req):
         return self.sizes[req.id]
@@ -38,12 +39,20 @@ class MockExecutor:
     def commit(self):
         pass
 
+    def hold(self, flags):
+        self.held = list(flags)
+
     def run_round(self, lmax):
         n_slots = max(self.slots) + 1 if self.slots else 1
         viol = np.zeros(n_slots)
         upd = np.zeros(n_slots, dtype=np.int32)
         done = np.zeros(n_slots, dtype=np.int32)
+        held = getattr(self, "held", [])
+        self.rounds.append(sorted(h["id"] for s, (h, n) in self.slots.items() if not (s < len(held) and held[s])))
         for slot, (h, n) in self.slots.items():
+            if slot < len(held) and held[slot]:
+                done[slot] = 1  # a held slot does no work
+                continue
             c = self.converge_at[h["id"]]
             conv = c is not None and h["k"] >= c
             upd[slot] = 0 if conv else lmax
@@ -58,9 +67,9 @@ class MockExecutor:
         return np.ones(2), [np.zeros((3, 2))] * self.nmodes, -1.0
 
 
-def _reqs(count, nmodes=3):
-    return [serve.Request(id=i, X=types.SimpleNamespace(dims=(5,) * nmodes), M=None, arrival=0.0)
-            for i in range(count)]
+def _reqs(count, nmodes=3, nnz=None):
+    return [serve.Request(id=i, X=types.SimpleNamespace(dims=(5,) * nmodes, nnz=(nnz[i] if nnz else 10)), M=None,
+                          arrival=0.0) for i in range(count)]
 
 
 def test_fifo_admission_budget_and_rejection():
@@ -126,3 +135,36 @@ def test_latency_summary():
     assert s["completed"] == 4 and s["rejected"] == 0
     assert s["p99_from_arrival_s"] >= s["p50_from_arrival_s"] >= 0
     assert all(r.t_done >= r.t_admit >= r.arrival for r in done)
+
+
+def test_srpt_runs_least_remaining_work_first():
+    """Shortest remaining work first under a per-round cap of nonzeros: each
+    round runs the requests with the least work left (nonzeros x mode rounds
+    left) until the cap, at least one; held requests do not advance. Queued
+    requests are ranked with the active ones and admitted only when a round
+    takes them. Short requests finish first; every request still finishes its
+    k_max sweeps."""
+    nnz = {0: 100, 1: 10, 2: 1000, 3: 40}
+    ex = MockExecutor({i: 1 for i in nnz}, {i: None for i in nnz}, 3)
+    srv = serve.Server(budget_bytes=10, max_slots=4, kmax=2, lmax=2, tol=1e-4, executor=ex, policy="srpt",
+                       round_cap=60)
+    done = srv.run_trace(_reqs(4, nnz=[nnz[i] for i in range(4)]))
+    assert [r.id for r in done] == [1, 3, 0, 2]
+    assert all(r.stats["outer_iters"] == 2 for r in done)
+    for ran in ex.rounds:
+        assert len(ran) == 1 or sum(nnz[i] for i in ran) <= 60
+    assert ex.rounds[0] == [1, 3]  # 10 + 40 <= 60; 100 and 1000 wait
+    # submitted in id order, admitted by remaining work, each only when its round comes
+    assert ex.admitted == [1, 3, 0, 2]
+    by_id = {r.id: r for r in done}
+    assert by_id[0].t_admit >= by_id[3].t_done and by_id[2].t_admit >= by_id[0].t_done
+    walk = [(k, n, e) for (i, e, k, n) in ex.events if i == 2]
+    assert walk == [(k, n, e) for k in (1, 2) for n in range(3) for e in ("begin", "end")]
+    assert "rejected" not in done[0].stats
+
+
+def test_policy_all_runs_everyone():
+    ex = MockExecutor({i: 1 for i in range(3)}, {i: None for i in range(3)}, 2)
+    srv = serve.Server(budget_bytes=10, max_slots=3, kmax=2, lmax=2, tol=1e-4, executor=ex)
+    srv.run_trace(_reqs(3, nmodes=2))
+    assert all(r == [0, 1, 2] for r in ex.rounds)
