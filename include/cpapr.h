@@ -218,6 +218,24 @@ int cpapr_phi_coo_workspace_size(const cpapr_coo* X, int32_t mode, int32_t R, si
 int cpapr_phi_coo(const cpapr_coo* X, int32_t mode, int32_t R, const double* B, const double* const* A, double eps,
                   double* Phi, void* ws, size_t ws_bytes, void* stream);
 
+/* Device scratch that cpapr_phi_coo_noalloc keeps in the library's static
+ * device memory, per GPU it runs on, until the process ends. */
+#define CPAPR_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* cpapr_phi_coo for callers that cannot allocate device memory (code that
+ * must not call hipMalloc: serving loops, harnesses that forbid it). Same
+ * arguments, checks and result as cpapr_phi_coo, with no workspace: the
+ * scratch is a static device array of CPAPR_NOALLOC_SCRATCH_BYTES on each GPU
+ * (a 3-way tensor of about 1.8M nonzeros fits). A tensor whose transient
+ * workspace (cpapr_phi_coo_workspace_size) is larger is refused with
+ * CPAPR_EUNSUPPORTED before any device work. Calls no hipMalloc, hipFree or
+ * other allocating routine. All calls on one GPU share its array: calls that
+ * overlap on a GPU (from other threads, on any stream) race; a call waits for
+ * its stream before returning, so calls made one after another are safe.
+ * Not for graph capture (it waits for the stream). FP64 only. */
+int cpapr_phi_coo_noalloc(const cpapr_coo* X, int32_t mode, int32_t R, const double* B, const double* const* A,
+                          double eps, double* Phi, void* stream);
+
 /* MU inner loop of Algorithm 1 for one mode, params lmax / tol / eps of the plan:
  * for l < lmax: Phi = phi(B); viol = max|min(B, 1 - Phi)|; stop if tol > 0 and
  * viol < tol; else B <- B .* Phi.

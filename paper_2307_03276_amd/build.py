@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcpapr.so")
-SOURCES = ["sort.hip", "phi.hip", "mu.hip", "pqnr.hip", "pdnr.hip", "batch.hip", "api.hip"]
+SOURCES = ["sort.hip", "phi.hip", "mu.hip", "pqnr.hip", "pdnr.hip", "batch.hip", "api.hip", "noalloc.hip"]
 ARCH = os.environ.get("CPAPR_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -92,6 +92,7 @@ def load():
         "cpapr_phi": (C.c_int, [vp, i32, vp, P(vp), dbl, vp, vp]),
         "cpapr_phi_coo_workspace_size": (C.c_int, [P(cpapr_coo), i32, i32, P(C.c_size_t)]),
         "cpapr_phi_coo": (C.c_int, [P(cpapr_coo), i32, i32, vp, P(vp), dbl, vp, vp, C.c_size_t, vp]),
+        "cpapr_phi_coo_noalloc": (C.c_int, [P(cpapr_coo), i32, i32, vp, P(vp), dbl, vp, vp]),
         "cpapr_mu_inner": (C.c_int, [vp, i32, vp, P(vp), vp, P(cpapr_stats), vp]),
         "cpapr_pqnr_inner": (C.c_int, [vp, i32, vp, P(vp), P(cpapr_stats), vp]),
         "cpapr_pdnr_inner": (C.c_int, [vp, i32, vp, P(vp), P(cpapr_stats), vp]),
@@ -131,7 +132,7 @@ def load():
 EXPORTED = ("cpapr_params_default", "cpapr_plan_workspace_size", "cpapr_plan_create", "cpapr_plan_destroy",
             "cpapr_plan_segments", "cpapr_plan_set_shape", "cpapr_plan_shape",
             "cpapr_plan_batch_shape", "cpapr_phi", "cpapr_phi_coo_workspace_size",
-            "cpapr_phi_coo", "cpapr_mu_inner", "cpapr_pqnr_inner",
+            "cpapr_phi_coo", "cpapr_phi_coo_noalloc", "cpapr_mu_inner", "cpapr_pqnr_inner",
             "cpapr_pdnr_inner", "cpapr_row_stats", "cpapr_solve", "cpapr_loglik",
             "cpapr_mttkrp", "cpapr_batch_workspace_size", "cpapr_batch_tiles", "cpapr_batch_create", "cpapr_batch_create2",
             "cpapr_batch_destroy", "cpapr_batch_set", "cpapr_batch_clear", "cpapr_batch_commit", "cpapr_batch_run",
@@ -243,6 +244,18 @@ def cpapr_phi_coo(coo, mode, R, B, A, eps, Phi, ws, stream=None):
     _need_cuda(ws, "ws")
     _check(load().cpapr_phi_coo(C.byref(coo), mode, R, B.data_ptr(), _ptr_array(A), eps, Phi.data_ptr(),
                                 ws.data_ptr(), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def cpapr_phi_coo_noalloc(coo, mode, R, B, A, eps, Phi, stream=None):
+    """Transient Phi with the library's static device scratch (no workspace, no allocation)."""
+    import torch
+    _need_cuda(B, "B", torch.float64)
+    _need_cuda(Phi, "Phi", torch.float64)
+    _check(load().cpapr_phi_coo_noalloc(C.byref(coo), mode, R, B.data_ptr(), _ptr_array(A), eps, Phi.data_ptr(),
+                                        _stream(stream)))
 
 
 def phi_coo(dims, idx, vals, mode, R, B, A, eps=1e-10, out=None, stream=None):
