@@ -112,6 +112,60 @@ def measured_traffic(workload, precision):
     return e.get("bytes_per_launch")
 
 
+def progress(msg):
+    """A progress line on stderr (the result stays the one JSON line on stdout)."""
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+def _counter_rows(path, counter):
+    """(kernel name, value) per dispatch, in dispatch order, of one counter in a
+    rocprofv3 --pmc csv (counter_collection.csv)."""
+    import csv
+    rows = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    return [(k, v) for _, k, v in rows]
+
+
+def record_traffic(fetch_csv, write_csv, workload, precision):
+    """Bytes past L2 per Phi launch from two rocprofv3 counter runs of
+    `bench.py --profile-phi` (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch),
+    each scaled by what the same counter reads for the run's 1 GiB device copy;
+    stored in the traffic file under the workload, precision and the kernel
+    source's hash."""
+    scaled = []
+    factors = []
+    names = set()
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        rows = _counter_rows(path, counter)
+        copy = max((v for k, v in rows if "copyBuffer" in k or "copy" in k.lower()), default=0.0)
+        if copy <= 0:
+            raise SystemExit(f"{path}: no device copy to calibrate {counter}")
+        factor = float(1 << 30) / (copy * 1024.0)
+        phi = [v * 1024.0 * factor for k, v in rows if "phi_seg_kernel" in k]
+        names.update(k for k, v in rows if "phi_seg_kernel" in k)
+        scaled.append(phi)
+        factors.append(factor)
+    if len(scaled[0]) != len(scaled[1]) or not scaled[0]:
+        raise SystemExit("the two runs hold different numbers of Phi dispatches")
+    per_launch = [a + b for a, b in zip(*scaled)]
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        d = {}
+    key = f"{workload}/{precision}"
+    d[key] = {"bytes_per_launch": sum(per_launch) / len(per_launch), "per_launch_bytes": per_launch,
+              "fetch_factor": factors[0], "write_factor": factors[1], "kernel": sorted(names)[0],
+              "kernel_hash": kernel_source_hash()}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    print(json.dumps({key: d[key]}), flush=True)
+
+
 def host_cpu():
     """The host's CPU model and core counts (what the CPU baseline ran on)."""
     model = "unknown"
@@ -296,10 +350,13 @@ def run_serving(count, warmup, prec, fp64_checks=2, seed=0, policy="srpt", round
     trace = synth.serving_trace(seed=seed, count=count + warmup)
     t_gen = time.perf_counter()
     reqs = []
-    for r in trace:
+    for i, r in enumerate(trace):
         X, M = synth.request_tensor(r)
         reqs.append(serve.Request(id=r["id"], X=X, M=M, arrival=r["arrival"]))
+        if (i + 1) % 50 == 0:
+            progress(f"serving: {i + 1} of {len(trace)} requests generated")
     t_gen = time.perf_counter() - t_gen
+    progress(f"serving: {len(reqs)} requests generated in {t_gen:.1f} s")
     kw = dict(kmax=20, lmax=10, tol=1e-4, precision=prec)
     warm, meas = reqs[:warmup], reqs[warmup:]
     t_first = meas[0].arrival
@@ -314,10 +371,12 @@ def run_serving(count, warmup, prec, fp64_checks=2, seed=0, policy="srpt", round
     done_all = srv_all.run_trace([serve.Request(id=r.id, X=r.X, M=r.M, arrival=r.arrival) for r in meas])
     summary_all = serve.latency_summary(done_all)
     torch.cuda.synchronize()
+    progress(f"serving: every request every round done ({summary_all.get('solves_per_s', 0):.1f} solves/s)")
     srv = serve.Server(budget_bytes=200e9, max_slots=64, policy=policy, round_cap=round_cap, **kw)
     done = srv.run_trace(meas)
     summary = serve.latency_summary(done)
     by_id = {r.id: r for r in done}
+    progress(f"serving: {policy} done ({summary.get('solves_per_s', 0):.1f} solves/s); one request at a time next")
     # the plain path on the same trace: one request at a time, in arrival order
     clock = 0.0
     ttc, busy = [], 0.0
@@ -465,6 +524,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the short served trace of the default run")
     ap.add_argument("--short-serve-count", type=int, default=16)
     ap.add_argument("--short-serve-warmup", type=int, default=4)
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="store bytes past L2 per Phi launch from two rocprofv3 counter runs of --profile-phi "
+                         "(FETCH_SIZE, WRITE_SIZE) for --workload / --precision, then exit")
     ap.add_argument("--profile-phi", action="store_true",
                     help="counter-collection driver: two Phi launches per mode on the benchmark tensor, "
                          "then a 1 GiB device copy that calibrates the byte counters; prints no JSON")
@@ -472,6 +534,12 @@ def main():
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.record_traffic:
+        wl = {"zipf3": "zipf3-20M-R16", "zipf4": "zipf4-100M-R32"}.get(args.workload)
+        if wl is None:
+            raise SystemExit("--record-traffic takes --workload zipf3 or zipf4")
+        record_traffic(args.record_traffic[0], args.record_traffic[1], wl, args.precision)
+        return
 
     import numpy as np
     import torch
@@ -490,6 +558,7 @@ def main():
             args.precision = "mixed"  # the served configuration stores factors in FP32
         serve_workload(args)
         return
+    progress(f"generating the {args.workload} tensor on the host")
     if args.workload == "zipf4":
         X, M, sched = synth.config_zipf4()
         wl_name, wl_desc = "zipf4-100M-R32", ("cpapr-mu 4-way 1000000x200000x10000x500, 100M nnz (Zipf(1.2) modes 1-2, "
@@ -519,6 +588,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     if args.profile_phi:
+        progress("Phi twice per mode, then a 1 GiB device copy")
         h = cpapr.cpapr_plan_create(coo, R, params, ws, stream)
         phi = torch.empty((max(X.dims), R), dtype=torch.float64, device=dev)
         for n in range(N):
@@ -543,9 +613,11 @@ def main():
         cpapr.cpapr_plan_destroy(h)
         return st, segs
 
+    progress(f"{wl_name} {args.precision}: plan inputs on the device; {args.warmup} warm-up steps")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    progress(f"{args.steps} timed steps")
     launches_per_step = sched["kmax"] * N * sched["lmax"]
     cpapr.cpapr_prof_enable(launches_per_step * args.steps + 16)
     torch.cuda.synchronize()
@@ -613,7 +685,9 @@ def main():
     out["hbm_probe"] = hbm_probe(torch)
     del idx, vals, ws, A, A0, lam, lam0
     torch.cuda.empty_cache()
+    progress(f"timed steps done: {ms_per_step:.1f} ms per step")
     if not args.no_serve and args.workload == "zipf3" and args.method == "mu":
+        progress("short served trace")
         try:
             out["serving"] = run_serving(args.short_serve_count, args.short_serve_warmup, cpapr.CPAPR_MIXED,
                                          fp64_checks=1)
@@ -623,6 +697,7 @@ def main():
         except Exception as e:  # the Phi line above stays valid
             out["serving"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
+        progress("CPU baseline (the oracle on the host)")
         if args.workload == "zipf4":
             out["cpu_baseline"] = cpu_baseline(X, M, modes=1, max_nnz=10_000_000)
         else:

@@ -129,8 +129,10 @@ def test_phi_quotient_within_a_few_ulps():
     estimate and one Newton step, against the oracle's correctly rounded
     division: a 2-way tensor with R = 1 and one nonzero per row of mode 0, so
     Phi[i] = (x / (b_i a_j)) a_j and every other operation is exact or rounded
-    identically on both sides. The quotient is within two ulps, so with the two
-    products' roundings the largest relative difference is <= 4 * 2^-52."""
+    identically on both sides. The Newton step squares the estimate's relative
+    error e: |error| <= e^2 + 3 * 2^-53 or so; an estimate good to 2^-23.5
+    keeps it within 32 * 2^-52 (measured: 10.2 * 2^-52). Without the Newton
+    step, or with a wrong one, the error is of the order of e itself (~1e-7)."""
     rng = np.random.default_rng(21)
     I, J = 1_000_000, 5000
     idx = np.stack([np.arange(I), rng.integers(0, J, I)]).astype(np.int32)
@@ -142,7 +144,7 @@ def test_phi_quotient_within_a_few_ulps():
     rel = np.abs(got - ref) / np.abs(ref)
     print(f"quotient: largest relative difference {rel.max():.3e} ({rel.max() / 2.0 ** -52:.2f} x 2^-52), "
           f"{np.count_nonzero(rel)} of {I} rows differ", flush=True)
-    assert rel.max() <= 4 * 2.0 ** -52
+    assert rel.max() <= 32 * 2.0 ** -52
     P.close()
 
 
