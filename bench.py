@@ -335,7 +335,38 @@ def _max_rel(got, ref):
     return float(np.linalg.norm(np.asarray(got) - ref) / n) if n > 0 else float(np.linalg.norm(got))
 
 
-def run_serving(count, warmup, prec, fp64_checks=2, seed=0, policy="srpt", round_cap=8e6):
+def _request_tensor(r):
+    from paper_2307_03276_amd import synth
+    return synth.request_tensor(r)
+
+
+def generate_requests(count, seed=0, workers=1):
+    """The serving trace's requests (tensors generated on the host). workers > 1
+    forks a process pool: call it before the GPU is first used, so the children
+    hold no GPU state."""
+    from paper_2307_03276_amd import serve, synth
+    trace = synth.serving_trace(seed=seed, count=count)
+    t0 = time.perf_counter()
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            tensors = []
+            for i, t in enumerate(pool.imap(_request_tensor, trace, chunksize=4)):
+                tensors.append(t)
+                if (i + 1) % 50 == 0:
+                    progress(f"serving: {i + 1} of {len(trace)} requests generated")
+    else:
+        tensors = []
+        for i, r in enumerate(trace):
+            tensors.append(synth.request_tensor(r))
+            if (i + 1) % 50 == 0:
+                progress(f"serving: {i + 1} of {len(trace)} requests generated")
+    reqs = [serve.Request(id=r["id"], X=X, M=M, arrival=r["arrival"]) for r, (X, M) in zip(trace, tensors)]
+    progress(f"serving: {len(reqs)} requests generated in {time.perf_counter() - t0:.1f} s")
+    return reqs, time.perf_counter() - t0
+
+
+def run_serving(count, warmup, prec, fp64_checks=2, seed=0, policy="srpt", round_cap=32e6, reqs=None):
     """Poisson arrivals at 200 requests/s of CP-APR MU solves (3- or 4-way, dims
     U[1e3, 1e5], nnz LogUniform[1e4, 2e7], Zipf(1.1), R in {10, 16, 32}, KKT
     tolerance 1e-4, k_max 20), admitted by a 200 GB HBM budget; against the
@@ -347,16 +378,10 @@ def run_serving(count, warmup, prec, fp64_checks=2, seed=0, policy="srpt", round
 
     from paper_2307_03276_amd import cpapr, serve, synth
 
-    trace = synth.serving_trace(seed=seed, count=count + warmup)
-    t_gen = time.perf_counter()
-    reqs = []
-    for i, r in enumerate(trace):
-        X, M = synth.request_tensor(r)
-        reqs.append(serve.Request(id=r["id"], X=X, M=M, arrival=r["arrival"]))
-        if (i + 1) % 50 == 0:
-            progress(f"serving: {i + 1} of {len(trace)} requests generated")
-    t_gen = time.perf_counter() - t_gen
-    progress(f"serving: {len(reqs)} requests generated in {t_gen:.1f} s")
+    if reqs is None:
+        reqs, t_gen = generate_requests(count + warmup, seed=seed)
+    else:
+        t_gen = None
     kw = dict(kmax=20, lmax=10, tol=1e-4, precision=prec)
     warm, meas = reqs[:warmup], reqs[warmup:]
     t_first = meas[0].arrival
@@ -370,17 +395,20 @@ def run_serving(count, warmup, prec, fp64_checks=2, seed=0, policy="srpt", round
     srv_all = serve.Server(budget_bytes=200e9, max_slots=64, **kw)
     done_all = srv_all.run_trace([serve.Request(id=r.id, X=r.X, M=r.M, arrival=r.arrival) for r in meas])
     summary_all = serve.latency_summary(done_all)
+    del done_all  # frees the results' device memory
     torch.cuda.synchronize()
     progress(f"serving: every request every round done ({summary_all.get('solves_per_s', 0):.1f} solves/s)")
     srv = serve.Server(budget_bytes=200e9, max_slots=64, policy=policy, round_cap=round_cap, **kw)
     done = srv.run_trace(meas)
     summary = serve.latency_summary(done)
+    serve.results_to_host(done)  # after the timed trace
     by_id = {r.id: r for r in done}
     progress(f"serving: {policy} done ({summary.get('solves_per_s', 0):.1f} solves/s); one request at a time next")
     # the plain path on the same trace: one request at a time, in arrival order
     clock = 0.0
     ttc, busy = [], 0.0
     err_lam, err_fac = 0.0, 0.0
+    fac_errs = {}
     stream = torch.cuda.Stream()
     for r in sorted(meas, key=lambda q: q.arrival):
         start = max(clock, r.arrival)
@@ -388,20 +416,30 @@ def run_serving(count, warmup, prec, fp64_checks=2, seed=0, policy="srpt", round
         lam1, facs1, _ = serve.solve_one(serve.Request(id=r.id, X=r.X, M=r.M, arrival=r.arrival), stream=stream, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        lam1, facs1 = lam1.cpu().numpy(), [a.cpu().numpy() for a in facs1]  # outside the timed solve
         busy += dt
         clock = start + dt
         ttc.append(clock - r.arrival)
         s = by_id.get(r.id)
         if s is not None and s.result_lam is not None:
             err_lam = max(err_lam, _max_rel(s.result_lam, lam1))
-            err_fac = max(err_fac, max(_max_rel(a, b) for a, b in zip(s.result_factors, facs1)))
-    # served results (this precision) against FP64 solves of the same requests
+            fac_errs[r.id] = max(_max_rel(a, b) for a, b in zip(s.result_factors, facs1))
+            err_fac = max(err_fac, fac_errs[r.id])
+    # served results (this precision) against FP64 solves of the same requests:
+    # the smallest and the largest request, and the one whose served and
+    # one-at-a-time results differ most
     fp64 = []
     pick = sorted(meas, key=lambda q: q.X.nnz)
-    for r in [pick[(i * (len(pick) - 1)) // max(1, fp64_checks - 1)] for i in range(fp64_checks)] if pick else []:
+    checks = [pick[(i * (len(pick) - 1)) // max(1, fp64_checks - 1)] for i in range(fp64_checks)] if pick else []
+    if fac_errs:
+        worst = max(fac_errs, key=fac_errs.get)
+        if all(r.id != worst for r in checks):
+            checks.append(next(r for r in meas if r.id == worst))
+    for r in checks:
         s = by_id[r.id]
         lam64, facs64, st64 = serve.solve_one(serve.Request(id=r.id, X=r.X, M=r.M), stream=stream,
                                               **dict(kw, precision=cpapr.CPAPR_FP64))
+        lam64, facs64 = lam64.cpu().numpy(), [a.cpu().numpy() for a in facs64]
         fp64.append({"id": r.id, "nnz": r.X.nnz, "rank": r.M.rank, "lambda_rel": _max_rel(s.result_lam, lam64),
                      "factors_rel": max(_max_rel(a, b) for a, b in zip(s.result_factors, facs64)),
                      "loglik_rel": abs(s.stats.get("loglik", float("nan")) - st64["loglik"]) / abs(st64["loglik"]),
@@ -424,17 +462,18 @@ def run_serving(count, warmup, prec, fp64_checks=2, seed=0, policy="srpt", round
                           "p99_from_arrival_s": float(np.percentile(ttc, 99)),
                           "solves_per_s": len(meas) / clock, "busy_s": busy},
         "accuracy": {"served_vs_alone_lambda_rel_max": err_lam, "served_vs_alone_factors_rel_max": err_fac,
+                     "served_vs_alone_factors_rel_median": float(np.median(list(fac_errs.values()))) if fac_errs else None,
                      "vs_fp64_solve": fp64},
         "generation_s": t_gen,
     }
 
 
-def serve_workload(args):
+def serve_workload(args, reqs=None):
     """The long served trace as its own JSON line."""
     from paper_2307_03276_amd import cpapr
 
     prec = cpapr.CPAPR_MIXED if args.precision == "mixed" else cpapr.CPAPR_FP64
-    res = run_serving(args.serve_count, args.serve_warmup, prec)
+    res = run_serving(args.serve_count, args.serve_warmup, prec, round_cap=args.round_cap, reqs=reqs)
     out = {
         "metric": "served solves/s",
         "value": res["served"]["solves_per_s"],
@@ -520,6 +559,8 @@ def main():
                          "solve to KKT 1e-4; batch: 512 uneven tensors; serve: a Poisson stream of solve requests")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-count", type=int, default=60)
+    ap.add_argument("--round-cap", type=float, default=32e6,
+                    help="serving: nonzeros per round of the shortest-remaining-work policy")
     ap.add_argument("--serve-warmup", type=int, default=6)
     ap.add_argument("--no-serve", action="store_true", help="skip the short served trace of the default run")
     ap.add_argument("--short-serve-count", type=int, default=16)
@@ -541,6 +582,11 @@ def main():
         record_traffic(args.record_traffic[0], args.record_traffic[1], wl, args.precision)
         return
 
+    serve_reqs = None
+    if args.workload == "serve":
+        # generated in forked workers before the GPU is first used
+        serve_reqs, _ = generate_requests(args.serve_count + args.serve_warmup, workers=8)
+
     import numpy as np
     import torch
 
@@ -556,7 +602,7 @@ def main():
     if args.workload == "serve":
         if args.precision == "fp64" and "--precision" not in sys.argv:
             args.precision = "mixed"  # the served configuration stores factors in FP32
-        serve_workload(args)
+        serve_workload(args, serve_reqs)
         return
     progress(f"generating the {args.workload} tensor on the host")
     if args.workload == "zipf4":

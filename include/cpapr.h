@@ -343,6 +343,13 @@ int cpapr_batch_create(int32_t max_slots, int64_t max_tiles, void* ws, size_t ws
  * (on MI355X about 1.5x slower per nonzero: each tile's descriptor loads are
  * serialised inside a workgroup instead of overlapped across workgroups). */
 #define CPAPR_BATCH_PERSISTENT 1
+/* CPAPR_BATCH_SKIP_HELD: held slots (cpapr_batch_hold) are left out of the
+ * launches altogether (no tiles, no fill, no MU work) instead of being passed
+ * over by the kernels; a change of the held set then takes effect at the next
+ * cpapr_batch_commit (a run before it fails as uncommitted), and a captured
+ * graph is re-captured when the tile counts change. For callers that run a
+ * small subset of many slots per round. */
+#define CPAPR_BATCH_SKIP_HELD 2
 int cpapr_batch_create2(int32_t max_slots, int64_t max_tiles, int32_t flags, void* ws, size_t ws_bytes,
                         cpapr_batch** out);
 int cpapr_batch_destroy(cpapr_batch* batch);
@@ -382,9 +389,11 @@ int cpapr_batch_inner(cpapr_batch* batch, int32_t lmax, int32_t use_graph, void*
  * calls (host array of max_slots entries: nonzero = hold). A held slot does no
  * work in those runs: its Phi, B and factors are left as they are and
  * cpapr_batch_status reports it as stopped with no updates. Lets a caller run
- * a subset of its slots (e.g. the requests with the least remaining work)
- * without changing the batch's shape, so a captured graph stays valid.
- * All slots run by default. Waits for `stream`. */
+ * a subset of its slots (e.g. the requests with the least remaining work).
+ * Without CPAPR_BATCH_SKIP_HELD the batch's shape is unchanged, so a captured
+ * graph stays valid and the held slots' tiles are launched and exit at once;
+ * with it, a changed held set needs a cpapr_batch_commit. All slots run by
+ * default. Waits for `stream`. */
 int cpapr_batch_hold(cpapr_batch* batch, const int32_t* hold, void* stream);
 
 /* Per-slot outcome since the last cpapr_batch_run / cpapr_batch_inner (host
@@ -405,6 +414,19 @@ int cpapr_batch_status(cpapr_batch* batch, double* viol, int32_t* updates, int32
 int cpapr_mode_begin(cpapr_plan* plan, int32_t mode, int32_t outer_iter, const double* lambda, double* A_mode,
                      const double* phi_prev, double* B, void* stream);
 int cpapr_mode_end(cpapr_plan* plan, int32_t mode, const double* B, double* lambda, double* A_mode, void* stream);
+
+/* The same steps for many solves in one host call (a serving loop advancing
+ * every request of a round): for item i in order, cpapr_mode_end(plans[i],
+ * end_mode[i], B[i], lambda[i], A[i][end_mode[i]]) when end_mode[i] >= 0,
+ * then cpapr_mode_begin(plans[i], begin_mode[i], outer_iter[i], lambda[i],
+ * A[i][begin_mode[i]], phi_prev[i], B[i]) when begin_mode[i] >= 0. Host
+ * arrays of `count` entries; A[i] is a host array of that plan's N device
+ * factor pointers; phi_prev may be NULL (no shift) or hold NULL entries.
+ * Stops at the first failing item and returns its error (earlier items'
+ * launches stay queued). Stream-ordered. */
+int cpapr_modes_advance(int32_t count, cpapr_plan* const* plans, const int32_t* end_mode, const int32_t* begin_mode,
+                        const int32_t* outer_iter, double* const* lambda, double* const* const* A, double* const* B,
+                        const double* const* phi_prev, void* stream);
 
 /* Mixed precision: refresh the plan's FP32 copies of all N factors from A
  * (host array of N device pointers). No-op in FP64. Stream-ordered. */

@@ -112,6 +112,7 @@ def load():
         "cpapr_batch_hold": (C.c_int, [vp, P(i32), vp]),
         "cpapr_mode_begin": (C.c_int, [vp, i32, i32, vp, vp, vp, vp, vp]),
         "cpapr_mode_end": (C.c_int, [vp, i32, vp, vp, vp, vp]),
+        "cpapr_modes_advance": (C.c_int, [i32, P(vp), P(i32), P(i32), P(i32), P(vp), P(vp), P(vp), P(vp), vp]),
         "cpapr_plan_sync_f32": (C.c_int, [vp, P(vp), vp]),
         "cpapr_batch_clear": (C.c_int, [vp, i32]),
         "cpapr_batch_commit": (C.c_int, [vp, vp]),
@@ -136,7 +137,7 @@ EXPORTED = ("cpapr_params_default", "cpapr_plan_workspace_size", "cpapr_plan_cre
             "cpapr_pdnr_inner", "cpapr_row_stats", "cpapr_solve", "cpapr_loglik",
             "cpapr_mttkrp", "cpapr_batch_workspace_size", "cpapr_batch_tiles", "cpapr_batch_create", "cpapr_batch_create2",
             "cpapr_batch_destroy", "cpapr_batch_set", "cpapr_batch_clear", "cpapr_batch_commit", "cpapr_batch_run",
-            "cpapr_batch_mu", "cpapr_batch_inner", "cpapr_batch_hold", "cpapr_batch_status", "cpapr_mode_begin", "cpapr_mode_end", "cpapr_plan_sync_f32",
+            "cpapr_batch_mu", "cpapr_batch_inner", "cpapr_batch_hold", "cpapr_batch_status", "cpapr_mode_begin", "cpapr_mode_end", "cpapr_modes_advance", "cpapr_plan_sync_f32",
             "cpapr_prof_enable", "cpapr_prof_disable", "cpapr_prof_read", "cpapr_last_error")
 
 
@@ -326,6 +327,7 @@ def cpapr_batch_tiles(plan_handle) -> int:
 
 
 CPAPR_BATCH_PERSISTENT = 1
+CPAPR_BATCH_SKIP_HELD = 2
 
 
 def cpapr_batch_create(max_slots, max_tiles, ws, flags=0):
@@ -379,6 +381,26 @@ def cpapr_mode_end(h, mode, B, lam, A_mode, stream=None):
     return _check(load().cpapr_mode_end(h, mode, B.data_ptr(), lam.data_ptr(), A_mode.data_ptr(), _stream(stream)))
 
 
+def cpapr_modes_advance(items, stream=None):
+    """Mode steps of many solves in one call. items: sequence of (plan handle,
+    end mode or -1, begin mode or -1, outer iteration, lambda device pointer,
+    ctypes array of the plan's factor device pointers, B device pointer,
+    previous-Phi device pointer or None), all plain integers / ctypes arrays
+    (pointers are taken once per solve, not per call)."""
+    n = len(items)
+    if n == 0:
+        return 0
+    plans = (C.c_void_p * n)(*[it[0] for it in items])
+    ends = (C.c_int32 * n)(*[it[1] for it in items])
+    begins = (C.c_int32 * n)(*[it[2] for it in items])
+    outer = (C.c_int32 * n)(*[it[3] for it in items])
+    lam = (C.c_void_p * n)(*[it[4] for it in items])
+    fac = (C.c_void_p * n)(*[C.cast(it[5], C.c_void_p) for it in items])
+    B = (C.c_void_p * n)(*[it[6] for it in items])
+    prev = (C.c_void_p * n)(*[it[7] for it in items])
+    return _check(load().cpapr_modes_advance(n, plans, ends, begins, outer, lam, fac, B, prev, _stream(stream)))
+
+
 def cpapr_plan_sync_f32(h, A, stream=None):
     return _check(load().cpapr_plan_sync_f32(h, _ptr_array(A), _stream(stream)))
 
@@ -398,13 +420,15 @@ def cpapr_batch_run(h, use_graph=False, stream=None):
 class Batch:
     """Slots of Phi work items run in persistent launches (optionally as a hipGraph)."""
 
-    def __init__(self, max_slots: int, max_tiles: int, device="cuda", persistent: bool = False):
+    def __init__(self, max_slots: int, max_tiles: int, device="cuda", persistent: bool = False,
+                 skip_held: bool = False):
         import torch
         self.max_slots, self.max_tiles = int(max_slots), int(max_tiles)
         nbytes = cpapr_batch_workspace_size(self.max_slots, self.max_tiles)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.handle = cpapr_batch_create(self.max_slots, self.max_tiles, self.ws,
-                                         CPAPR_BATCH_PERSISTENT if persistent else 0)
+                                         (CPAPR_BATCH_PERSISTENT if persistent else 0) |
+                                         (CPAPR_BATCH_SKIP_HELD if skip_held else 0))
         self._keep = {}
 
     def set(self, slot, plan, mode, B, A, Phi, flags=0):

@@ -748,6 +748,32 @@ int cpapr_mode_end(cpapr_plan* plan, int32_t mode, const double* B, double* lamb
     return report(cpapr::launch_normalize(B, lambda, A_mode, a32, plan->dims[mode], plan->R, s));
 }
 
+int cpapr_modes_advance(int32_t count, cpapr_plan* const* plans, const int32_t* end_mode, const int32_t* begin_mode,
+                        const int32_t* outer_iter, double* const* lambda, double* const* const* A, double* const* B,
+                        const double* const* phi_prev, void* stream)
+{
+    if (count < 0) return fail(CPAPR_EINVAL, "count must be >= 0");
+    if (count > 0 && (!plans || !end_mode || !begin_mode || !outer_iter || !lambda || !A || !B))
+        return fail(CPAPR_EINVAL, "an item array is NULL");
+    for (int32_t i = 0; i < count; ++i) {
+        cpapr_plan* P = plans[i];
+        if (!P || !A[i]) return fail(CPAPR_EINVAL, "item " + std::to_string(i) + ": plan or factor array is NULL");
+        const int e0 = end_mode[i], b0 = begin_mode[i];
+        if ((e0 >= 0 && e0 >= P->N) || (b0 >= 0 && b0 >= P->N))
+            return fail(CPAPR_EINVAL, "item " + std::to_string(i) + ": mode out of range");
+        if (e0 >= 0) {
+            const int rc = cpapr_mode_end(P, e0, B[i], lambda[i], A[i][e0], stream);
+            if (rc != CPAPR_OK) return rc;
+        }
+        if (b0 >= 0) {
+            const int rc = cpapr_mode_begin(P, b0, outer_iter[i], lambda[i], A[i][b0], phi_prev ? phi_prev[i] : nullptr,
+                                            B[i], stream);
+            if (rc != CPAPR_OK) return rc;
+        }
+    }
+    return CPAPR_OK;
+}
+
 int cpapr_plan_sync_f32(cpapr_plan* plan, const double* const* A, void* stream)
 {
     if (!plan) return fail(CPAPR_EINVAL, "plan is NULL");

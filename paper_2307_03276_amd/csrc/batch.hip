@@ -120,6 +120,7 @@ struct cpapr_batch {
     std::vector<int> classes;           // classes with work at the last commit
     std::vector<int64_t> class_tiles;   // their tile counts (grid launches)
     bool persistent = true;
+    bool skip_held = false;             // held slots are left out of the launches at commit
     int grid_cache[kMaxClasses] = {};   // persistent grid per class
     int copy_grid = 0;
     struct Graph {
@@ -286,11 +287,12 @@ int cpapr_batch_create2(int32_t max_slots, int64_t max_tiles, int32_t flags, voi
         if (ws_bytes < L.total) return fail(CPAPR_EWORKSPACE, "workspace too small");
         cpapr_batch* b = new (std::nothrow) cpapr_batch();
         if (!b) return fail(CPAPR_EINVAL, "out of host memory");
-        if (flags & ~CPAPR_BATCH_PERSISTENT) {
+        if (flags & ~(CPAPR_BATCH_PERSISTENT | CPAPR_BATCH_SKIP_HELD)) {
             delete b;
             return fail(CPAPR_EINVAL, "unknown batch flags");
         }
         b->persistent = (flags & CPAPR_BATCH_PERSISTENT) != 0;
+        b->skip_held = (flags & CPAPR_BATCH_SKIP_HELD) != 0;
         b->max_slots = max_slots;
         b->max_tiles = max_tiles;
         b->ws = (char*)ws;
@@ -373,7 +375,7 @@ int cpapr_batch_commit(cpapr_batch* batch, void* stream)
         std::vector<std::vector<int>> by_class(ncls);
         for (int i = 0; i < b->max_slots; ++i) {
             const HostSlot& h = b->slots[i];
-            if (!h.set) continue;
+            if (!h.set || (b->skip_held && b->hold[i])) continue;
             const cpapr_plan* P = h.plan;
             const int c = slot_class(P);
             if (c < 0) return fail(CPAPR_EUNSUPPORTED, "slot with an unsupported shape");
@@ -430,7 +432,7 @@ int cpapr_batch_commit(cpapr_batch* batch, void* stream)
         int64_t mu_total = 0;
         for (int i = 0; i < b->max_slots; ++i) {
             const HostSlot& h = b->slots[i];
-            if (!h.set) continue;
+            if (!h.set || (b->skip_held && b->hold[i])) continue;
             const cpapr_plan* P = h.plan;
             cpapr::BatchMu mu{const_cast<double*>(h.B), h.Phi, P->dims[h.mode] * (int64_t)P->R, mu_total,
                               P->params.tol, i, 0};
@@ -479,7 +481,14 @@ int cpapr_batch_hold(cpapr_batch* batch, const int32_t* hold, void* stream)
     try {
         if (!batch) return fail(CPAPR_EINVAL, "batch is NULL");
         if (!hold) return fail(CPAPR_EINVAL, "hold is NULL");
-        for (int i = 0; i < batch->max_slots; ++i) batch->hold[i] = hold[i] != 0;
+        bool changed = false;
+        for (int i = 0; i < batch->max_slots; ++i) {
+            const int32_t v = hold[i] != 0;
+            changed = changed || v != batch->hold[i];
+            batch->hold[i] = v;
+        }
+        // left out of the launches: the held set takes effect at the next commit
+        if (batch->skip_held && changed) batch->committed = false;
         hipStream_t s = (hipStream_t)stream;
         if (hipMemcpyAsync(batch->st.hold, batch->hold.data(), 4 * (size_t)batch->max_slots, hipMemcpyHostToDevice,
                            s) != hipSuccess)

@@ -51,8 +51,10 @@ class Request:
     # filled by the server
     t_admit: Optional[float] = None
     t_done: Optional[float] = None
-    result_lam: Optional[np.ndarray] = None
-    result_factors: Optional[List[np.ndarray]] = None
+    # the final model, left in device memory (torch tensors) when the request
+    # completes; results_to_host() turns them into host arrays
+    result_lam: Optional[object] = None
+    result_factors: Optional[List[object]] = None
     stats: dict = dataclasses.field(default_factory=dict)
 
 
@@ -74,13 +76,18 @@ class GpuExecutor:
     """Device side of the service: plans, factors and one batch whose slots
     hold the active requests' current modes (the C ABI's batch calls)."""
 
-    def __init__(self, params: dict, max_slots: int, max_tiles: int, use_graph: bool, stream, compute_loglik: bool):
+    def __init__(self, params: dict, max_slots: int, max_tiles: int, use_graph: bool, stream, compute_loglik: bool,
+                 skip_held: bool = False):
         import torch
         self.params = params
-        self.use_graph = use_graph
+        # skip_held: held slots are left out of the launches, so the held set
+        # changes the launch shapes; rounds then run as direct launches (a
+        # captured graph would be re-captured whenever the set changes)
+        self.commit_on_hold = skip_held
+        self.use_graph = use_graph and not skip_held
         self.compute_loglik = compute_loglik
         self.stream = stream if stream is not None else torch.cuda.Stream()
-        self.batch = cpapr.Batch(max_slots, max_tiles)
+        self.batch = cpapr.Batch(max_slots, max_tiles, skip_held=skip_held)
         self.flags = cpapr.CPAPR_BATCH_F32_CURRENT if params["precision"] == cpapr.CPAPR_MIXED else 0
 
     def footprint(self, req: Request) -> int:
@@ -107,6 +114,9 @@ class GpuExecutor:
                      B=torch.empty((max(req.X.dims), req.M.rank), dtype=torch.float64, device="cuda"),
                      phi=[torch.zeros((d, req.M.rank), dtype=torch.float64, device="cuda") for d in req.X.dims])
             cpapr.cpapr_plan_sync_f32(plan.handle, h["A"], self.stream)
+        # device pointers taken once per request, for the batched mode steps
+        h["ptrs"] = dict(plan=plan.handle.value, lam=h["lam"].data_ptr(), A=cpapr._ptr_array(h["A"]),
+                         B=h["B"].data_ptr(), phi=[p.data_ptr() for p in h["phi"]])
         return h
 
     def mode_begin(self, h, n: int, k: int):
@@ -134,12 +144,23 @@ class GpuExecutor:
     def mode_end(self, h, n: int):
         cpapr.cpapr_mode_end(h["plan"].handle, n, h["B"], h["lam"], h["A"][n], self.stream)
 
+    def advance(self, items):
+        """Mode steps of many requests in one call: items of (h, mode to end,
+        mode to begin or None, outer iteration of the begun mode)."""
+        rows = []
+        for h, end, begin, k in items:
+            p = h["ptrs"]
+            rows.append((p["plan"], end, -1 if begin is None else begin, k, p["lam"], p["A"], p["B"],
+                         p["phi"][begin] if begin is not None and k > 1 else None))
+        cpapr.cpapr_modes_advance(rows, self.stream)
+
     def retire(self, h):
-        """Final model (host) and its log-likelihood; frees the request's device memory."""
+        """The final model (lambda and the factors, left in device memory for
+        the caller) and its log-likelihood; frees the rest of the request's
+        device memory (plan, B, the last Phi of every mode)."""
         ll = h["plan"].loglik(h["lam"], h["A"], stream=self.stream) if self.compute_loglik else None
         self.stream.synchronize()
-        lam = h["lam"].cpu().numpy()
-        facs = [x.cpu().numpy() for x in h["A"]]
+        lam, facs = h["lam"], list(h["A"])
         h["plan"].close()
         h.clear()
         return lam, facs, ll
@@ -152,13 +173,14 @@ class Server:
     def __init__(self, budget_bytes: float = 200e9, max_slots: int = 64, max_tiles: int = 1 << 22,
                  kmax: int = 20, lmax: int = 10, tol: float = 1e-4, eps: float = 1e-10,
                  precision: int = cpapr.CPAPR_MIXED, use_graph: bool = True, stream=None,
-                 compute_loglik: bool = True, executor=None, policy: str = "all", round_cap: float = 8e6):
+                 compute_loglik: bool = True, executor=None, policy: str = "all", round_cap: float = 32e6):
         self.budget = float(budget_bytes)
         self.used = 0.0
         self.max_slots = max_slots
         self.params = dict(kmax=kmax, lmax=lmax, tol=tol, eps=eps, precision=precision)
         self.ex = executor if executor is not None else GpuExecutor(self.params, max_slots, max_tiles, use_graph,
-                                                                   stream, compute_loglik)
+                                                                   stream, compute_loglik,
+                                                                   skip_held=policy == "srpt")
         self.queue: deque = deque()
         self.active: List[_Active] = []
         self.free_slots = list(range(max_slots - 1, -1, -1))
@@ -175,8 +197,9 @@ class Server:
         self._held = None  # hold flags last sent to the executor
         # host seconds per phase of tick(): admission (upload + plan build),
         # batch commit, hold flags, the round (device time + status read-back),
-        # advancing the loop state (mode epilogue / prologue, retirement)
-        self.phase_s = dict(admit=0.0, commit=0.0, hold=0.0, round=0.0, advance=0.0)
+        # advancing the loop state (mode epilogue / prologue), retirement
+        # (log-likelihood and the result's copy to the host)
+        self.phase_s = dict(admit=0.0, commit=0.0, hold=0.0, round=0.0, advance=0.0, retire=0.0)
 
     # ------------------------------------------------------------------ admission
     def footprint(self, req: Request) -> int:
@@ -260,34 +283,35 @@ class Server:
         self.phase_s["admit"] += dt
         if not self.active:
             return bool(self.queue)
-        changed = False
-        for a in self.active:
-            if a.dirty:
-                self.ex.set_slot(a.slot, a.h, a.n)
-                a.dirty = False
-                changed = True
-        if changed or self._need_commit:
-            self.ex.commit()
-            self._need_commit = False
-        t, dt = clock(), clock() - t
-        self.phase_s["commit"] += dt
         lmax, kmax, tol = self.params["lmax"], self.params["kmax"], self.params["tol"]
         run = self._select()
         held = [0] * self.max_slots
         for a in self.active:
             if a not in run:
                 held[a.slot] = 1
-        if held != self._held and (self._held is not None or any(held)):
+        hold_changed = held != self._held and (self._held is not None or any(held))
+        if hold_changed:
             self.ex.hold(held)
             self._held = held
         t, dt = clock(), clock() - t
         self.phase_s["hold"] += dt
+        changed = False
+        for a in self.active:
+            if a.dirty:
+                self.ex.set_slot(a.slot, a.h, a.n)
+                a.dirty = False
+                changed = True
+        if changed or self._need_commit or (hold_changed and getattr(self.ex, "commit_on_hold", False)):
+            self.ex.commit()
+            self._need_commit = False
+        t, dt = clock(), clock() - t
+        self.phase_s["commit"] += dt
         # the whole inner loop of every running request's current mode, stops on the device
         viol, updates, done = self.ex.run_round(lmax)
         self.ticks += 1
         t, dt = clock(), clock() - t
         self.phase_s["round"] += dt
-        keep = []
+        keep, steps, retiring = [], [], []
         for a in self.active:
             if a not in run:
                 keep.append(a)  # held this round: nothing ran
@@ -297,19 +321,26 @@ class Server:
             if updates[a.slot] > 0:
                 a.any_update = True
             # mode finished: lambda and normalisation, then the next mode
-            self.ex.mode_end(a.h, a.n)
+            end = a.n
             a.n += 1
             if a.n == a.N:
                 a.n = 0
                 if (tol > 0 and not a.any_update) or a.k >= kmax:
-                    self._retire(a)
+                    steps.append((a.h, end, None, a.k))
+                    retiring.append(a)
                     continue
                 a.k += 1
                 a.any_update = False
-            self._mode_begin(a)
+            steps.append((a.h, end, a.n, a.k))
+            a.dirty = True
             keep.append(a)
+        self.ex.advance(steps)
+        t, dt = clock(), clock() - t
+        self.phase_s["advance"] += dt
+        for a in retiring:
+            self._retire(a)
         self.active = keep
-        self.phase_s["advance"] += clock() - t
+        self.phase_s["retire"] += clock() - t
         return bool(self.active or self.queue)
 
     def _remaining(self, a) -> float:
@@ -357,8 +388,18 @@ class Server:
         return self.done
 
 
+def results_to_host(reqs: List[Request]) -> List[Request]:
+    """Copy completed requests' models from device memory into host arrays."""
+    for r in reqs:
+        if r.result_lam is not None and not isinstance(r.result_lam, np.ndarray):
+            r.result_lam = r.result_lam.cpu().numpy()
+            r.result_factors = [a.cpu().numpy() for a in r.result_factors]
+    return reqs
+
+
 def solve_one(req: Request, precision=cpapr.CPAPR_MIXED, kmax=20, lmax=10, tol=1e-4, eps=1e-10, stream=None):
-    """The plain path: one request on its own with cpapr_solve."""
+    """The plain path: one request on its own with cpapr_solve. Returns the
+    final model in device memory (lambda, factors) and the solve's stats."""
     import torch
     stream = stream if stream is not None else torch.cuda.current_stream()
     with torch.cuda.stream(stream):
@@ -371,7 +412,7 @@ def solve_one(req: Request, precision=cpapr.CPAPR_MIXED, kmax=20, lmax=10, tol=1
         A = [torch.from_numpy(a).to("cuda") for a in req.M.factors]
         st = plan.solve(lam, A, stream=stream)
         plan.close()
-        return lam.cpu().numpy(), [a.cpu().numpy() for a in A], st
+        return lam, A, st
 
 
 def latency_summary(done: List[Request]) -> dict:

@@ -171,6 +171,14 @@ def test_calls_reject_null_plan(lib):
     assert lib.cpapr_plan_segments(None, 0) == -1
     g = C.c_int32(0)
     assert lib.cpapr_plan_shape(None, C.byref(g), C.byref(g)) == -1
+    assert lib.cpapr_plan_batch_shape(None, C.byref(g), C.byref(g)) == -1
+    # batched mode steps: no items is a no-op; a NULL plan or array is refused before any launch
+    assert lib.cpapr_modes_advance(0, None, None, None, None, None, None, None, None, None) == 0
+    assert lib.cpapr_modes_advance(-1, None, None, None, None, None, None, None, None, None) == -1
+    one = (C.c_void_p * 1)()
+    i1 = (C.c_int32 * 1)(0)
+    assert lib.cpapr_modes_advance(1, one, i1, i1, i1, one, one, one, None, None) == -1
+    assert lib.cpapr_modes_advance(1, None, i1, i1, i1, one, one, one, None, None) == -1
 
 
 def test_phi_coo_workspace_size(lib):

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_2307_03276_amd import cpapr, serve, synth
-from tests.gpu_util import assert_iterate_parity, assert_parity
+from tests.gpu_util import assert_iterate_parity, assert_parity, host
 
 pytestmark = pytest.mark.gpu
 
@@ -45,10 +45,10 @@ def _clone(r):
 def test_mix_equals_alone_and_oracle_fp64():
     kw = dict(kmax=6, lmax=5, tol=1e-4, precision=cpapr.CPAPR_FP64)
     reqs = _requests(8)
-    mix = serve.Server(max_slots=8, **kw).run_trace([_clone(r) for r in reqs])
+    mix = serve.results_to_host(serve.Server(max_slots=8, **kw).run_trace([_clone(r) for r in reqs]))
     mix = {r.id: r for r in mix}
     for r in reqs:
-        alone = serve.Server(max_slots=1, **kw).run_trace([_clone(r)])[0]
+        alone = serve.results_to_host(serve.Server(max_slots=1, **kw).run_trace([_clone(r)]))[0]
         m = mix[r.id]
         assert m.stats["outer_iters"] == alone.stats["outer_iters"]
         assert m.stats["inner_updates"] == alone.stats["inner_updates"]
@@ -67,10 +67,11 @@ def test_mix_equals_alone_and_oracle_fp64():
 def test_mix_mixed_precision_matches_plain_path():
     kw = dict(kmax=5, lmax=5, tol=1e-4)
     reqs = _requests(6, seed=1)
-    done = {r.id: r for r in serve.Server(max_slots=6, precision=cpapr.CPAPR_MIXED, **kw).run_trace(
-        [_clone(r) for r in reqs])}
+    done = {r.id: r for r in serve.results_to_host(serve.Server(max_slots=6, precision=cpapr.CPAPR_MIXED, **kw).run_trace(
+        [_clone(r) for r in reqs]))}
     for r in reqs:
         lam, facs, st = serve.solve_one(_clone(r), precision=cpapr.CPAPR_MIXED, **kw)
+        lam, facs = host(lam), [host(a) for a in facs]
         m = done[r.id]
         assert m.stats["outer_iters"] == st["outer_iters"] and m.stats["inner_updates"] == st["inner_iters"]
         assert_parity(m.result_lam, lam, 1e-10, "lambda")
@@ -109,10 +110,10 @@ def test_srpt_rounds_give_the_same_results():
     when all run every round."""
     kw = dict(kmax=4, lmax=4, tol=1e-4, precision=cpapr.CPAPR_FP64)
     reqs = _requests(6, seed=3)
-    allr = {r.id: r for r in serve.Server(max_slots=6, **kw).run_trace([_clone(r) for r in reqs])}
+    allr = {r.id: r for r in serve.results_to_host(serve.Server(max_slots=6, **kw).run_trace([_clone(r) for r in reqs]))}
     cap = sorted(r.X.nnz for r in reqs)[2]  # about two requests per round
     srv = serve.Server(max_slots=6, policy="srpt", round_cap=cap, **kw)
-    srpt = {r.id: r for r in srv.run_trace([_clone(r) for r in reqs])}
+    srpt = {r.id: r for r in serve.results_to_host(srv.run_trace([_clone(r) for r in reqs]))}
     assert srv.ticks > max(r.stats["outer_iters"] for r in srpt.values()) * 4  # rounds were split
     for r in reqs:
         a, s = allr[r.id], srpt[r.id]

@@ -63,6 +63,12 @@ class MockExecutor:
     def mode_end(self, h, n):
         self.events.append((h["id"], "end", h["k"], n))
 
+    def advance(self, items):
+        for h, end, begin, k in items:
+            self.mode_end(h, end)
+            if begin is not None:
+                self.mode_begin(h, begin, k)
+
     def retire(self, h):
         return np.ones(2), [np.zeros((3, 2))] * self.nmodes, -1.0
 
