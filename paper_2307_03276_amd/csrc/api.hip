@@ -185,11 +185,14 @@ Error phi_factors(cpapr_plan* P, int mode, const double* const* A, const void** 
 }
 
 // One inner loop (Algorithm 1): zero Phi, then lmax x {Phi, KKT, MU update},
-// all gated by the device-side `done` flag. No host synchronisation.
+// all gated by the device-side `done` flag. No host synchronisation. With a
+// fixed schedule (tol <= 0) nothing depends on the violation before the
+// update, so KKT and update are one pass over B and Phi.
 Error enqueue_inner(cpapr_plan* P, int mode, double* B, const void* const* fac, double* Phi, hipStream_t s)
 {
     const int64_t n = P->dims[mode] * (int64_t)P->R;
     const bool mixed = P->params.precision == CPAPR_MIXED;
+    const bool fused = !(P->params.tol > 0.0);
     const int* done = &P->state->done;
     Error e = cpapr::launch_fill(Phi, n, 0.0, done, s);
     if (e.code) return e;
@@ -197,12 +200,17 @@ Error enqueue_inner(cpapr_plan* P, int mode, double* B, const void* const* fac, 
     for (int l = 0; l < lmax; ++l) {
         e = cpapr::launch_phi(P, mode, B, fac, mixed, P->params.eps, Phi, done, s);
         if (e.code) return e;
-        e = cpapr::launch_kkt(B, Phi, n, P->state, l, s);
-        if (e.code) return e;
         // the update clears Phi for the next Phi launch, except after the last one
-        e = cpapr::launch_mu_update(B, Phi, n, P->state, l, mode, P->params.tol, l + 1 < lmax, s);
+        if (fused) {
+            e = cpapr::launch_mu_fused(B, Phi, n, P->state, l, mode, l + 1 < lmax, s);
+        } else {
+            e = cpapr::launch_kkt(B, Phi, n, P->state, l, s);
+            if (e.code) return e;
+            e = cpapr::launch_mu_update(B, Phi, n, P->state, l, mode, P->params.tol, l + 1 < lmax, s);
+        }
         if (e.code) return e;
     }
+    if (fused && lmax > 0) return cpapr::launch_kkt_fold(P->state, lmax - 1, mode, s);
     return {CPAPR_OK, ""};
 }
 

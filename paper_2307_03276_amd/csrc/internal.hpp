@@ -277,6 +277,10 @@ Error enqueue_pdnr_inner(cpapr_plan* P, int mode, double* B, const void* const* 
 Error launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 Error launch_reset_state(DevState* st, bool new_sweep, bool all, hipStream_t s);
 Error launch_kkt(const double* B, const double* Phi, int64_t n, DevState* st, int l, hipStream_t s);
+// tol <= 0: the KKT violation and the update in one pass (the violation reaches
+// last_viol one launch later; launch_kkt_fold after the last iteration).
+Error launch_mu_fused(double* B, double* Phi, int64_t n, DevState* st, int l, int mode, bool zero_phi, hipStream_t s);
+Error launch_kkt_fold(DevState* st, int l, int mode, hipStream_t s);
 Error launch_mu_update(double* B, double* Phi, int64_t n, DevState* st, int l, int mode, double tol, bool zero_phi,
                        hipStream_t s);
 Error launch_shift_scale(double* A, const double* phi_prev, const double* lam, double* B, int64_t I, int R,

@@ -134,6 +134,62 @@ __global__ __launch_bounds__(kBlock) void mu_update_kernel(double* __restrict__ 
     }
 }
 
+// A fixed schedule (tol <= 0) takes no stop decision, so iteration l's KKT
+// violation (before the update) and the update go through the entries in one
+// pass: B <- B .* Phi (Phi cleared for the next accumulation with zero_phi)
+// while the block maxima of |min(B, 1 - Phi)| fold into the slots of parity
+// l & 1. Block 0 folds the previous iteration's slots (complete: that launch
+// has finished) into last_viol and clears them for iteration l + 1; after the
+// last iteration kkt_fold_kernel folds its slots. Counters as kkt_kernel and
+// mu_update_kernel keep them.
+__global__ __launch_bounds__(kBlock) void mu_fused_kernel(double* __restrict__ B, double* __restrict__ Phi, int64_t n,
+                                                          DevState* st, int l, int mode, int zero_phi)
+{
+    if (st->done) return;
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+        const int prev = (l + 1) & 1;
+        if (l > 0) {
+            double v = __longlong_as_double((long long)st->viol[prev][threadIdx.x * kViolStride]);
+            v = wave_max(v);
+            if (threadIdx.x == 0) st->last_viol[mode] = v;
+        }
+        if (threadIdx.x < kViolSlots) st->viol[prev][threadIdx.x * kViolStride] = 0ull;
+        if (threadIdx.x == 0) {
+            st->phi_evals += 1;
+            st->updates += 1;
+            st->sweep_updates += 1;
+            st->total_updates += 1;
+        }
+    }
+    double v = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const double b = B[i], p = Phi[i], q = 1.0 - p;
+        v = fmax(v, fabs(b < q ? b : q));
+        B[i] = b * p;
+        if (zero_phi) Phi[i] = 0.0;
+    }
+    __shared__ double red[kBlock / 64];
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < kBlock / 64; ++w) m = fmax(m, red[w]);
+        atomicMax(&st->viol[l & 1][(blockIdx.x % kViolSlots) * kViolStride], (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// The last iteration's violation of a fused loop: fold its slots into
+// last_viol and clear them.
+__global__ __launch_bounds__(64) void kkt_fold_kernel(DevState* st, int l, int mode)
+{
+    if (st->done) return;
+    double v = __longlong_as_double((long long)st->viol[l & 1][threadIdx.x * kViolStride]);
+    v = wave_max(v);
+    if (threadIdx.x == 0) st->last_viol[mode] = v;
+    if (threadIdx.x < kViolSlots) st->viol[l & 1][threadIdx.x * kViolStride] = 0ull;
+}
+
 // A(n) += kappa where A < kappa_tol and the previous Phi > 1 (from the second
 // outer iteration on), then B = A(n) diag(lambda).
 __global__ __launch_bounds__(kBlock) void shift_scale_kernel(double* __restrict__ A,
@@ -383,6 +439,20 @@ Error launch_mu_update(double* B, double* Phi, int64_t n, DevState* st, int l, i
                        hipStream_t s)
 {
     mu_update_kernel<<<grid_for(n, 4096), kBlock, 0, s>>>(B, Phi, n, st, l, mode, tol, zero_phi ? 1 : 0);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+Error launch_mu_fused(double* B, double* Phi, int64_t n, DevState* st, int l, int mode, bool zero_phi, hipStream_t s)
+{
+    mu_fused_kernel<<<grid_for(n, 4096), kBlock, 0, s>>>(B, Phi, n, st, l, mode, zero_phi ? 1 : 0);
+    CPAPR_LAUNCHED();
+    return {CPAPR_OK, ""};
+}
+
+Error launch_kkt_fold(DevState* st, int l, int mode, hipStream_t s)
+{
+    kkt_fold_kernel<<<1, 64, 0, s>>>(st, l, mode);
     CPAPR_LAUNCHED();
     return {CPAPR_OK, ""};
 }
