@@ -94,6 +94,7 @@ Error check_params(const cpapr_params* p, int32_t R, int nmodes)
 // partials, column sums and the device state block.
 struct Layout {
     size_t mode_rows[CPAPR_MAX_MODES], mode_cidx[CPAPR_MAX_MODES], mode_vals[CPAPR_MAX_MODES];
+    size_t mode_pk[CPAPR_MAX_MODES];  // packed records (N <= 3), size 0 otherwise
     size_t f32[CPAPR_MAX_MODES];
     size_t region2;
     size_t B, phi_prev[CPAPR_MAX_MODES], partial, llpart, colsums, state, pqnr, pdnr, det_part, det_rows;
@@ -111,6 +112,8 @@ Layout layout(int N, int64_t nnz, const int64_t* dims, int R, bool mixed, int me
         off += align256((size_t)nnz * 4 * (N - 1));
         L.mode_vals[n] = off;
         off += align256((size_t)nnz * 8);
+        L.mode_pk[n] = off;
+        if (N <= 3) off += align256((size_t)nnz * 16);
     }
     for (int n = 0; n < N; ++n) {
         L.f32[n] = off;
@@ -402,6 +405,7 @@ int cpapr_plan_create(const cpapr_coo* X, int32_t R, const cpapr_params* p, void
             P->mode[n].rows = (int32_t*)(w + L.mode_rows[n]);
             P->mode[n].cofs = (uint32_t*)(w + L.mode_cidx[n]);
             P->mode[n].vals = (double*)(w + L.mode_vals[n]);
+            P->mode[n].pk = P->N <= 3 && X->nnz > 0 ? (int4*)(w + L.mode_pk[n]) : nullptr;
             P->f32[n] = mixed ? (float*)(w + L.f32[n]) : nullptr;
             P->phi_prev[n] = (double*)(w + L.phi_prev[n]);
         }

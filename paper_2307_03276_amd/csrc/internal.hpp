@@ -98,6 +98,11 @@ struct PlanMode {
     int32_t* rows;  // [nnz] sorted mode-n coordinates
     uint32_t* cofs;  // [(N-1) * nnz] the other modes' factor row offsets (coordinate x R), ascending m
     double* vals;   // [nnz]
+    // [nnz] the same nonzeros as 16-byte records {row, offset 0, offset 1 (0 for
+    // N = 2), value as FP32}: one load per staged nonzero instead of N + 1.
+    // Only for N <= 3 and when every value is exact in FP32 (counts up to
+    // 2^24); nullptr otherwise.
+    int4* pk;
     int64_t segments;
 };
 
@@ -108,6 +113,7 @@ struct PhiArgs {
     const int32_t* rows;
     const uint32_t* cofs;
     const double* vals;
+    const int4* pk;        // packed records of the same nonzeros (nullptr: read the arrays above)
     const void* fac[kMaxOther];
     const double* B;
     double* Phi;

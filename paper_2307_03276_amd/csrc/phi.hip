@@ -372,19 +372,32 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
     // Metadata of the next round is loaded into registers while the current
     // round is processed (coalesced: lane j of the group takes entries j, j+G, ...).
     Staged<NM1> pre[EPL];
+    // With packed records (up to two other modes, values exact in FP32) a
+    // staged nonzero is one 16-byte load instead of NM1 + 2: the gather path's
+    // address and data units work per lane and load instruction, and the
+    // metadata loads were a fifth of them.
+    const bool packed = NM1 <= 2 && a.pk != nullptr;
     auto load_meta = [&](int64_t base) {
 #pragma unroll
         for (int k = 0; k < EPL; ++k) {
             const int64_t p = base + k * G + lane;
             if (p < p1) {
-                pre[k].row = a.rows[p];
+                if (packed) {
+                    const int4 q = a.pk[p];
+                    pre[k].row = q.x;
+                    pre[k].c[0] = (uint32_t)q.y;
+                    if constexpr (NM1 == 2) pre[k].c[NM1 - 1] = (uint32_t)q.z;
+                    pre[k].x = (double)__int_as_float(q.w);
+                } else {
+                    pre[k].row = a.rows[p];
+#pragma unroll
+                    for (int m = 0; m < NM1; ++m) pre[k].c[m] = a.cofs[(int64_t)m * nnz + p];
+                    pre[k].x = a.vals[p];
+                }
                 // line-search pass: a row not in a line search is staged as ~row
                 // (negative), so the skip costs no load in the gather loop
                 if constexpr (LS)
                     if (a.live[pre[k].row] != 1) pre[k].row = ~pre[k].row;
-#pragma unroll
-                for (int m = 0; m < NM1; ++m) pre[k].c[m] = a.cofs[(int64_t)m * nnz + p];
-                pre[k].x = a.vals[p];
             }
         }
     };
@@ -1107,6 +1120,7 @@ PhiArgs make_args(const cpapr_plan* P, int mode, const double* B, const void* co
     a.rows = pm.rows;
     a.cofs = pm.cofs;
     a.vals = pm.vals;
+    a.pk = pm.pk;
     int j = 0;
     for (int m = 0; m < P->N; ++m)
         if (m != mode) a.fac[j++] = fac[m];
@@ -1190,12 +1204,15 @@ int resolve_chunk(int group, int requested)
 //  * a large tensor's shape: 512-nonzero tiles with lanes by rank, except
 //    17 <= R <= 32 with up to four modes: 16 lanes x 2 columns on 256-nonzero
 //    tiles in FP64, 8 lanes x 4 columns on 1024-nonzero tiles with FP32-stored
-//    factors (half the gathered words per lane);
+//    factors (half the gathered words per lane); and 5 <= R <= 16 with packed
+//    nonzero records (one load per staged nonzero): 1024-nonzero tiles, the
+//    tile's merge and row flushes weighing more against the cheaper nonzeros
+//    (-10 % at zipf3 against 512);
 //  * a tensor too small to give ~900 such tiles (3.5 per compute unit) takes
 //    tiles of the largest power of two <= nnz / 900 (at least 32): up to 128
 //    nonzeros on 16 lanes (shorter per-nonzero chains, the launch being
-//    latency-bound); at 256 or 512 lanes by rank, 16 for 9 <= R <= 16 with
-//    FP32-stored factors. Fewer tiles leave the last round of workgroups on
+//    latency-bound); at 256 or 512 lanes by rank (at 256 16 lanes for
+//    9 <= R <= 16 with FP32-stored factors). Fewer tiles leave the last round of workgroups on
 //    part of the device (measured: 780 tiles 5-13 % slower than 1560 of half
 //    the size; 980 within 2 % of the best);
 //  * the deterministic mode keeps tiles of at least 128 nonzeros;
@@ -1206,12 +1223,13 @@ namespace {
 struct ModelIn {
     int64_t nnz;
     int R, nm1;
-    bool mixed, det;
+    bool mixed, det, packed;
 };
 
 ModelIn model_in(const cpapr_plan* P)
 {
-    return {P->nnz, P->R, P->N - 1, P->params.precision == CPAPR_MIXED, P->params.deterministic != 0};
+    return {P->nnz, P->R, P->N - 1, P->params.precision == CPAPR_MIXED, P->params.deterministic != 0,
+            P->mode[0].pk != nullptr};
 }
 
 bool group16_ok(const ModelIn& m)
@@ -1232,6 +1250,8 @@ void model_shape(const ModelIn& m, int* tile, int* group)
             tb = 256;
             gb = 16;
         }
+    } else if (m.packed && m.R > 4 && m.R <= 16) {
+        tb = 1024;  // one load per staged nonzero: the tile's fixed costs weigh more
     }
     int64_t t = 32;  // the largest power of two <= nnz / 900, up to the large tensor's tile
     while (t < tb && 2 * t * 900 <= m.nnz) t *= 2;
@@ -1244,7 +1264,7 @@ void model_shape(const ModelIn& m, int* tile, int* group)
         *group = group16_ok(m) ? 16 : g0;
     } else {
         *tile = (int)t;
-        *group = m.mixed && m.R > 8 && m.R <= 16 && group16_ok(m) ? 16 : g0;
+        *group = t == 256 && m.mixed && m.R > 8 && m.R <= 16 && group16_ok(m) ? 16 : g0;
     }
 }
 }  // namespace

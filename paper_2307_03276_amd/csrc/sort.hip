@@ -62,6 +62,7 @@ __global__ __launch_bounds__(kBlock) void validate_pack_kernel(const int32_t* __
         }
         const double v = vals[k];
         if (!(v > 0.0) || !(v <= 1.7976931348623157e308)) bad |= 2;
+        if ((double)(float)v != v) bad |= 4;  // the packed records need values exact in FP32
         __builtin_memcpy(&w[RSW - 2], &v, sizeof(double));
         uint4* r = rec + k * (RSW / 4);
 #pragma unroll
@@ -225,13 +226,14 @@ __global__ __launch_bounds__(kBlock) void permute_keys_kernel(const int32_t* __r
 
 // Write the sorted copy of one mode: row, value and the other modes' factor
 // row offsets (coordinate x R), read from the records through the permutation
-// (perm == nullptr: identity).
+// (perm == nullptr: identity); with pk also the packed 16-byte records
+// {row, offset 0, offset 1 or 0, value as FP32} (N <= 3, values exact in FP32).
 template <int RSW>
 __global__ __launch_bounds__(kBlock) void gather_sorted_kernel(const uint4* __restrict__ rec, int64_t nnz, int N,
                                                                int mode, const int32_t* __restrict__ perm, int R,
                                                                int32_t* __restrict__ rows,
                                                                uint32_t* __restrict__ cofs,
-                                                               double* __restrict__ svals)
+                                                               double* __restrict__ svals, int4* __restrict__ pk)
 {
     for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * kBlock) {
         int64_t k = perm ? perm[p] : p;
@@ -250,16 +252,22 @@ __global__ __launch_bounds__(kBlock) void gather_sorted_kernel(const uint4* __re
         __builtin_memcpy(&v, &w[RSW - 2], sizeof(double));
         svals[p] = v;
         int j = 0;
+        uint32_t off[2] = {0u, 0u};
+        int32_t row = 0;
 #pragma unroll
         for (int m = 0; m < RSW - 2; ++m) {
             if (m >= N) break;
             if (m == mode) {
                 rows[p] = w[m];
+                row = w[m];
             } else {
-                cofs[(int64_t)j * nnz + p] = (uint32_t)w[m] * (uint32_t)R;
+                const uint32_t o = (uint32_t)w[m] * (uint32_t)R;
+                cofs[(int64_t)j * nnz + p] = o;
+                if (j < 2) off[j] = o;
                 ++j;
             }
         }
+        if (pk != nullptr) pk[p] = make_int4(row, (int)off[0], (int)off[1], __float_as_int((float)v));
     }
 }
 
@@ -375,6 +383,8 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
     CPAPR_HIP(hipStreamSynchronize(s));
     if (hflags & 1) return {CPAPR_EINDEX, "a coordinate lies outside its mode's range"};
     if (hflags & 2) return {CPAPR_EVALUE, "a tensor value is not finite and positive"};
+    if (hflags & 4)  // some value is not exact in FP32: the kernels read the arrays
+        for (int n = 0; n < N; ++n) P->mode[n].pk = nullptr;
 
     for (int n = 0; n < N; ++n) {
         if (only >= 0 && n != only) continue;
@@ -442,10 +452,10 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
         }
         if (rsw == 8)
             gather_sorted_kernel<8><<<grid_for(nnz), kBlock, 0, s>>>(rec, nnz, N, n, pin, P->R, pm.rows, pm.cofs,
-                                                                     pm.vals);
+                                                                     pm.vals, pm.pk);
         else
             gather_sorted_kernel<16><<<grid_for(nnz), kBlock, 0, s>>>(rec, nnz, N, n, pin, P->R, pm.rows, pm.cofs,
-                                                                      pm.vals);
+                                                                      pm.vals, pm.pk);
         CPAPR_LAUNCHED();
         const int gseg = std::min(grid_for(nnz), kSegPartials);
         count_segments_kernel<<<gseg, kBlock, 0, s>>>(pm.rows, nnz, segpart);

@@ -148,6 +148,20 @@ def test_phi_quotient_within_a_few_ulps():
     P.close()
 
 
+@pytest.mark.parametrize("dims", [(300, 200, 50), (400, 90)])
+def test_phi_values_not_exact_in_fp32(dims):
+    """Plans of up to three modes stage each nonzero from a packed 16-byte
+    record with the value in FP32, when every value is exact there (counts);
+    a value that is not (here counts + 0.1) keeps the separate arrays with the
+    FP64 value. Both against the oracle, and the packed plan against the
+    unpacked one on the same counts."""
+    X = synth.random_tensor(23, dims, 30_000, zipf=(1.2,) + (None,) * (len(dims) - 1))
+    M = synth.random_model(23, dims, 16)
+    Xf = synth.SparseTensor(X.dims, X.idx, X.vals + 0.1)
+    _phi_case(Xf, M)
+    _phi_case(X, M)
+
+
 def test_phi_atomic_variant_matches():
     X, M, _ = synth.config_small()
     _phi_case(X, M, variant=cpapr.CPAPR_VARIANT_ATOMIC)
@@ -248,21 +262,22 @@ def test_launch_policy_model_shapes():
     """Default launch shape from the launch-policy model of the tensor. A large
     tensor gets 512-nonzero tiles with lanes by rank, except 17 <= R <= 32
     (16 x 2 on 256-nonzero tiles in FP64, 8 x 4 on 1024 with FP32-stored
-    factors); a smaller one tiles of the largest power of two <= nnz/900 (at
-    least 32), on 16 lanes up to 128 nonzeros, lanes by rank at 256 and 512
-    (16 for 9 <= R <= 16 with FP32-stored factors); deterministic plans keep
-    tiles of at least 128. Explicit shapes are kept, and the model returns when
+    factors) and 5 <= R <= 16 with packed nonzero records (values exact in
+    FP32, up to three modes: 1024-nonzero tiles); a smaller one tiles of the
+    largest power of two <= nnz/900 (at least 32), on 16 lanes up to 128
+    nonzeros, lanes by rank at 256 and 512 (16 at 256 for 9 <= R <= 16 with
+    FP32-stored factors); deterministic plans keep tiles of at least 128. Explicit shapes are kept, and the model returns when
     the shape is reset. In a batch a plan on the model's shape takes the large
     tensor's shape."""
     X, M, _ = synth.config_small()  # 10,000 nonzeros, R = 10
     P = cpapr.Plan.from_tensor(X, 10)
     assert P.shape() == (16, 2)
-    assert P.batch_shape() == (8, 16) and P.tiles() == 20
+    assert P.batch_shape() == (8, 32) and P.tiles() == 10
     P.set_shape(8, 40)
     assert P.shape() == (8, 40) and P.batch_shape() == (8, 40)
     assert P.tiles() == -(-10_000 // (32 * 40))
     P.set_shape(0, 0)
-    assert P.shape() == (16, 2) and P.batch_shape() == (8, 16)
+    assert P.shape() == (16, 2) and P.batch_shape() == (8, 32)
     P.set_shape(8, 0)
     assert P.shape() == (8, 1) and P.batch_shape() == (8, 1)
     P.close()
@@ -274,9 +289,10 @@ def test_launch_policy_model_shapes():
              600_000: [(16, cpapr.CPAPR_FP64, (8, 16)), (16, cpapr.CPAPR_MIXED, (8, 16)),
                        (32, cpapr.CPAPR_FP64, (16, 16)), (32, cpapr.CPAPR_MIXED, (8, 16)),
                        (8, cpapr.CPAPR_FP64, (8, 16)), (64, cpapr.CPAPR_FP64, (16, 32))],
-             1_100_000: [(32, cpapr.CPAPR_MIXED, (8, 32)), (32, cpapr.CPAPR_FP64, (16, 16))]}
-    big = {(16, cpapr.CPAPR_FP64): (8, 16), (8, cpapr.CPAPR_MIXED): (8, 16), (16, cpapr.CPAPR_MIXED): (8, 16),
-           (32, cpapr.CPAPR_FP64): (16, 16), (32, cpapr.CPAPR_MIXED): (8, 32), (8, cpapr.CPAPR_FP64): (8, 16),
+             1_100_000: [(32, cpapr.CPAPR_MIXED, (8, 32)), (32, cpapr.CPAPR_FP64, (16, 16)),
+                         (16, cpapr.CPAPR_FP64, (8, 32))]}
+    big = {(16, cpapr.CPAPR_FP64): (8, 32), (8, cpapr.CPAPR_MIXED): (8, 32), (16, cpapr.CPAPR_MIXED): (8, 32),
+           (32, cpapr.CPAPR_FP64): (16, 16), (32, cpapr.CPAPR_MIXED): (8, 32), (8, cpapr.CPAPR_FP64): (8, 32),
            (64, cpapr.CPAPR_FP64): (16, 32)}
     for nnz, want in cases.items():
         Xn = synth.random_tensor(nnz % 97, (400, 300, 200), nnz)
@@ -285,6 +301,12 @@ def test_launch_policy_model_shapes():
             assert Pn.shape() == shape, (nnz, R, prec, Pn.shape())
             assert Pn.batch_shape() == big[(R, prec)], (nnz, R, prec, Pn.batch_shape())
             Pn.close()
+    # values not exact in FP32: no packed records, so 512-nonzero tiles
+    Xn = synth.random_tensor(7, (400, 300, 200), 1_100_000)
+    Xf = synth.SparseTensor(Xn.dims, Xn.idx, Xn.vals + 0.1)
+    Pf = cpapr.Plan.from_tensor(Xf, 16)
+    assert Pf.shape() == (8, 16) and Pf.batch_shape() == (8, 16)
+    Pf.close()
 
 
 def test_mu_inner_fixed_schedule():
