@@ -549,6 +549,72 @@ def tune_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def plan_workload(args):
+    """Plan creation against the in-row order it buys: for the zipf3 and zipf4
+    tensors (FP64) and both sort orders, the plan's creation time (host clock
+    around the call, median of 3) and Phi per mode (library-recorded kernel
+    time, median of 7 launches), and the largest difference between the two
+    orders' Phi (the order only changes rounding)."""
+    import time
+
+    import torch
+
+    from paper_2307_03276_amd import cpapr, synth
+
+    dev = torch.device("cuda")
+    cases = []
+    for name, make in (("zipf3-20M-R16", lambda: synth.config_zipf3()[:2]),
+                       ("zipf4-100M-R32", lambda: synth.config_zipf4()[:2])):
+        progress(f"generating the {name} tensor on the host")
+        X, M = make()
+        R = M.rank
+        idx = torch.from_numpy(X.idx).to(dev)
+        vals = torch.from_numpy(X.vals).to(dev)
+        A = [torch.from_numpy(a).to(dev) for a in M.factors]
+        lam = torch.from_numpy(M.lam).to(dev)
+        phis = {}
+        for sort, sname in ((cpapr.CPAPR_SORT_ROW_COL, "row_col"), (cpapr.CPAPR_SORT_ROW, "row")):
+            ts = []
+            for rep in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                P = cpapr.Plan(X.dims, idx, vals, R, sort=sort)
+                torch.cuda.synchronize()
+                ts.append(1e3 * (time.perf_counter() - t0))
+                if rep < 2:
+                    P.close()
+            per_mode, outs = [], []
+            for n in range(X.nmodes):
+                B = (A[n] * lam).contiguous()
+                out = torch.empty((X.dims[n], R), dtype=torch.float64, device=dev)
+                P.phi(n, B, A, out=out)
+                torch.cuda.synchronize()
+                cpapr.cpapr_prof_enable(7)
+                for _ in range(7):
+                    P.phi(n, B, A, out=out)
+                torch.cuda.synchronize()
+                recs = cpapr.cpapr_prof_read(7)
+                cpapr.cpapr_prof_disable()
+                per_mode.append(sorted(t for _, t in recs)[3])
+                outs.append(out.cpu())
+            phis[sname] = outs
+            cases.append({"tensor": name, "sort": sname, "plan_ms": sorted(ts)[1], "plan_ms_reps": ts,
+                          "phi_ms_per_mode": per_mode, "phi_ms_sum": sum(per_mode)})
+            progress(f"{name} {sname}: plan {sorted(ts)[1]:.2f} ms, Phi summed over modes {sum(per_mode):.4f} ms")
+            P.close()
+            torch.cuda.empty_cache()
+        cases[-1]["phi_max_rel_diff_between_orders"] = max(
+            float((a - b).abs().max() / a.abs().max()) for a, b in zip(phis["row_col"], phis["row"]))
+        del idx, vals, A, lam
+        torch.cuda.empty_cache()
+    out = {"metric": "plan creation time (ROW_COL order, zipf3)", "value": cases[0]["plan_ms"], "unit": "ms",
+           "n_gpus": 1, "steps": 3, "warmup": 0, "ms_per_step": cases[0]["plan_ms"], "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "plan creation and Phi per mode, both in-row orders, zipf3 and zipf4"},
+           "cases": cases}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -559,9 +625,10 @@ def main():
                     help="inner solver of the zipf3 / zipf4 jobs: MU (Algorithm 1), PQNR or PDNR row solves")
     ap.add_argument("--nnz", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["zipf3", "zipf4", "batch", "serve", "tune"], default="zipf3",
+    ap.add_argument("--workload", choices=["zipf3", "zipf4", "batch", "serve", "tune", "plan"], default="zipf3",
                     help="zipf3: the 20M-nonzero 3-way CP-APR MU job (default); zipf4: the 100M-nonzero 4-way "
-                         "solve to KKT 1e-4; batch: 512 uneven tensors; serve: a Poisson stream of solve requests")
+                         "solve to KKT 1e-4; batch: 512 uneven tensors; serve: a Poisson stream of solve requests; "
+                         "tune: the launch-policy model against a search; plan: plan creation and the in-row orders")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-count", type=int, default=60)
     ap.add_argument("--round-cap", type=float, default=32e6,
@@ -603,6 +670,9 @@ def main():
         return
     if args.workload == "tune":
         tune_workload(args)
+        return
+    if args.workload == "plan":
+        plan_workload(args)
         return
     if args.workload == "serve":
         if args.precision == "fp64" and "--precision" not in sys.argv:

@@ -75,8 +75,12 @@ enum { CPAPR_VARIANT_AUTO = 0, CPAPR_VARIANT_SEGMENTED = 1, CPAPR_VARIANT_ATOMIC
 
 /* Order of the nonzeros inside a row of the mode-n sorted copy (Phi's sum over
  * a row is order-free). ROW: input order (a stable sort by i_n). ROW_COL: by
- * the coordinate of the largest other mode, so long rows sweep that factor in
- * order. */
+ * the coordinate of the largest other mode (the first such mode on ties), so
+ * long rows sweep that factor in order: a stable sort by the 32-bit key
+ * (i_n << k) | (j >> d), where j is that coordinate, b_n and b_j the bit widths
+ * of the two modes' sizes (ceil(log2 I)), k = min(b_j, 32 - b_n) and
+ * d = b_j - k; when b_n + b_j > 32, runs of 2^d consecutive values of j keep
+ * input order. */
 enum { CPAPR_SORT_ROW = 0, CPAPR_SORT_ROW_COL = 1 };
 
 /* Inner solver of each mode. MU: the multiplicative update of Algorithm 1.

@@ -7,12 +7,16 @@
 // each mode instead gets a physically permuted structure-of-arrays copy, so the
 // Phi kernel streams coordinates and values in order.
 //
-// Sort: stable least-significant-digit radix sort of (i_n, k) pairs with
-// 8-bit digits, one pass per digit of ceil(log2 I_n) bits. Each pass is
-// (1) per-tile digit histograms, (2) an exclusive scan of the digit-major
-// histogram table, (3) a stable scatter that ranks equal digits inside a wave
-// with ballots and across the workgroup's waves through LDS. Stability keeps
-// nonzeros of a row in input order, so plans and Phi are deterministic.
+// Sort: stable least-significant-digit radix sort of (key, k) pairs with 8-bit
+// digits, one pass per digit of the key's width. The key is i_n, or (in the
+// ROW_COL order) i_n followed by the high bits of the largest other mode's
+// coordinate in one 32-bit word. Each pass is (1) per-tile digit histograms,
+// (2) each (tile, digit)'s output offset, scanned over digits and tiles, (3) a stable
+// scatter: a tile is ranked in registers (equal digits matched inside a wave
+// with ballots, running counts per wave in LDS), reordered by digit in LDS and
+// written out in digit runs, so consecutive lanes store to consecutive
+// addresses. Stability keeps nonzeros of equal keys in input order, so plans
+// and Phi are deterministic.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -24,7 +28,7 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortRounds = 16;                // items per thread per tile
 constexpr int kSortTile = kBlock * kSortRounds;  // 4096 keys per tile
-constexpr int kScanChunk = 4096;                 // elements per block in the scan
+constexpr int kScanTiles = 32;                   // tiles per workgroup in the offsets scan
 constexpr int kSegPartials = 1024;               // blocks of the segment count
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -71,157 +75,219 @@ __global__ __launch_bounds__(kBlock) void validate_pack_kernel(const int32_t* __
     if (bad) atomicOr(flags, bad);
 }
 
-// Digit histogram of one 4096-key tile, written digit-major: counts[d * ntiles + tile].
-__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const int32_t* __restrict__ keys, int64_t n,
-                                                            int shift, int* __restrict__ counts, int ntiles)
+// Mask of the lanes of this wave whose digit equals this lane's (8 ballots);
+// lanes with valid == false match nothing.
+__device__ __forceinline__ unsigned long long digit_peers(int d, bool valid)
+{
+    unsigned long long m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const unsigned long long ones = __ballot((d >> b) & 1);
+        m &= ((d >> b) & 1) ? ones : ~ones;
+    }
+    return m;
+}
+
+__device__ __forceinline__ unsigned long long lanes_below()
+{
+    const int lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Digit histogram of one 4096-key tile, written tile-major: counts[tile * 256 + d].
+// One LDS add per distinct digit of a wave (its lowest lane adds the group's size),
+// so skewed digits do not serialise on one LDS address.
+__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
+                                                            int shift, int* __restrict__ counts)
 {
     __shared__ int h[kRadix];
     const int t = threadIdx.x;
+    const unsigned long long below = lanes_below();
     h[t] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    uint32_t key[kSortRounds];
+#pragma unroll
     for (int q = 0; q < kSortRounds; ++q) {
-        int64_t e = base + q * kBlock + t;
-        if (e < n) atomicAdd(&h[(keys[e] >> shift) & (kRadix - 1)], 1);
+        const int64_t e = base + q * kBlock + t;
+        key[q] = e < n ? keys[e] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kSortRounds; ++q) {
+        const bool valid = base + q * kBlock + t < n;
+        const int d = (int)((key[q] >> shift) & (kRadix - 1));
+        const unsigned long long match = digit_peers(d, valid);
+        if (valid && (match & below) == 0) atomicAdd(&h[d], __popcll(match));
     }
     __syncthreads();
-    counts[(int64_t)t * ntiles + blockIdx.x] = h[t];
+    counts[(int64_t)blockIdx.x * kRadix + t] = h[t];
 }
 
-// Block-wide exclusive scan of one value per thread; returns the block total.
-__device__ int block_exclusive_scan(int v, int* tmp, int& total)
+// Output offsets of a pass: offset(tile, d) = (keys with a smaller digit) +
+// (keys with digit d in earlier tiles), in place over the tile-major table, in
+// three steps with one thread per digit (every access coalesced across digits):
+// per-group column sums over kScanTiles tiles, a walk down the groups, and the
+// scan inside each group.
+__global__ __launch_bounds__(kBlock) void offsets_sum_kernel(const int* __restrict__ counts, int ntiles,
+                                                             int* __restrict__ part)
 {
-    const int t = threadIdx.x;
-    tmp[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        int add = t >= off ? tmp[t - off] : 0;
-        __syncthreads();
-        tmp[t] += add;
-        __syncthreads();
-    }
-    int incl = tmp[t];
-    total = tmp[kBlock - 1];
-    __syncthreads();
-    return incl - v;
-}
-
-// Scan phase 1: sums of kScanChunk-element chunks.
-__global__ __launch_bounds__(kBlock) void scan_reduce_kernel(const int* __restrict__ a, int64_t n,
-                                                             int* __restrict__ sums)
-{
-    __shared__ int red[kBlock];
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    const int t0 = blockIdx.x * kScanTiles;
+    const int t1 = min(t0 + kScanTiles, ntiles);
     int s = 0;
-    for (int q = threadIdx.x; q < kScanChunk; q += kBlock)
-        if (base + q < n) s += a[base + q];
-    red[threadIdx.x] = s;
+    for (int tile = t0; tile < t1; ++tile) s += counts[(int64_t)tile * kRadix + threadIdx.x];
+    part[(int64_t)blockIdx.x * kRadix + threadIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void offsets_groups_kernel(int* __restrict__ part, int ngroups)
+{
+    static_assert(kRadix == kBlock, "one digit per thread");
+    __shared__ int wsum[kBlock / 64];
+    const int d = threadIdx.x;
+    const int lane = d & 63;
+    int run = 0;
+#pragma unroll 8
+    for (int g = 0; g < ngroups; ++g) {
+        const int v = part[(int64_t)g * kRadix + d];
+        part[(int64_t)g * kRadix + d] = run;
+        run += v;
+    }
+    // exclusive scan of the digit totals
+    int incl = run;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
+    }
+    if (lane == 63) wsum[d >> 6] = incl;
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+    int base = incl - run;
+    for (int w = 0; w < (d >> 6); ++w) base += wsum[w];
+#pragma unroll 8
+    for (int g = 0; g < ngroups; ++g) part[(int64_t)g * kRadix + d] += base;
 }
 
-// Scan phase 2: exclusive scan of the chunk sums by one workgroup.
-__global__ __launch_bounds__(kBlock) void scan_sums_kernel(int* sums, int nsums)
+__global__ __launch_bounds__(kBlock) void offsets_tiles_kernel(int* __restrict__ counts, int ntiles,
+                                                               const int* __restrict__ part)
 {
-    __shared__ int tmp[kBlock];
-    int carry = 0;
-    for (int base = 0; base < nsums; base += kBlock) {
-        int i = base + threadIdx.x;
-        int v = i < nsums ? sums[i] : 0;
-        int total;
-        int ex = block_exclusive_scan(v, tmp, total);
-        if (i < nsums) sums[i] = carry + ex;
-        carry += total;
+    const int t0 = blockIdx.x * kScanTiles;
+    const int t1 = min(t0 + kScanTiles, ntiles);
+    int run = part[(int64_t)blockIdx.x * kRadix + threadIdx.x];
+    for (int tile = t0; tile < t1; ++tile) {
+        const int64_t i = (int64_t)tile * kRadix + threadIdx.x;
+        const int v = counts[i];
+        counts[i] = run;
+        run += v;
     }
 }
 
-// Scan phase 3: exclusive scan inside each chunk, offset by the chunk's prefix.
-__global__ __launch_bounds__(kBlock) void scan_chunks_kernel(int* a, int64_t n, const int* __restrict__ sums)
-{
-    __shared__ int tmp[kBlock];
-    constexpr int per = kScanChunk / kBlock;  // consecutive elements per thread
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * per;
-    int loc[per];
-    int s = 0;
-    for (int q = 0; q < per; ++q) {
-        loc[q] = base + q < n ? a[base + q] : 0;
-        s += loc[q];
-    }
-    int total;
-    int ex = block_exclusive_scan(s, tmp, total) + sums[blockIdx.x];
-    for (int q = 0; q < per; ++q) {
-        if (base + q < n) a[base + q] = ex;
-        ex += loc[q];
-    }
-}
-
-// Stable scatter of one tile. Items are visited in rounds of 256 consecutive
-// keys (round-major, thread-minor = input order). Within a round, lanes of a
-// wave with equal digits are matched by 8 ballots; a lane's rank is the number
-// of matching lower lanes plus the counts of earlier waves, plus the digit's
-// running offset from earlier rounds and from earlier tiles (the scan).
-__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const int32_t* __restrict__ keys_in,
+// Stable scatter of one tile. Wave w ranks the tile's w-th quarter in rounds
+// of 64 consecutive keys: a key's rank among equal digits is its matching lower
+// lanes plus the wave's running count of that digit (LDS). The per-wave counts
+// then give each key its position in the tile ordered by (digit, input order);
+// the tile is rearranged in LDS and written out in that order, the digit's
+// global offset (from the scan) minus the digit's start in the tile added to
+// the LDS position.
+__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* __restrict__ keys_in,
                                                                const int32_t* __restrict__ pay_in,
-                                                               int32_t* __restrict__ keys_out,
+                                                               uint32_t* __restrict__ keys_out,
                                                                int32_t* __restrict__ pay_out, int64_t n,
-                                                               int shift, const int* __restrict__ offsets,
-                                                               int ntiles)
+                                                               int shift, const int* __restrict__ offsets)
 {
     constexpr int kWaves = kBlock / 64;
-    __shared__ int run[kRadix];
-    __shared__ int wcnt[kWaves][kRadix];
+    constexpr int kRounds = kSortTile / kBlock;  // rounds of 64 keys per wave
+    static_assert(kRadix == kBlock, "one digit per thread in the per-digit steps");
+    __shared__ int wrun[kWaves][kRadix];  // per-wave digit counts, then their exclusive prefix over waves
+    __shared__ int dstart[kRadix];        // digit start in the tile's sorted order
+    __shared__ int64_t gshift[kRadix];    // global position - tile position, per digit
+    __shared__ int wsum[kWaves];
+    __shared__ uint32_t skey[kSortTile];
+    __shared__ int32_t spay[kSortTile];
     const int t = threadIdx.x;
     const int wave = t >> 6;
     const int lane = t & 63;
-    run[t] = offsets[(int64_t)t * ntiles + blockIdx.x];
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int q = 0; q < kSortRounds; ++q) {
-        const int64_t e = base + q * kBlock + t;
-        const bool valid = e < n;
-        int32_t key = valid ? keys_in[e] : 0;
-        int32_t pay = valid ? (pay_in ? pay_in[e] : (int32_t)e) : 0;
-        const int d = (key >> shift) & (kRadix - 1);
-        for (int w = 0; w < kWaves; ++w) wcnt[w][t] = 0;
-        __syncthreads();
-        unsigned long long match = __ballot(valid);
-        for (int b = 0; b < kRadixBits; ++b) {
-            unsigned long long ones = __ballot((d >> b) & 1);
-            match &= ((d >> b) & 1) ? ones : ~ones;
-        }
-        const int rank = __popcll(match & below);
-        if (valid && rank == 0) wcnt[wave][d] = __popcll(match);
-        __syncthreads();
-        if (valid) {
-            int64_t pos = (int64_t)run[d] + rank;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            if (pos >= 0 && pos < n) {  // always true when the histogram scan is consistent
-                keys_out[pos] = key;
-                pay_out[pos] = pay;
+    const unsigned long long below = lanes_below();
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wrun[w][t] = 0;
+    const int64_t tbase = (int64_t)blockIdx.x * kSortTile;
+    const int64_t wbase = tbase + (int64_t)wave * (kSortTile / kWaves);
+    uint32_t key[kRounds];
+    int32_t pay[kRounds];
+    int rk[kRounds];
+#pragma unroll
+    for (int q = 0; q < kRounds; ++q) {
+        const int64_t e = wbase + q * 64 + lane;
+        key[q] = e < n ? keys_in[e] : 0u;
+        pay[q] = e < n ? (pay_in ? pay_in[e] : (int32_t)e) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kRounds; ++q) {
+        const bool valid = wbase + q * 64 + lane < n;
+        const int d = (int)((key[q] >> shift) & (kRadix - 1));
+        const unsigned long long match = digit_peers(d, valid);
+        const int prev = wrun[wave][d];
+        rk[q] = prev + __popcll(match & below);
+        // every lane has read its digit's count before the group's lowest lane adds to it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (valid && (match & below) == 0) wrun[wave][d] = prev + __popcll(match);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __syncthreads();
+    // thread t = digit t: prefix over waves, then the digit's start in the tile
+    int tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const int c = wrun[w][t];
+        wrun[w][t] = tot;
+        tot += c;
+    }
+    int incl = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int start = incl - tot;
+    for (int w = 0; w < wave; ++w) start += wsum[w];
+    dstart[t] = start;
+    gshift[t] = (int64_t)offsets[(int64_t)blockIdx.x * kRadix + t] - start;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kRounds; ++q) {
+        if (wbase + q * 64 + lane < n) {
+            const int d = (int)((key[q] >> shift) & (kRadix - 1));
+            const int j = dstart[d] + wrun[wave][d] + rk[q];
+            if ((unsigned)j < (unsigned)kSortTile) {  // always true: the counts are this tile's own
+                skey[j] = key[q];
+                spay[j] = pay[q];
             }
         }
-        __syncthreads();
-        int add = 0;
-        for (int w = 0; w < kWaves; ++w) add += wcnt[w][t];
-        run[t] += add;
-        __syncthreads();
+    }
+    __syncthreads();
+    const int cnt = (int)min((int64_t)kSortTile, n - tbase);
+    for (int j = t; j < cnt; j += kBlock) {
+        const uint32_t k = skey[j];
+        const int64_t pos = gshift[(k >> shift) & (kRadix - 1)] + j;
+        if (pos >= 0 && pos < n) {  // always true when the histogram scan is consistent
+            keys_out[pos] = k;
+            pay_out[pos] = spay[j];
+        }
     }
 }
 
-// keys_out[p] = keys[perm[p]]: a key array in the order of an earlier sort.
-__global__ __launch_bounds__(kBlock) void permute_keys_kernel(const int32_t* __restrict__ keys,
-                                                              const int32_t* __restrict__ perm, int64_t nnz,
-                                                              int32_t* __restrict__ keys_out)
+// Sort keys of the ROW_COL order: i_n in the high bits, the secondary
+// coordinate without its `drop` low bits below it (lo_bits = its kept width).
+__global__ __launch_bounds__(kBlock) void composite_keys_kernel(const int32_t* __restrict__ hi,
+                                                                const int32_t* __restrict__ lo, int64_t nnz,
+                                                                int lo_bits, int drop, uint32_t* __restrict__ keys)
 {
-    for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * kBlock) {
-        int64_t k = perm[p];
-        if (k < 0 || k >= nnz) k = p;  // a permutation never leaves [0, nnz); keeps reads in bounds
-        keys_out[p] = keys[k];
-    }
+    for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * kBlock)
+        keys[p] = ((uint32_t)hi[p] << lo_bits) | ((uint32_t)lo[p] >> drop);
 }
 
 // Write the sorted copy of one mode: row, value and the other modes' factor
@@ -313,14 +379,14 @@ int grid_for(int64_t n)
     return (int)g;
 }
 
-Error exclusive_scan(int* a, int64_t n, int* sums, hipStream_t s)
+Error pass_offsets(int* counts, int ntiles, int* part, hipStream_t s)
 {
-    const int nchunks = (int)cdiv(n, kScanChunk);
-    scan_reduce_kernel<<<nchunks, kBlock, 0, s>>>(a, n, sums);
+    const int ngroups = (int)cdiv(ntiles, kScanTiles);
+    offsets_sum_kernel<<<ngroups, kBlock, 0, s>>>(counts, ntiles, part);
     CPAPR_LAUNCHED();
-    scan_sums_kernel<<<1, kBlock, 0, s>>>(sums, nchunks);
+    offsets_groups_kernel<<<1, kBlock, 0, s>>>(part, ngroups);
     CPAPR_LAUNCHED();
-    scan_chunks_kernel<<<nchunks, kBlock, 0, s>>>(a, n, sums);
+    offsets_tiles_kernel<<<ngroups, kBlock, 0, s>>>(counts, ntiles, part);
     CPAPR_LAUNCHED();
     return {CPAPR_OK, ""};
 }
@@ -333,9 +399,9 @@ int64_t sort_scratch_bytes(int64_t nnz, int N)
     const int64_t ncounts = ntiles * kRadix;
     size_t b = 0;
     b += align256((size_t)nnz * 4 * record_words(N));       // nonzero records
-    b += 5 * align256((size_t)nnz * 4);                     // keys/payload ping-pong, secondary order
+    b += 4 * align256((size_t)nnz * 4);                     // keys/payload ping-pong
     b += align256((size_t)ncounts * 4);                     // histogram table
-    b += align256((size_t)cdiv(ncounts, kScanChunk) * 4 + 4);  // scan chunk sums
+    b += align256((size_t)cdiv(ntiles, kScanTiles) * kRadix * 4);  // offsets scan: group sums
     b += 256;                                                // flags / counters
     b += align256(kSegPartials * 8);                         // segment-count partials
     return (int64_t)b;
@@ -355,14 +421,12 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
     };
     const int rsw = record_words(N);
     uint4* rec = (uint4*)take((size_t)nnz * 4 * rsw);
-    int32_t* ka = (int32_t*)take((size_t)nnz * 4);
-    int32_t* kb = (int32_t*)take((size_t)nnz * 4);
+    uint32_t* ka = (uint32_t*)take((size_t)nnz * 4);
+    uint32_t* kb = (uint32_t*)take((size_t)nnz * 4);
     int32_t* pa = (int32_t*)take((size_t)nnz * 4);
     int32_t* pb = (int32_t*)take((size_t)nnz * 4);
-    int32_t* secperm = (int32_t*)take((size_t)nnz * 4);  // order by the secondary key, kept for reuse
-    int sec_cached = -1;
     int* counts = (int*)take((size_t)ncounts * 4);
-    int* sums = (int*)take((size_t)cdiv(ncounts, kScanChunk) * 4 + 4);
+    int* part = (int*)take((size_t)cdiv(ntiles, kScanTiles) * kRadix * 4);
     int* flags = (int*)take(256);
     unsigned long long* segc = (unsigned long long*)(flags + 8);
     unsigned long long* segpart = (unsigned long long*)take(kSegPartials * 8);
@@ -395,60 +459,45 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
         }
         // LSD passes over the low `bits` bits of the keys in (kin, pin); outputs
         // alternate between (ka, kb) and (pa, pb), never aliasing the inputs.
-        const int32_t* kin = nullptr;
+        const uint32_t* kin = (const uint32_t*)(X->idx + (int64_t)n * nnz);  // validated: >= 0
         const int32_t* pin = nullptr;  // nullptr: identity payload
-        auto passes = [&](int64_t dim) -> Error {
+        auto width = [](int64_t dim) {
             int bits = 0;
             while (bits < 31 && ((int64_t)1 << bits) < dim) ++bits;
-            for (int ps = 0; ps < (bits + kRadixBits - 1) / kRadixBits; ++ps) {
-                const int shift = ps * kRadixBits;
-                int32_t* kout = (kin == ka) ? kb : ka;
-                int32_t* pout = (pin == pa) ? pb : pa;
-                radix_hist_kernel<<<(int)ntiles, kBlock, 0, s>>>(kin, nnz, shift, counts, (int)ntiles);
-                CPAPR_LAUNCHED();
-                Error e = exclusive_scan(counts, ncounts, sums, s);
-                if (e.code) return e;
-                radix_scatter_kernel<<<(int)ntiles, kBlock, 0, s>>>(kin, pin, kout, pout, nnz, shift, counts,
-                                                                    (int)ntiles);
-                CPAPR_LAUNCHED();
-                kin = kout;
-                pin = pout;
-            }
-            return {CPAPR_OK, ""};
+            return bits;
         };
-        // Secondary key first (stable LSD order): within each row of mode n the
-        // nonzeros then follow the largest other mode's coordinate, so that
-        // mode's factor rows are swept in order inside long rows.
+        int bits = width(P->dims[n]);
+        // ROW_COL: within each row of mode n the nonzeros follow the largest
+        // other mode's coordinate, so that mode's factor rows are swept in order
+        // inside long rows. Both go into one 32-bit key; when i_n and that
+        // coordinate need more bits, the coordinate's low bits are dropped
+        // (runs of 2^drop consecutive coordinates keep input order).
         int sec = -1;
         if (P->params.sort == CPAPR_SORT_ROW_COL)
             for (int m = 0; m < N; ++m)
                 if (m != n && (sec < 0 || P->dims[m] > P->dims[sec])) sec = m;
-        if (sec >= 0 && sec == sec_cached) {
-            pin = secperm;  // the same secondary order as the previous mode's: reuse it
-        } else if (sec >= 0) {
-            kin = X->idx + (int64_t)sec * nnz;
-            Error e = passes(P->dims[sec]);
-            if (e.code) return e;
-            if (pin != nullptr) {
-                CPAPR_HIP(hipMemcpyAsync(secperm, pin, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s));
-                sec_cached = sec;
-            }
-        }
         if (sec >= 0) {
-            if (pin != nullptr) {  // keys of mode n in the secondary order
-                int32_t* kout = (kin == ka) ? kb : ka;
-                permute_keys_kernel<<<grid_for(nnz), kBlock, 0, s>>>(X->idx + (int64_t)n * nnz, pin, nnz, kout);
-                CPAPR_LAUNCHED();
-                kin = kout;
-            } else {
-                kin = X->idx + (int64_t)n * nnz;
-            }
-        } else {
-            kin = X->idx + (int64_t)n * nnz;
+            const int sbits = width(P->dims[sec]);
+            const int keep = std::min(sbits, 32 - bits);
+            composite_keys_kernel<<<grid_for(nnz), kBlock, 0, s>>>(X->idx + (int64_t)n * nnz,
+                                                                   X->idx + (int64_t)sec * nnz, nnz, keep,
+                                                                   sbits - keep, ka);
+            CPAPR_LAUNCHED();
+            kin = ka;
+            bits += keep;
         }
-        {
-            Error e = passes(P->dims[n]);
+        for (int ps = 0; ps < (bits + kRadixBits - 1) / kRadixBits; ++ps) {
+            const int shift = ps * kRadixBits;
+            uint32_t* kout = (kin == ka) ? kb : ka;
+            int32_t* pout = (pin == pa) ? pb : pa;
+            radix_hist_kernel<<<(int)ntiles, kBlock, 0, s>>>(kin, nnz, shift, counts);
+            CPAPR_LAUNCHED();
+            Error e = pass_offsets(counts, (int)ntiles, part, s);
             if (e.code) return e;
+            radix_scatter_kernel<<<(int)ntiles, kBlock, 0, s>>>(kin, pin, kout, pout, nnz, shift, counts);
+            CPAPR_LAUNCHED();
+            kin = kout;
+            pin = pout;
         }
         if (rsw == 8)
             gather_sorted_kernel<8><<<grid_for(nnz), kBlock, 0, s>>>(rec, nnz, N, n, pin, P->R, pm.rows, pm.cofs,

@@ -80,6 +80,51 @@ def test_phi_sort_modes(sort, dims):
     _phi_case(X, M, sort=sort)
 
 
+def _key_width(dim):
+    b = 0
+    while b < 31 and (1 << b) < dim:
+        b += 1
+    return b
+
+
+def _expected_order(X, n, sort):
+    """Stable order by i_n, or (ROW_COL) by i_n then the largest other mode's
+    coordinate, both in one 32-bit key: the coordinate keeps its high bits."""
+    key = X.idx[n].astype(np.uint64)
+    if sort == cpapr.CPAPR_SORT_ROW_COL:
+        sec = max((m for m in range(X.nmodes) if m != n), key=lambda m: X.dims[m])
+        bits, sbits = _key_width(X.dims[n]), _key_width(X.dims[sec])
+        keep = min(sbits, 32 - bits)
+        key = (key << np.uint64(keep)) | (X.idx[sec].astype(np.uint64) >> np.uint64(sbits - keep))
+    return np.argsort(key, kind="stable")
+
+
+@pytest.mark.parametrize("sort", [0, 1])
+@pytest.mark.parametrize("dims", [(3000, 2000, 100), ((1 << 17) + 1, (1 << 16) + 1, 300),
+                                  (40, 1 << 20, 30, 1 << 14)])
+def test_plan_order_is_the_stable_key_order(sort, dims):
+    """A plan orders each mode's nonzeros exactly as the stable sort by its key:
+    a plan of the tensor given already in that order (which a stable sort leaves
+    as it is) has the same tiles and summation order, so deterministic Phi
+    agrees bit for bit; any other order of a row's nonzeros changes its sums'
+    rounding. Two of the shapes need more than 32 key bits in ROW_COL, so the
+    secondary coordinate loses low bits there."""
+    X = synth.random_tensor(21, dims, 200_000, zipf=(1.1,) * len(dims))
+    M = synth.random_model(21, dims, 16)
+    A = [dev(a) for a in M.factors]
+    P = cpapr.Plan.from_tensor(X, 16, deterministic=1, sort=sort)
+    for n in range(X.nmodes):
+        o = _expected_order(X, n, sort)
+        Xs = synth.SparseTensor(X.dims, np.ascontiguousarray(X.idx[:, o]), X.vals[o].copy())
+        Q = cpapr.Plan.from_tensor(Xs, 16, deterministic=1, sort=sort)
+        assert P.shape() == Q.shape() and P.segments(n) == Q.segments(n)
+        B = dev(M.factors[n] * M.lam)
+        a, b = host(P.phi(n, B, A)), host(Q.phi(n, B, A))
+        assert np.array_equal(a, b), f"mode {n}: the plan's order is not the stable key order"
+        Q.close()
+    P.close()
+
+
 def test_phi_one_row_spans_everything():
     """Every nonzero in one row of mode 0: the row crosses every tile boundary."""
     rng = np.random.default_rng(5)
@@ -148,18 +193,30 @@ def test_phi_quotient_within_a_few_ulps():
     P.close()
 
 
-@pytest.mark.parametrize("dims", [(300, 200, 50), (400, 90)])
+@pytest.mark.parametrize("dims", [(300, 200, 50), (400, 90), (60, 50, 40, 30)])
 def test_phi_values_not_exact_in_fp32(dims):
     """Plans of up to three modes stage each nonzero from a packed 16-byte
     record with the value in FP32, when every value is exact there (counts);
     a value that is not (here counts + 0.1) keeps the separate arrays with the
-    FP64 value. Both against the oracle, and the packed plan against the
-    unpacked one on the same counts."""
+    FP64 value; four-mode plans always read the arrays. All against the
+    oracle."""
     X = synth.random_tensor(23, dims, 30_000, zipf=(1.2,) + (None,) * (len(dims) - 1))
     M = synth.random_model(23, dims, 16)
     Xf = synth.SparseTensor(X.dims, X.idx, X.vals + 0.1)
     _phi_case(Xf, M)
     _phi_case(X, M)
+
+
+@pytest.mark.parametrize("group,R", [(4, 8), (8, 16), (16, 32), (32, 64), (64, 100)])
+@pytest.mark.parametrize("precision", [cpapr.CPAPR_FP64, cpapr.CPAPR_MIXED])
+def test_phi_four_way_packed_shapes(group, R, precision):
+    """Four-way plans at lane-group shapes from 4 to 64 lanes, both
+    precisions, non-integer values, several tiles and a ragged tail."""
+    X = synth.random_tensor(31 + R, (700, 300, 90, 20), 50_003, zipf=(1.2, 1.1, None, None))
+    X = synth.SparseTensor(X.dims, X.idx, X.vals * 0.75 + 0.01)
+    M = synth.random_model(31, X.dims, R)
+    _phi_case(X, M, tol=TOL64 if precision == cpapr.CPAPR_FP64 else TOLMIX, precision=precision,
+              group=group, chunk=0)
 
 
 def test_phi_atomic_variant_matches():
