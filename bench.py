@@ -43,6 +43,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROF_EVERY = 7  # Phi launches per timed one in the job benchmarks
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phi_traffic.json")
 
 
@@ -740,14 +741,18 @@ def main():
     torch.cuda.synchronize()
     progress(f"{args.steps} timed steps")
     launches_per_step = sched["kmax"] * N * sched["lmax"]
-    cpapr.cpapr_prof_enable(launches_per_step * args.steps + 16)
+    # Every 7th Phi launch of the timed steps is bracketed by HIP events (7 is
+    # coprime to the 10 inner iterations and 3 modes, so every mode and inner
+    # position is sampled); an event pair holds the stream for about 5 us on
+    # either side of its kernel, so timing all launches would cost the job 3 %.
+    cpapr.cpapr_prof_enable_sampled(launches_per_step * args.steps // PROF_EVERY + 16, PROF_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         st, segs = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    recs = cpapr.cpapr_prof_read(launches_per_step * args.steps + 16)
+    recs = cpapr.cpapr_prof_read(launches_per_step * args.steps // PROF_EVERY + 16)
     cpapr.cpapr_prof_disable()
 
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
@@ -798,7 +803,9 @@ def main():
                        "issued_bytes_per_launch": issued / max(1, len(recs)),
                        "issued_GBs": issued / (tot_ms / 1000.0) / 1e9,
                        "measured_bytes_per_launch": traffic_bytes,
-                       "segments": segs, "share_of_step": tot_ms / (ms_per_step * args.steps)},
+                       "segments": segs, "sampled_every": PROF_EVERY,
+                       # the sampled launches stand for PROF_EVERY launches each
+                       "share_of_step": PROF_EVERY * tot_ms / (ms_per_step * args.steps)},
         "solve": {"method": args.method, "outer": st["outer_iters"], "inner_updates": st["inner_iters"],
                   "phi_evals": st["phi_evals"], "trial_evals": st["trial_evals"], "row_steps": st["row_steps"],
                   "converged": bool(st["converged"]), "kkt": st["kkt_violation"], "loglik": st["loglik"]},

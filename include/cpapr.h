@@ -438,10 +438,15 @@ int cpapr_plan_sync_f32(cpapr_plan* plan, const double* const* A, void* stream);
 
 /* Kernel timing for measurement: while enabled, every Phi kernel launch is
  * bracketed by HIP events on its stream (up to `capacity` launches).
- * cpapr_prof_read waits for the recorded events and writes, per launch, the
- * mode and the kernel's duration in milliseconds; returns the number of
- * launches written (<= cap) or a negative error. Not thread-safe. */
+ * cpapr_prof_enable_sampled brackets only every `every`-th launch after the
+ * call (the 1st, the every+1-th, ...): each event pair holds the stream for a
+ * few microseconds on either side of its kernel, so sampling keeps the timed
+ * work close to an unobserved run. cpapr_prof_read waits for the recorded
+ * events and writes, per recorded launch, the mode and the kernel's duration
+ * in milliseconds; returns the number of launches written (<= cap) or a
+ * negative error. Not thread-safe. */
 int cpapr_prof_enable(int32_t capacity);
+int cpapr_prof_enable_sampled(int32_t capacity, int32_t every);
 int cpapr_prof_disable(void);
 int cpapr_prof_read(int32_t* modes, float* ms, int32_t cap);
 

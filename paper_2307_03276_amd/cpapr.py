@@ -118,6 +118,7 @@ def load():
         "cpapr_batch_commit": (C.c_int, [vp, vp]),
         "cpapr_batch_run": (C.c_int, [vp, i32, vp]),
         "cpapr_prof_enable": (C.c_int, [i32]),
+        "cpapr_prof_enable_sampled": (C.c_int, [i32, i32]),
         "cpapr_prof_disable": (C.c_int, []),
         "cpapr_prof_read": (C.c_int, [P(i32), P(C.c_float), i32]),
         "cpapr_last_error": (C.c_char_p, []),
@@ -138,7 +139,8 @@ EXPORTED = ("cpapr_params_default", "cpapr_plan_workspace_size", "cpapr_plan_cre
             "cpapr_mttkrp", "cpapr_batch_workspace_size", "cpapr_batch_tiles", "cpapr_batch_create", "cpapr_batch_create2",
             "cpapr_batch_destroy", "cpapr_batch_set", "cpapr_batch_clear", "cpapr_batch_commit", "cpapr_batch_run",
             "cpapr_batch_mu", "cpapr_batch_inner", "cpapr_batch_hold", "cpapr_batch_status", "cpapr_mode_begin", "cpapr_mode_end", "cpapr_modes_advance", "cpapr_plan_sync_f32",
-            "cpapr_prof_enable", "cpapr_prof_disable", "cpapr_prof_read", "cpapr_last_error")
+            "cpapr_prof_enable", "cpapr_prof_enable_sampled", "cpapr_prof_disable", "cpapr_prof_read",
+            "cpapr_last_error")
 
 
 def _check(rc: int):
@@ -471,6 +473,10 @@ class Batch:
 
 def cpapr_prof_enable(capacity: int):
     return _check(load().cpapr_prof_enable(capacity))
+
+
+def cpapr_prof_enable_sampled(capacity: int, every: int):
+    return _check(load().cpapr_prof_enable_sampled(capacity, every))
 
 
 def cpapr_prof_disable():

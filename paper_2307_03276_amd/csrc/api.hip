@@ -33,6 +33,8 @@ struct Prof {
     bool on = false;
     int cap = 0;
     int count = 0;
+    int every = 1;      // record every `every`-th launch
+    int64_t seen = 0;   // launches since enable
     bool open = false;
     std::vector<hipEvent_t> start, stop;
     std::vector<int> mode;
@@ -246,7 +248,8 @@ void set_last_error(const std::string& msg) { g_error = msg; }
 
 void prof_begin(int mode, hipStream_t s)
 {
-    if (!g_prof.on || g_prof.count >= g_prof.cap) return;
+    if (!g_prof.on) return;
+    if (g_prof.seen++ % g_prof.every != 0 || g_prof.count >= g_prof.cap) return;
     if (hipEventRecord(g_prof.start[g_prof.count], s) == hipSuccess) {
         g_prof.mode[g_prof.count] = mode;
         g_prof.open = true;
@@ -835,9 +838,12 @@ int cpapr_mttkrp(cpapr_plan* plan, int32_t mode, const double* const* A, double*
     }
 }
 
-int cpapr_prof_enable(int32_t capacity)
+int cpapr_prof_enable(int32_t capacity) { return cpapr_prof_enable_sampled(capacity, 1); }
+
+int cpapr_prof_enable_sampled(int32_t capacity, int32_t every)
 {
     if (capacity < 1 || capacity > (1 << 20)) return fail(CPAPR_EINVAL, "capacity must be in [1, 2^20]");
+    if (every < 1) return fail(CPAPR_EINVAL, "every must be >= 1");
     cpapr_prof_disable();
     g_prof.start.resize(capacity);
     g_prof.stop.resize(capacity);
@@ -851,6 +857,8 @@ int cpapr_prof_enable(int32_t capacity)
     }
     g_prof.cap = capacity;
     g_prof.count = 0;
+    g_prof.every = every;
+    g_prof.seen = 0;
     g_prof.open = false;
     g_prof.on = true;
     return CPAPR_OK;

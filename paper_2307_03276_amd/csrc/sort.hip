@@ -28,7 +28,7 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortRounds = 16;                // items per thread per tile
 constexpr int kSortTile = kBlock * kSortRounds;  // 4096 keys per tile
-constexpr int kScanTiles = 32;                   // tiles per workgroup in the offsets scan
+constexpr int kScanTiles = 64;                   // tiles per workgroup in the offsets scan
 constexpr int kSegPartials = 1024;               // blocks of the segment count
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -95,16 +95,14 @@ __device__ __forceinline__ unsigned long long lanes_below()
 }
 
 // Digit histogram of one 4096-key tile, written tile-major: counts[tile * 256 + d].
-// One LDS add per distinct digit of a wave (its lowest lane adds the group's size),
-// so skewed digits do not serialise on one LDS address.
+// The tile's keys are loaded first (all loads in flight), then counted with
+// one LDS add each.
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
                                                             int shift, int* __restrict__ counts)
 {
     __shared__ int h[kRadix];
     const int t = threadIdx.x;
-    const unsigned long long below = lanes_below();
     h[t] = 0;
-    __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     uint32_t key[kSortRounds];
 #pragma unroll
@@ -112,13 +110,10 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __re
         const int64_t e = base + q * kBlock + t;
         key[q] = e < n ? keys[e] : 0u;
     }
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kSortRounds; ++q) {
-        const bool valid = base + q * kBlock + t < n;
-        const int d = (int)((key[q] >> shift) & (kRadix - 1));
-        const unsigned long long match = digit_peers(d, valid);
-        if (valid && (match & below) == 0) atomicAdd(&h[d], __popcll(match));
-    }
+    for (int q = 0; q < kSortRounds; ++q)
+        if (base + q * kBlock + t < n) atomicAdd(&h[(key[q] >> shift) & (kRadix - 1)], 1);
     __syncthreads();
     counts[(int64_t)blockIdx.x * kRadix + t] = h[t];
 }
@@ -126,26 +121,29 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __re
 // Output offsets of a pass: offset(tile, d) = (keys with a smaller digit) +
 // (keys with digit d in earlier tiles), in place over the tile-major table, in
 // three steps with one thread per digit (every access coalesced across digits):
-// per-group column sums over kScanTiles tiles, a walk down the groups, and the
-// scan inside each group.
+// per-group column sums over kScanTiles tiles; one walk down the groups (their
+// exclusive prefixes per digit) and the scan of the digit totals; the scan
+// inside each group.
 __global__ __launch_bounds__(kBlock) void offsets_sum_kernel(const int* __restrict__ counts, int ntiles,
                                                              int* __restrict__ part)
 {
     const int t0 = blockIdx.x * kScanTiles;
     const int t1 = min(t0 + kScanTiles, ntiles);
     int s = 0;
+#pragma unroll 16
     for (int tile = t0; tile < t1; ++tile) s += counts[(int64_t)tile * kRadix + threadIdx.x];
     part[(int64_t)blockIdx.x * kRadix + threadIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void offsets_groups_kernel(int* __restrict__ part, int ngroups)
+__global__ __launch_bounds__(kBlock) void offsets_groups_kernel(int* __restrict__ part, int ngroups,
+                                                                int* __restrict__ dbase)
 {
     static_assert(kRadix == kBlock, "one digit per thread");
     __shared__ int wsum[kBlock / 64];
     const int d = threadIdx.x;
     const int lane = d & 63;
     int run = 0;
-#pragma unroll 8
+#pragma unroll 16
     for (int g = 0; g < ngroups; ++g) {
         const int v = part[(int64_t)g * kRadix + d];
         part[(int64_t)g * kRadix + d] = run;
@@ -161,16 +159,17 @@ __global__ __launch_bounds__(kBlock) void offsets_groups_kernel(int* __restrict_
     __syncthreads();
     int base = incl - run;
     for (int w = 0; w < (d >> 6); ++w) base += wsum[w];
-#pragma unroll 8
-    for (int g = 0; g < ngroups; ++g) part[(int64_t)g * kRadix + d] += base;
+    dbase[d] = base;
 }
 
 __global__ __launch_bounds__(kBlock) void offsets_tiles_kernel(int* __restrict__ counts, int ntiles,
-                                                               const int* __restrict__ part)
+                                                               const int* __restrict__ part,
+                                                               const int* __restrict__ dbase)
 {
     const int t0 = blockIdx.x * kScanTiles;
     const int t1 = min(t0 + kScanTiles, ntiles);
-    int run = part[(int64_t)blockIdx.x * kRadix + threadIdx.x];
+    int run = part[(int64_t)blockIdx.x * kRadix + threadIdx.x] + dbase[threadIdx.x];
+#pragma unroll 16
     for (int tile = t0; tile < t1; ++tile) {
         const int64_t i = (int64_t)tile * kRadix + threadIdx.x;
         const int v = counts[i];
@@ -384,9 +383,9 @@ Error pass_offsets(int* counts, int ntiles, int* part, hipStream_t s)
     const int ngroups = (int)cdiv(ntiles, kScanTiles);
     offsets_sum_kernel<<<ngroups, kBlock, 0, s>>>(counts, ntiles, part);
     CPAPR_LAUNCHED();
-    offsets_groups_kernel<<<1, kBlock, 0, s>>>(part, ngroups);
+    offsets_groups_kernel<<<1, kBlock, 0, s>>>(part, ngroups, part + (int64_t)ngroups * kRadix);
     CPAPR_LAUNCHED();
-    offsets_tiles_kernel<<<ngroups, kBlock, 0, s>>>(counts, ntiles, part);
+    offsets_tiles_kernel<<<ngroups, kBlock, 0, s>>>(counts, ntiles, part, part + (int64_t)ngroups * kRadix);
     CPAPR_LAUNCHED();
     return {CPAPR_OK, ""};
 }
@@ -401,7 +400,7 @@ int64_t sort_scratch_bytes(int64_t nnz, int N)
     b += align256((size_t)nnz * 4 * record_words(N));       // nonzero records
     b += 4 * align256((size_t)nnz * 4);                     // keys/payload ping-pong
     b += align256((size_t)ncounts * 4);                     // histogram table
-    b += align256((size_t)cdiv(ntiles, kScanTiles) * kRadix * 4);  // offsets scan: group sums
+    b += align256((size_t)(cdiv(ntiles, kScanTiles) + 1) * kRadix * 4);  // offsets scan: group sums, digit bases
     b += 256;                                                // flags / counters
     b += align256(kSegPartials * 8);                         // segment-count partials
     return (int64_t)b;
@@ -426,7 +425,7 @@ Error build_sorted(cpapr_plan* P, const cpapr_coo* X, char* scratch, hipStream_t
     int32_t* pa = (int32_t*)take((size_t)nnz * 4);
     int32_t* pb = (int32_t*)take((size_t)nnz * 4);
     int* counts = (int*)take((size_t)ncounts * 4);
-    int* part = (int*)take((size_t)cdiv(ntiles, kScanTiles) * kRadix * 4);
+    int* part = (int*)take((size_t)(cdiv(ntiles, kScanTiles) + 1) * kRadix * 4);
     int* flags = (int*)take(256);
     unsigned long long* segc = (unsigned long long*)(flags + 8);
     unsigned long long* segpart = (unsigned long long*)take(kSegPartials * 8);

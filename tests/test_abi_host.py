@@ -181,6 +181,16 @@ def test_calls_reject_null_plan(lib):
     assert lib.cpapr_modes_advance(1, None, i1, i1, i1, one, one, one, None, None) == -1
 
 
+def test_prof_rejects_bad_arguments(lib):
+    """Kernel-timing switches: capacity outside [1, 2^20] and a sampling
+    stride below 1 are refused before any event is made."""
+    assert lib.cpapr_prof_enable(0) == -1
+    assert lib.cpapr_prof_enable_sampled(0, 1) == -1
+    assert lib.cpapr_prof_enable_sampled(16, 0) == -1
+    assert lib.cpapr_prof_enable_sampled(16, -3) == -1
+    assert lib.cpapr_prof_disable() == 0
+
+
 def test_phi_coo_workspace_size(lib):
     """Transient Phi's workspace: one mode's sorted copy plus its sort's
     scratch; grows with nnz; rejects a bad mode or rank (host checks only)."""

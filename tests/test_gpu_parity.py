@@ -246,6 +246,26 @@ def test_phi_deterministic_repeat():
     P.close()
 
 
+def test_prof_sampled_records_every_kth_launch():
+    """Kernel timing sampled every 3rd Phi launch: of 10 launches alternating
+    modes 0 and 1, launches 0, 3, 6 and 9 are recorded, with their modes and
+    positive durations."""
+    X, M, _ = synth.config_small()
+    P = cpapr.Plan.from_tensor(X, M.rank)
+    A = [dev(a) for a in M.factors]
+    Bs = [dev(M.factors[n] * M.lam) for n in range(2)]
+    cpapr.cpapr_prof_enable_sampled(16, 3)
+    try:
+        for i in range(10):
+            P.phi(i % 2, Bs[i % 2], A)
+        recs = cpapr.cpapr_prof_read(16)
+    finally:
+        cpapr.cpapr_prof_disable()
+    assert [m for m, _ in recs] == [0, 1, 0, 1]
+    assert all(ms > 0 for _, ms in recs)
+    P.close()
+
+
 def test_deterministic_mode_repeats_bit_for_bit():
     """Deterministic plans: Phi, MTTKRP, a solve and PQNR row solves repeat bit
     for bit, and still match the oracle; heavy Zipf rows span many tiles."""
