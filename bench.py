@@ -9,8 +9,8 @@ HBM before timing.
 
 value = Phi nonzero visits per second over the whole step (Phi evaluations
         the solve actually computed x nnz / step time).
-roofline: the Phi kernel, timed by HIP events on its own stream inside the
-        timed steps, against HBM peak. achieved = the compulsory traffic
+roofline: the Phi kernel, timed by HIP events on its own stream around every
+        7th Phi launch of the timed steps, against HBM peak. achieved = the compulsory traffic
         M_min of one launch / its average duration, M_min per mode n being
         nnz (4(N-1) + 8) (the other modes' coordinates and the value; i_n
         follows from the segment table) + S_n (2 R 8 + 8) (per nonempty row
@@ -28,7 +28,9 @@ serving: a short Poisson trace of solve requests through the continuous-
 
 Other workloads: --workload zipf4 (4-way, 100M nonzeros, R = 32, solve to KKT
 1e-4), batch (512 tensors, batched graph replays), serve (a Poisson stream of
-solve requests); --precision mixed; --method pqnr | pdnr.
+solve requests), mttkrp (MTTKRP of every mode on the same engine, the kernel of
+CP-ALS), plan (plan creation and the in-row orders), tune (the launch-policy
+model against a search); --precision mixed; --method pqnr | pdnr.
 
 Prints one JSON line. Only one GPU is supported.
 """
@@ -182,10 +184,11 @@ def host_cpu():
     return {"cpu_model": model, "nproc": os.cpu_count(), "cores_allowed": len(allowed)}, allowed
 
 
-def cpu_baseline(X, M, modes=None, max_nnz=None, runs=5):
-    """The FP64 oracle's Phi on the host: one thread pinned to one core, median
-    of `runs` runs, each Phi over `modes` modes of the first max_nnz nonzeros
-    (nonzeros are drawn independently, so a prefix is a fair sample)."""
+def cpu_baseline(X, M, modes=None, max_nnz=None, runs=5, kind="phi"):
+    """The FP64 oracle's Phi (or MTTKRP, kind="mttkrp") on the host: one thread
+    pinned to one core, median of `runs` runs, each over `modes` modes of the
+    first max_nnz nonzeros (nonzeros are drawn independently, so a prefix is a
+    fair sample)."""
     import numpy as np
 
     import oracle
@@ -203,14 +206,18 @@ def cpu_baseline(X, M, modes=None, max_nnz=None, runs=5):
         for _ in range(runs):
             t0 = time.perf_counter()
             for n in range(modes):
-                oracle.phi(X, n, Bs[n], M.factors)
+                if kind == "mttkrp":
+                    oracle.mttkrp(X, n, M.factors)
+                else:
+                    oracle.phi(X, n, Bs[n], M.factors)
             times.append(time.perf_counter() - t0)
     finally:
         os.sched_setaffinity(0, set(allowed))
     med = float(np.median(times))
     return dict({"value": modes * X.nnz / med, "unit": "nonzeros/s", "cores": 1, "kind": "oracle",
                  "pinned_core": core, "runs": runs, "run_s": times,
-                 "sample": f"FP64 oracle Phi(n) over {modes} mode(s) of the first {X.nnz} nonzeros of the same "
+                 "sample": f"FP64 oracle {'MTTKRP' if kind == 'mttkrp' else 'Phi(n)'} over {modes} mode(s) of the "
+                           f"first {X.nnz} nonzeros of the same "
                            f"tensor per run, single thread pinned to one core, median of {runs} runs "
                            f"({sum(times):.1f} s in all)"}, **info)
 
@@ -550,6 +557,105 @@ def tune_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def mttkrp_min_bytes(N, R, nnz, dims, segs, mode):
+    """Compulsory HBM bytes of one MTTKRP launch for `mode` (Eqs. 10-12): per
+    nonzero the other modes' coordinates and the value, 4(N-1) + 8 bytes; per
+    nonempty row of this mode the output row written and an 8-byte segment
+    entry; every row of the other factors once (FP64). Phi's M_min without the
+    B row reads."""
+    fac = sum(dims[m] for m in range(N) if m != mode) * R * 8
+    return nnz * (4 * (N - 1) + 8) + segs[mode] * (R * 8 + 8) + fac
+
+
+def mttkrp_workload(args):
+    """MTTKRP, the kernel of CP-ALS (Eqs. 10-12: M(n) = X_(n) times the
+    Khatri-Rao product of the other factors), on the same plan and tile code
+    as Phi: one step = one MTTKRP per mode of the zipf3 (or, with --tensor
+    zipf4, the zipf4) tensor, FP64, with the plan built beforehand (an ALS
+    solver builds it once and calls MTTKRP every sweep)."""
+    import math
+
+    import torch
+
+    from paper_2307_03276_amd import cpapr, synth
+
+    if args.tensor == "zipf4":
+        X, M, _ = synth.config_zipf4()
+        wl_name = "mttkrp-zipf4-100M-R32"
+        wl_desc = ("mttkrp 4-way 1000000x200000x10000x500, 100M nnz (Zipf(1.2) modes 1-2, uniform 3-4), R=32, "
+                   "one MTTKRP per mode per step, plan prebuilt")
+    else:
+        X, M, _ = synth.config_zipf3(nnz=args.nnz)
+        wl_name = "mttkrp-zipf3-20M-R16"
+        wl_desc = ("mttkrp 3-way 200000x150000x20000, 20M Zipf(1.1) nnz, R=16, one MTTKRP per mode per step, "
+                   "plan prebuilt")
+    N, R = X.nmodes, M.rank
+    dev = torch.device("cuda")
+    progress(f"{wl_name}: building the plan")
+    P = cpapr.Plan.from_tensor(X, R)
+    A = [torch.from_numpy(a).to(dev) for a in M.factors]
+    outs = [torch.empty((X.dims[n], R), dtype=torch.float64, device=dev) for n in range(N)]
+    segs = [P.segments(n) for n in range(N)]
+    if args.profile_phi:
+        progress("MTTKRP twice per mode, then a 1 GiB device copy")
+        for n in range(N):
+            for _ in range(2):
+                P.mttkrp(n, A, out=outs[n])
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        P.close()
+        print("profile-mttkrp done", flush=True)
+        return
+
+    def step():
+        for n in range(N):
+            P.mttkrp(n, A, out=outs[n])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # every `every`-th launch bracketed by events; every is coprime to N so
+    # that all modes are sampled
+    every = next(k for k in range(2, 10) if math.gcd(k, N) == 1)
+    cap = N * args.steps // every + 16
+    cpapr.cpapr_prof_enable_sampled(cap, every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    recs = cpapr.cpapr_prof_read(cap)
+    cpapr.cpapr_prof_disable()
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    value = N * X.nnz / (ms_per_step / 1000.0)
+    tot_bytes = sum(mttkrp_min_bytes(N, R, X.nnz, list(X.dims), segs, m) for m, _ in recs)
+    tot_ms = sum(ms for _, ms in recs)
+    avg_ms = tot_ms / max(1, len(recs))
+    achieved = tot_bytes / (tot_ms / 1000.0) / 1e9
+    per_mode_ms = [sum(ms for m, ms in recs if m == n) / max(1, sum(1 for m, _ in recs if m == n)) for n in range(N)]
+    traffic_bytes = measured_traffic(wl_name, "fp64")
+    traffic = None if traffic_bytes is None else traffic_bytes / (avg_ms / 1000.0) / 1e9
+    out = {"metric": "MTTKRP nonzeros/s", "value": value, "unit": "nonzeros/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": wl_desc, "nnz": X.nnz, "rank": R},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+           "mttkrp_kernel": {"kernel": "phi_seg_kernel (MTTKRP)", "launches": len(recs), "sampled_every": every,
+                             "avg_ms": avg_ms, "avg_ms_per_mode": per_mode_ms,
+                             "min_bytes_per_launch": tot_bytes / max(1, len(recs)),
+                             "measured_bytes_per_launch": traffic_bytes, "segments": segs}}
+    if not args.no_cpu_baseline:
+        progress("CPU baseline (the oracle's MTTKRP on the host)")
+        out["cpu_baseline"] = cpu_baseline(X, M, modes=1 if N > 3 else None,
+                                           max_nnz=10_000_000 if N > 3 else None, kind="mttkrp")
+    P.close()
+    print(json.dumps(out), flush=True)
+
+
 def plan_workload(args):
     """Plan creation against the in-row order it buys: for the zipf3 and zipf4
     tensors (FP64) and both sort orders, the plan's creation time (host clock
@@ -626,10 +732,13 @@ def main():
                     help="inner solver of the zipf3 / zipf4 jobs: MU (Algorithm 1), PQNR or PDNR row solves")
     ap.add_argument("--nnz", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["zipf3", "zipf4", "batch", "serve", "tune", "plan"], default="zipf3",
+    ap.add_argument("--workload", choices=["zipf3", "zipf4", "batch", "serve", "tune", "plan", "mttkrp"],
+                    default="zipf3",
                     help="zipf3: the 20M-nonzero 3-way CP-APR MU job (default); zipf4: the 100M-nonzero 4-way "
                          "solve to KKT 1e-4; batch: 512 uneven tensors; serve: a Poisson stream of solve requests; "
-                         "tune: the launch-policy model against a search; plan: plan creation and the in-row orders")
+                         "tune: the launch-policy model against a search; plan: plan creation and the in-row orders; "
+                         "mttkrp: MTTKRP per mode on the zipf3 (or --tensor zipf4) tensor")
+    ap.add_argument("--tensor", choices=["zipf3", "zipf4"], default="zipf3", help="tensor of --workload mttkrp")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-count", type=int, default=60)
     ap.add_argument("--round-cap", type=float, default=32e6,
@@ -642,16 +751,20 @@ def main():
                     help="store bytes past L2 per Phi launch from two rocprofv3 counter runs of --profile-phi "
                          "(FETCH_SIZE, WRITE_SIZE) for --workload / --precision, then exit")
     ap.add_argument("--profile-phi", action="store_true",
-                    help="counter-collection driver: two Phi launches per mode on the benchmark tensor, "
-                         "then a 1 GiB device copy that calibrates the byte counters; prints no JSON")
+                    help="counter-collection driver: two Phi launches per mode on the benchmark tensor (MTTKRP "
+                         "launches with --workload mttkrp), then a 1 GiB device copy that calibrates the byte "
+                         "counters; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     if args.record_traffic:
-        wl = {"zipf3": "zipf3-20M-R16", "zipf4": "zipf4-100M-R32"}.get(args.workload)
+        names = {"zipf3": "zipf3-20M-R16", "zipf4": "zipf4-100M-R32"}
+        wl = names.get(args.workload)
+        if args.workload == "mttkrp":
+            wl = "mttkrp-" + names[args.tensor]
         if wl is None:
-            raise SystemExit("--record-traffic takes --workload zipf3 or zipf4")
+            raise SystemExit("--record-traffic takes --workload zipf3, zipf4 or mttkrp")
         record_traffic(args.record_traffic[0], args.record_traffic[1], wl, args.precision)
         return
 
@@ -674,6 +787,9 @@ def main():
         return
     if args.workload == "plan":
         plan_workload(args)
+        return
+    if args.workload == "mttkrp":
+        mttkrp_workload(args)
         return
     if args.workload == "serve":
         if args.precision == "fp64" and "--precision" not in sys.argv:

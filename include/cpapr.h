@@ -436,8 +436,9 @@ int cpapr_modes_advance(int32_t count, cpapr_plan* const* plans, const int32_t* 
  * (host array of N device pointers). No-op in FP64. Stream-ordered. */
 int cpapr_plan_sync_f32(cpapr_plan* plan, const double* const* A, void* stream);
 
-/* Kernel timing for measurement: while enabled, every Phi kernel launch is
- * bracketed by HIP events on its stream (up to `capacity` launches).
+/* Kernel timing for measurement: while enabled, every Phi, MTTKRP and PDNR
+ * Hessian-pass kernel launch is bracketed by HIP events on its stream (up to
+ * `capacity` launches).
  * cpapr_prof_enable_sampled brackets only every `every`-th launch after the
  * call (the 1st, the every+1-th, ...): each event pair holds the stream for a
  * few microseconds on either side of its kernel, so sampling keeps the timed

@@ -1396,7 +1396,9 @@ Error launch_mttkrp(const cpapr_plan* P, int mode, const double* const* A, doubl
     if (e.code) return e;
     e = attach_det(P, a);
     if (e.code) return e;
+    prof_begin(mode, s);
     e = dispatch_seg<false, kMttkrp>(G, RPL, a, s);
+    prof_end(s);
     if (e.code) return e;
     return launch_det_fixup(P, mode, a, M, nullptr, s);
 }

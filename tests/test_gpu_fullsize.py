@@ -53,6 +53,39 @@ def test_phi_fullsize_sampled_rows_and_mass(big, precision, tol):
     P.close()
 
 
+def _mttkrp_rows(X, n, rows, factors):
+    """The oracle's MTTKRP rows `rows` of mode n, from the nonzeros in them."""
+    sel = np.isin(X.idx[n], rows)
+    Xs = synth.SparseTensor(X.dims, np.ascontiguousarray(X.idx[:, sel]), X.vals[sel].copy())
+    return oracle.mttkrp(Xs, n, factors)[rows]
+
+
+def test_mttkrp_fullsize_sampled_rows_and_weighted_sum(big):
+    """MTTKRP (Eqs. 10-12) at full size in the launch shape the benchmark
+    times: sampled rows against the oracle, empty rows exactly zero, and every
+    row at once through sum_ir M[i,r] A(n)[i,r] lambda_r = sum_k x_k m_k, the
+    model's value summed over the nonzeros weighted by x (computed here from
+    the definition, in chunks)."""
+    X, M, _ = big
+    P = cpapr.Plan.from_tensor(X, M.rank)
+    A = [dev(a) for a in M.factors]
+    rng = np.random.default_rng(3)
+    xm = 0.0
+    for c in range(0, X.nnz, 1 << 21):
+        m = np.broadcast_to(M.lam, (min(1 << 21, X.nnz - c), M.rank)).copy()
+        for q in range(3):
+            m *= M.factors[q][X.idx[q, c:c + (1 << 21)]]
+        xm += float(X.vals[c:c + (1 << 21)] @ m.sum(axis=1))
+    for n in range(3):
+        got = host(P.mttkrp(n, A))
+        rows, counts = _sample_rows(X, n, rng)
+        assert_parity(got[rows], _mttkrp_rows(X, n, rows, M.factors), 1e-12, f"MTTKRP mode {n} sampled rows")
+        assert np.all(got[counts == 0] == 0)
+        ws = float(np.sum(got * (M.factors[n] * M.lam)))
+        assert abs(ws - xm) <= 1e-12 * xm, f"mode {n}: weighted sum {ws} vs {xm}"
+    P.close()
+
+
 def test_mu_inner_fullsize_sampled_rows(big):
     X, M, sched = big
     P = cpapr.Plan.from_tensor(X, M.rank, lmax=sched["lmax"], tol=0.0)

@@ -57,6 +57,28 @@ def test_phi_4way_fullsize_sampled_rows_and_mass(big4, precision, tol):
     P.close()
 
 
+def test_mttkrp_4way_fullsize_sampled_rows(big4):
+    """MTTKRP at the 100M-nonzero size in the benchmarked launch shape:
+    sampled rows (one heavy row and random ones) against the oracle, which
+    computes them from those rows' nonzeros; empty rows exactly zero."""
+    X, M, _ = big4
+    P = cpapr.Plan.from_tensor(X, M.rank)
+    A = [dev(a) for a in M.factors]
+    rng = np.random.default_rng(4)
+    for n in range(4):
+        got = host(P.mttkrp(n, A))
+        counts = np.bincount(X.idx[n], minlength=X.dims[n])
+        nonempty = np.flatnonzero(counts)
+        rows = np.unique(np.concatenate([[np.argmax(counts)],
+                                         rng.choice(nonempty, size=min(12, nonempty.size), replace=False)]))
+        sel = np.isin(X.idx[n], rows)
+        Xs = synth.SparseTensor(X.dims, np.ascontiguousarray(X.idx[:, sel]), X.vals[sel].copy())
+        ref = oracle.mttkrp(Xs, n, M.factors)[rows]
+        assert_parity(got[rows], ref, 1e-12, f"MTTKRP mode {n} sampled rows")
+        assert np.all(got[counts == 0] == 0)
+    P.close()
+
+
 def test_mu_inner_4way_fullsize_sampled_rows(big4):
     X, M, sched = big4
     P = cpapr.Plan.from_tensor(X, M.rank, lmax=sched["lmax"], tol=0.0)
