@@ -379,7 +379,8 @@ def generate_requests(count, seed=0, workers=1):
     return reqs, time.perf_counter() - t0
 
 
-def run_serving(count, warmup, prec, fp64_checks=2, seed=0, policy="srpt", round_cap=32e6, reqs=None):
+def run_serving(count, warmup, prec, fp64_checks=2, seed=0, policy="srpt", round_cap=32e6, round_cap_min=4e6,
+                reqs=None):
     """Poisson arrivals at 200 requests/s of CP-APR MU solves (3- or 4-way, dims
     U[1e3, 1e5], nnz LogUniform[1e4, 2e7], Zipf(1.1), R in {10, 16, 32}, KKT
     tolerance 1e-4, k_max 20), admitted by a 200 GB HBM budget; against the
@@ -411,7 +412,8 @@ def run_serving(count, warmup, prec, fp64_checks=2, seed=0, policy="srpt", round
     del done_all  # frees the results' device memory
     torch.cuda.synchronize()
     progress(f"serving: every request every round done ({summary_all.get('solves_per_s', 0):.1f} solves/s)")
-    srv = serve.Server(budget_bytes=200e9, max_slots=64, policy=policy, round_cap=round_cap, **kw)
+    srv = serve.Server(budget_bytes=200e9, max_slots=64, policy=policy, round_cap=round_cap,
+                       round_cap_min=round_cap_min, **kw)
     done = srv.run_trace(meas)
     summary = serve.latency_summary(done)
     serve.results_to_host(done)  # after the timed trace
@@ -464,7 +466,7 @@ def run_serving(count, warmup, prec, fp64_checks=2, seed=0, policy="srpt", round
         "requests": len(meas), "warmup_requests": len(warm), "total_nnz": int(nnz.sum()),
         "mean_nnz": float(nnz.mean()), "arrival_span_s": span,
         "offered_req_per_s": (len(meas) - 1) / span if span > 0 else None,
-        "served": dict(summary, policy=policy, round_cap_nnz=round_cap, peak_active=srv.peak_active,
+        "served": dict(summary, policy=policy, round_cap_nnz=[round_cap_min, round_cap], peak_active=srv.peak_active,
                        peak_hbm_bytes=srv.peak_used, ticks=srv.ticks,
                        host_phase_s={k: round(v, 4) for k, v in srv.phase_s.items()},
                        converged=int(sum(1 for r in done if r.stats.get("converged"))),
@@ -486,7 +488,8 @@ def serve_workload(args, reqs=None):
     from paper_2307_03276_amd import cpapr
 
     prec = cpapr.CPAPR_MIXED if args.precision == "mixed" else cpapr.CPAPR_FP64
-    res = run_serving(args.serve_count, args.serve_warmup, prec, round_cap=args.round_cap, reqs=reqs)
+    res = run_serving(args.serve_count, args.serve_warmup, prec, round_cap=args.round_cap,
+                      round_cap_min=args.round_cap_min, reqs=reqs)
     out = {
         "metric": "served solves/s",
         "value": res["served"]["solves_per_s"],
@@ -742,7 +745,9 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-count", type=int, default=60)
     ap.add_argument("--round-cap", type=float, default=32e6,
-                    help="serving: nonzeros per round of the shortest-remaining-work policy")
+                    help="serving: most nonzeros per round of the shortest-remaining-work policy")
+    ap.add_argument("--round-cap-min", type=float, default=4e6,
+                    help="serving: the round cap's floor (the cap is an eighth of the pending nonzeros, clamped)")
     ap.add_argument("--serve-warmup", type=int, default=6)
     ap.add_argument("--no-serve", action="store_true", help="skip the short served trace of the default run")
     ap.add_argument("--short-serve-count", type=int, default=16)

@@ -166,6 +166,20 @@ __device__ __forceinline__ double nonzero_scale(const double (&b)[RPL], const do
     }
 }
 
+// The nonzero stream (records or coordinate / value arrays) is read once per
+// launch: non-temporal loads keep it from displacing reused factor rows in L2.
+template <typename T>
+__device__ __forceinline__ T stream_load(const T* p)
+{
+    return __builtin_nontemporal_load(p);
+}
+__device__ __forceinline__ int4 stream_load(const int4* p)
+{
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const v4i v = __builtin_nontemporal_load((const v4i*)p);
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+
 // Staged nonzero: its row, the other modes' coordinates and its value. A lane
 // group loads G consecutive nonzeros cooperatively (coalesced) into its slice
 // of LDS and then reads them back one at a time as broadcasts.
@@ -383,16 +397,16 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
             const int64_t p = base + k * G + lane;
             if (p < p1) {
                 if (packed) {
-                    const int4 q = a.pk[p];
+                    const int4 q = stream_load(a.pk + p);
                     pre[k].row = q.x;
                     pre[k].c[0] = (uint32_t)q.y;
                     if constexpr (NM1 == 2) pre[k].c[NM1 - 1] = (uint32_t)q.z;
                     pre[k].x = (double)__int_as_float(q.w);
                 } else {
-                    pre[k].row = a.rows[p];
+                    pre[k].row = stream_load(a.rows + p);
 #pragma unroll
-                    for (int m = 0; m < NM1; ++m) pre[k].c[m] = a.cofs[(int64_t)m * nnz + p];
-                    pre[k].x = a.vals[p];
+                    for (int m = 0; m < NM1; ++m) pre[k].c[m] = stream_load(a.cofs + (int64_t)m * nnz + p);
+                    pre[k].x = stream_load(a.vals + p);
                 }
                 // line-search pass: a row not in a line search is staged as ~row
                 // (negative), so the skip costs no load in the gather loop

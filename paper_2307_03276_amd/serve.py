@@ -18,8 +18,13 @@ budget and queued requests are admitted.
 Round policy: "all" admits first come, first served, whatever fits, and runs
 every active request in every round. "srpt" (shortest remaining work first)
 ranks the active and the queued requests together by remaining work (nonzeros
-x mode rounds left) and runs the shortest until the round holds `round_cap`
-nonzeros (at least one request); queued requests are admitted (uploaded and
+x mode rounds left) and runs the shortest until the round holds its cap of
+nonzeros (at least one request). The cap follows the load: an eighth of the
+nonzeros of all active and queued requests, clamped to [round_cap_min,
+round_cap]. Under a light load small rounds let short requests finish without
+sharing rounds with long ones; under a deep queue large rounds spread each
+round's fixed costs (launches, the status read-back, the host's bookkeeping)
+over more work. Queued requests are admitted (uploaded and
 sorted) only when the ranking puts them in a round, and active ones outside it
 are held (their slots do no work and their state stays as it is). Short
 requests then finish without waiting for the long ones, or for the uploads of
@@ -173,7 +178,8 @@ class Server:
     def __init__(self, budget_bytes: float = 200e9, max_slots: int = 64, max_tiles: int = 1 << 22,
                  kmax: int = 20, lmax: int = 10, tol: float = 1e-4, eps: float = 1e-10,
                  precision: int = cpapr.CPAPR_MIXED, use_graph: bool = True, stream=None,
-                 compute_loglik: bool = True, executor=None, policy: str = "all", round_cap: float = 32e6):
+                 compute_loglik: bool = True, executor=None, policy: str = "all", round_cap: float = 32e6,
+                 round_cap_min: float = 4e6):
         self.budget = float(budget_bytes)
         self.used = 0.0
         self.max_slots = max_slots
@@ -194,6 +200,7 @@ class Server:
             raise ValueError("policy must be 'all' or 'srpt'")
         self.policy = policy
         self.round_cap = float(round_cap)
+        self.round_cap_min = min(float(round_cap_min), self.round_cap)
         self._held = None  # hold flags last sent to the executor
         # host seconds per phase of tick(): admission (upload + plan build),
         # batch commit, hold flags, the round (device time + status read-back),
@@ -353,17 +360,24 @@ class Server:
 
     def _ranked_round(self, with_queue: bool) -> list:
         """Shortest remaining work first: the active (and, with_queue, queued)
-        requests of the next round, until it holds round_cap nonzeros."""
+        requests of the next round, until it holds the round's cap of nonzeros."""
         items = list(self.active) + (list(self.queue) if with_queue else [])
         nnz = lambda q: float(q.X.nnz if isinstance(q, Request) else q.req.X.nnz)  # noqa: E731
         rid = lambda q: q.id if isinstance(q, Request) else q.req.id  # noqa: E731
+        cap = self.cap()
         out, work = [], 0.0
         for q in sorted(items, key=lambda q: (self._remaining(q), rid(q))):
-            if out and work + nnz(q) > self.round_cap:
+            if out and work + nnz(q) > cap:
                 break
             out.append(q)
             work += nnz(q)
         return out
+
+    def cap(self) -> float:
+        """Nonzeros a shortest-first round may hold: an eighth of the active and
+        queued requests' nonzeros, within [round_cap_min, round_cap]."""
+        pending = sum(float(a.req.X.nnz) for a in self.active) + sum(float(r.X.nnz) for r in self.queue)
+        return min(self.round_cap, max(self.round_cap_min, pending / 8.0))
 
     def _select(self) -> set:
         """The active requests that run this round."""

@@ -174,3 +174,33 @@ def test_policy_all_runs_everyone():
     srv = serve.Server(budget_bytes=10, max_slots=3, kmax=2, lmax=2, tol=1e-4, executor=ex)
     srv.run_trace(_reqs(3, nmodes=2))
     assert all(r == [0, 1, 2] for r in ex.rounds)
+
+
+def test_srpt_round_cap_follows_the_pending_work():
+    """The shortest-first round cap is an eighth of the active and queued
+    requests' nonzeros, clamped to [round_cap_min, round_cap]; a floor above
+    the ceiling is lowered to it."""
+    ex = MockExecutor({}, {}, 3)
+    srv = serve.Server(budget_bytes=1e12, max_slots=4, kmax=2, lmax=2, tol=1e-4, executor=ex, policy="srpt",
+                       round_cap=800, round_cap_min=100)
+    assert srv.cap() == 100  # nothing pending: the floor
+    for r in _reqs(3, nnz=[400, 2000, 3000]):
+        srv.submit(r)
+    assert srv.cap() == 675  # 5400 / 8
+    srv.submit(_reqs(1, nnz=[8000])[0])
+    assert srv.cap() == 800  # 13400 / 8 above the ceiling
+    assert serve.Server(executor=ex, policy="srpt", round_cap=60).cap() == 60
+
+
+def test_srpt_small_rounds_under_a_light_load():
+    """Under a light load the cap stays near its floor (an eighth of 980
+    pending nonzeros here, far below the ceiling), so the short requests run
+    together and never share a round with the long one."""
+    nnz = {0: 50, 1: 10, 2: 900, 3: 20}
+    ex = MockExecutor({i: 1 for i in nnz}, {i: None for i in nnz}, 3)
+    srv = serve.Server(budget_bytes=10, max_slots=4, kmax=2, lmax=2, tol=1e-4, executor=ex, policy="srpt",
+                       round_cap=2000, round_cap_min=100)
+    done = srv.run_trace(_reqs(4, nnz=[nnz[i] for i in range(4)]))
+    assert [r.id for r in done] == [1, 3, 0, 2]
+    assert all(2 not in ran or len(ran) == 1 for ran in ex.rounds)
+    assert ex.rounds[0] == [0, 1, 3]  # 10 + 20 + 50 <= 980 / 8 < 10 + 20 + 50 + 900
