@@ -167,7 +167,8 @@ __device__ __forceinline__ double nonzero_scale(const double (&b)[RPL], const do
 }
 
 // The nonzero stream (records or coordinate / value arrays) is read once per
-// launch: non-temporal loads keep it from displacing reused factor rows in L2.
+// launch: non-temporal loads keep it from displacing reused factor rows in L2
+// (used where one load instruction reads whole or half cache lines).
 template <typename T>
 __device__ __forceinline__ T stream_load(const T* p)
 {
@@ -403,10 +404,21 @@ __device__ __forceinline__ void phi_tile(const PhiArgs& a, int64_t tile, TileSha
                     if constexpr (NM1 == 2) pre[k].c[NM1 - 1] = (uint32_t)q.z;
                     pre[k].x = (double)__int_as_float(q.w);
                 } else {
-                    pre[k].row = stream_load(a.rows + p);
+                    // non-temporal only where a group's load covers at least half a
+                    // 128-byte line of each array: 8 lanes read a quarter line of the
+                    // 4-byte arrays and come back to it three times, re-fetching it
+                    // once it has been let go (measured 13 % slower)
+                    if constexpr (G >= 16) {
+                        pre[k].row = stream_load(a.rows + p);
 #pragma unroll
-                    for (int m = 0; m < NM1; ++m) pre[k].c[m] = stream_load(a.cofs + (int64_t)m * nnz + p);
-                    pre[k].x = stream_load(a.vals + p);
+                        for (int m = 0; m < NM1; ++m) pre[k].c[m] = stream_load(a.cofs + (int64_t)m * nnz + p);
+                        pre[k].x = stream_load(a.vals + p);
+                    } else {
+                        pre[k].row = a.rows[p];
+#pragma unroll
+                        for (int m = 0; m < NM1; ++m) pre[k].c[m] = a.cofs[(int64_t)m * nnz + p];
+                        pre[k].x = a.vals[p];
+                    }
                 }
                 // line-search pass: a row not in a line search is staged as ~row
                 // (negative), so the skip costs no load in the gather loop
